@@ -1,0 +1,46 @@
+/*
+ * pff_mesh.h - host-only inspection of the mesh the library builds (no GPU
+ * needed). Same geometry rules as pff_create (pff.h): quadtree of
+ * (-10,10)^2 with band refinement and 2:1 face balancing (Kolditz & Wick,
+ * Sec. 4, Table 1), Q_p nodes on an integer lattice, hanging-node constraints
+ * and the local-smoothing level hierarchy of Sec. 3.2.
+ *
+ * All pointers are HOST pointers owned by the caller; sizes come from
+ * pff_mesh_sizes. Return 0 on success, PFF_E_ARG / PFF_E_MESH otherwise.
+ */
+#ifndef PFF_MESH_H_
+#define PFF_MESH_H_
+
+#include "pff.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pff_mesh pff_mesh;
+
+/* Build the mesh on the host. */
+int pff_mesh_build(const pff_mesh_spec* spec, pff_mesh** out);
+int pff_mesh_free(pff_mesh* m);
+/* n_nodes: leaf nodes; n_levels; level_nodes (n_levels entries, nullable);
+ * M: lattice units across the domain (x = -10 + 20 X / M). */
+int pff_mesh_sizes(const pff_mesh* m, int64_t* n_nodes, int32_t* n_levels, int64_t* level_nodes, int64_t* M);
+/* xy: 2 n int32 (all X, then all Y) of the leaf (level = -1) or a level. */
+int pff_mesh_coords(const pff_mesh* m, int32_t level, int32_t* xy);
+/* flags: n bytes, bits as in pff_node_flags (active bits are never set here). */
+int pff_mesh_flags(const pff_mesh* m, int32_t level, uint8_t* flags);
+/* Hanging constraints: *count entries; node (count), masters and weights
+ * (3 per entry, unused slots -1 / 0). Pass NULL arrays to query the count. */
+int pff_mesh_hanging(const pff_mesh* m, int64_t* count, int32_t* node, int32_t* masters, double* weights);
+/* Prolongation from level-1 to level (level >= 1) in CSR form over the level's
+ * nodes: ptr (n_level + 1), col and val (nnz). NULL arrays query nnz. */
+int pff_mesh_prolongation(const pff_mesh* m, int32_t level, int64_t* nnz, int64_t* ptr, int32_t* col, double* val);
+/* Leaf node at the position of every node of a level (n_level int32). */
+int pff_mesh_leaf_index(const pff_mesh* m, int32_t level, int32_t* idx);
+/* Tile statistics: tiles, cell records (own + halo), largest tile. */
+int pff_mesh_tile_stats(const pff_mesh* m, int32_t level, int64_t* n_tiles, int64_t* n_records, int64_t* max_cells);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFF_MESH_H_ */

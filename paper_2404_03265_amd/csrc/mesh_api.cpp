@@ -1,0 +1,119 @@
+// Host-only C ABI over the mesh builder (declared in pff_mesh.h).
+#include <cstring>
+
+#include "../../include/pff_mesh.h"
+#include "mesh.hpp"
+
+struct pff_mesh {
+  pff::Mesh m;
+};
+
+namespace {
+pff::MeshSpec to_spec(const pff_mesh_spec* s) {
+  pff::MeshSpec ms;
+  ms.n_base = s->n_base;
+  ms.n_local = s->n_local;
+  ms.degree = s->degree;
+  ms.coarse = s->coarse > 0 ? s->coarse : 16;
+  ms.band_x = s->band_x;
+  ms.band_y = s->band_y;
+  ms.tile_x = s->tile_x;
+  ms.tile_y = s->tile_y;
+  return ms;
+}
+bool bad_level(const pff_mesh* m, int32_t level) {
+  return !m || level < -1 || level >= int32_t(m->m.levels.size());
+}
+}  // namespace
+
+extern "C" {
+
+int pff_mesh_build(const pff_mesh_spec* spec, pff_mesh** out) {
+  if (!spec || !out) return PFF_E_ARG;
+  *out = nullptr;
+  pff_mesh* m = new pff_mesh();
+  try {
+    if (!m->m.build(to_spec(spec))) {
+      delete m;
+      return PFF_E_MESH;
+    }
+  } catch (...) {
+    delete m;
+    return PFF_E_MESH;
+  }
+  *out = m;
+  return PFF_OK;
+}
+
+int pff_mesh_free(pff_mesh* m) {
+  delete m;
+  return PFF_OK;
+}
+
+int pff_mesh_sizes(const pff_mesh* m, int64_t* n_nodes, int32_t* n_levels, int64_t* level_nodes, int64_t* M) {
+  if (!m) return PFF_E_ARG;
+  if (n_nodes) *n_nodes = m->m.n_nodes;
+  if (n_levels) *n_levels = int32_t(m->m.levels.size());
+  if (level_nodes)
+    for (size_t l = 0; l < m->m.levels.size(); ++l) level_nodes[l] = m->m.levels[l].n;
+  if (M) *M = m->m.M;
+  return PFF_OK;
+}
+
+int pff_mesh_coords(const pff_mesh* m, int32_t level, int32_t* xy) {
+  if (bad_level(m, level) || !xy) return PFF_E_ARG;
+  const auto& X = level < 0 ? m->m.NX : m->m.levels[level].NX;
+  const auto& Y = level < 0 ? m->m.NY : m->m.levels[level].NY;
+  std::memcpy(xy, X.data(), X.size() * sizeof(int32_t));
+  std::memcpy(xy + X.size(), Y.data(), Y.size() * sizeof(int32_t));
+  return PFF_OK;
+}
+
+int pff_mesh_flags(const pff_mesh* m, int32_t level, uint8_t* flags) {
+  if (bad_level(m, level) || !flags) return PFF_E_ARG;
+  const auto& F = level < 0 ? m->m.flags : m->m.levels[level].flags;
+  std::memcpy(flags, F.data(), F.size());
+  return PFF_OK;
+}
+
+int pff_mesh_hanging(const pff_mesh* m, int64_t* count, int32_t* node, int32_t* masters, double* weights) {
+  if (!m || !count) return PFF_E_ARG;
+  *count = int64_t(m->m.hanging.size());
+  for (size_t i = 0; i < m->m.hanging.size(); ++i) {
+    const pff::Hanging& h = m->m.hanging[i];
+    if (node) node[i] = h.node;
+    for (int k = 0; k < 3; ++k) {
+      if (masters) masters[3 * i + k] = h.master[k];
+      if (weights) weights[3 * i + k] = h.weight[k];
+    }
+  }
+  return PFF_OK;
+}
+
+int pff_mesh_prolongation(const pff_mesh* m, int32_t level, int64_t* nnz, int64_t* ptr, int32_t* col, double* val) {
+  if (!m || !nnz || level < 1 || level >= int32_t(m->m.levels.size())) return PFF_E_ARG;
+  const pff::Csr& P = m->m.levels[level].P;
+  *nnz = int64_t(P.col.size());
+  if (ptr) std::memcpy(ptr, P.ptr.data(), P.ptr.size() * sizeof(int64_t));
+  if (col) std::memcpy(col, P.col.data(), P.col.size() * sizeof(int32_t));
+  if (val) std::memcpy(val, P.val.data(), P.val.size() * sizeof(double));
+  return PFF_OK;
+}
+
+int pff_mesh_leaf_index(const pff_mesh* m, int32_t level, int32_t* idx) {
+  if (!m || !idx || level < 0 || level >= int32_t(m->m.levels.size())) return PFF_E_ARG;
+  const auto& L = m->m.levels[level].leaf_index;
+  std::memcpy(idx, L.data(), L.size() * sizeof(int32_t));
+  return PFF_OK;
+}
+
+int pff_mesh_tile_stats(const pff_mesh* m, int32_t level, int64_t* n_tiles, int64_t* n_records, int64_t* max_cells) {
+  if (bad_level(m, level)) return PFF_E_ARG;
+  const pff::TileSet& t = level < 0 ? m->m.tiles : m->m.levels[level].tiles;
+  if (n_tiles) *n_tiles = t.n_tiles;
+  if (n_records) *n_records = t.n_cell_records;
+  if (max_cells) *max_cells = t.max_cells;
+  return PFF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1102 @@
+// C ABI of the matrix-free phase-field solver library (declared in pff.h).
+// Host orchestration: device tables, state setup, operator launches, the
+// local-smoothing V-cycle, GMRES and the Newton / active set iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/pff.h"
+#include "mesh.hpp"
+#include "tile_kernel.hpp"
+#include "util_kernels.hpp"
+
+using namespace pff;
+
+namespace {
+
+#define HIPCHK(expr)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      throw std::runtime_error(std::string("HIP error ") + hipGetErrorString(e_) + " at " #expr); \
+    }                                                                           \
+  } while (0)
+
+struct DevTiles {
+  int32_t* info = nullptr;
+  int32_t* halo = nullptr;
+  uint16_t* loc = nullptr;
+  uint16_t* cinfo = nullptr;
+  int n_tiles = 0, max_local = 0, max_owned = 0, max_cells = 0;
+  int64_t n_rec = 0;
+};
+
+template <typename T>
+struct LevelWork {
+  bool ready = false;
+  T* state = nullptr;  // (u_x, u_y, phit): 3 n
+  T* d = nullptr;      // right-hand side / defect
+  T* x[2] = {nullptr, nullptr};
+  T* dir[2] = {nullptr, nullptr};
+  T* dinv = nullptr;
+  T* Pval = nullptr;   // prolongation weights in this precision
+  T* PTval = nullptr;
+};
+
+struct DevLevel {
+  int64_t n = 0;
+  DevTiles tiles;
+  uint8_t* flags = nullptr;
+  int32_t* leaf_index = nullptr;
+  int64_t* P_ptr = nullptr;
+  int32_t* P_col = nullptr;
+  int64_t* PT_ptr = nullptr;
+  int32_t* PT_col = nullptr;
+  LevelWork<double> w64;
+  LevelWork<float> w32;
+  double lam_max[2] = {1, 1}, lam_min[2] = {1, 1};
+};
+
+template <typename T>
+Basis<T> make_basis(int p) {
+  Basis<T> B{};
+  const int N = p + 1;
+  double g[3], w[3];
+  if (p == 1) {
+    const double s = 0.5 / std::sqrt(3.0);
+    g[0] = 0.5 - s; g[1] = 0.5 + s; w[0] = w[1] = 0.5;
+  } else {
+    const double s = 0.5 * std::sqrt(0.6);
+    g[0] = 0.5 - s; g[1] = 0.5; g[2] = 0.5 + s;
+    w[0] = w[2] = 5.0 / 18.0; w[1] = 8.0 / 18.0;
+  }
+  auto lag = [&](int k, double t) {
+    double v = 1.0;
+    for (int m = 0; m < N; ++m) if (m != k) v *= (t - double(m) / p) / (double(k - m) / p);
+    return v;
+  };
+  auto dlag = [&](int k, double t) {
+    double s = 0.0;
+    for (int r = 0; r < N; ++r) {
+      if (r == k) continue;
+      double v = 1.0 / (double(k - r) / p);
+      for (int m = 0; m < N; ++m) if (m != k && m != r) v *= (t - double(m) / p) / (double(k - m) / p);
+      s += v;
+    }
+    return s;
+  };
+  for (int q = 0; q < N; ++q) {
+    B.w[q] = T(w[q]);
+    for (int a = 0; a < N; ++a) {
+      B.v[q][a] = T(lag(a, g[q]));
+      B.d[q][a] = T(dlag(a, g[q]));
+    }
+  }
+  for (int sub = 0; sub < 2; ++sub)
+    for (int t = 0; t < N; ++t)
+      for (int k = 0; k < N; ++k) B.hang[sub][t][k] = T(lag(k, (sub + double(t) / p) / 2.0));
+  return B;
+}
+
+template <typename T>
+T* dalloc(int64_t count) {
+  if (count <= 0) count = 1;
+  void* p = nullptr;
+  if (hipMalloc(&p, size_t(count) * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+T* upload(const std::vector<T>& v) {
+  T* d = dalloc<T>(int64_t(v.size()));
+  if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+
+DevTiles upload_tiles(const TileSet& t) {
+  DevTiles d;
+  d.info = upload(t.tile_info);
+  d.halo = upload(t.halo);
+  d.loc = upload(t.cell_loc);
+  d.cinfo = upload(t.cell_info);
+  d.n_tiles = t.n_tiles;
+  d.max_local = t.max_local;
+  d.max_owned = t.max_owned;
+  d.max_cells = t.max_cells;
+  d.n_rec = t.n_cell_records;
+  return d;
+}
+
+inline int grid_for(int64_t n, int threads = 256) {
+  int64_t b = (n + threads - 1) / threads;
+  return int(std::max<int64_t>(1, std::min<int64_t>(b, 65536)));
+}
+
+}  // namespace
+
+struct pff_ctx {
+  Mesh mesh;
+  pff_params prm{};
+  int p = 1;
+  int64_t n = 0;
+  DevTiles tiles;
+  uint8_t* flags = nullptr;
+  Hanging* hang = nullptr;
+  int n_hang = 0;
+  std::vector<DevLevel> lv;
+  double* U = nullptr;
+  double* phio = nullptr;
+  double* phit = nullptr;
+  double* mass = nullptr;
+  double* wv[8] = {};
+  double* red_part = nullptr;
+  double* red_out = nullptr;
+  double* host_red = nullptr;   // pinned
+  double* V = nullptr;          // GMRES basis
+  int V_cap = 0;
+  bool has_state = false;
+  bool mg_ready = false;
+  bool eig_fixed = false;
+  std::string err;
+  hipStream_t s = nullptr;
+
+  Material mat() const {
+    Material m;
+    m.E = prm.E;
+    m.mu = prm.E / (2.0 * (1.0 + prm.nu));
+    m.lam = prm.E * prm.nu / ((1.0 + prm.nu) * (1.0 - 2.0 * prm.nu));
+    m.kappa = prm.kappa;
+    m.pressure = prm.pressure;
+    m.Gc = prm.Gc;
+    m.ell = prm.ell;
+    return m;
+  }
+
+  // ---------------------------------------------------------------- tiles --
+  template <typename T, int MODE, int EPI>
+  void launch_tile(const DevTiles& t, const uint8_t* fl, int64_t nn, TileArgs<T>& a) {
+    a.tile_info = t.info;
+    a.halo = t.halo;
+    a.cell_loc = t.loc;
+    a.cell_info = t.cinfo;
+    a.flags = fl;
+    a.n = nn;
+    a.max_local = t.max_local;
+    a.max_owned = t.max_owned;
+    for (int l = 0; l < 16; ++l) a.H[l] = T(l < int(mesh.level_H.size()) ? mesh.level_H[l] : 1.0);
+    a.B = make_basis<T>(p);
+    a.mat = mat();
+    using TR = ModeTraits<MODE>;
+    constexpr int NF = TR::n_src + TR::n_state;
+    const size_t lds = size_t((NF > 0 ? NF : 1) * t.max_local + 3 * t.max_owned) * sizeof(T);
+    int threads = ((std::min(t.max_cells, 256) + 63) / 64) * 64;
+    threads = std::max(64, threads);
+    if (p == 1)
+      hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI>), dim3(t.n_tiles), dim3(threads), lds, s, a);
+    else
+      hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI>), dim3(t.n_tiles), dim3(threads), lds, s, a);
+    HIPCHK(hipGetLastError());
+  }
+
+  template <int MODE>
+  void leaf_op(double* dst, const double* src, const double* const* st) {
+    TileArgs<double> a{};
+    a.src = src;
+    a.dst = dst;
+    for (int i = 0; i < 4; ++i) a.st[i] = st ? st[i] : nullptr;
+    launch_tile<double, MODE, EPI_PLAIN>(tiles, flags, n, a);
+  }
+
+  const double* const* leaf_state4(const double** buf) {
+    buf[0] = U;
+    buf[1] = U + n;
+    buf[2] = U + 2 * n;
+    buf[3] = phit;
+    return buf;
+  }
+
+  // ------------------------------------------------------------ reductions --
+  double dot(const double* a, const double* b, int64_t len) {
+    hipLaunchKernelGGL((k_dot_partial<double>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, a, b, len, red_part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, 1, red_out);
+    HIPCHK(hipMemcpyAsync(host_red, red_out, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return host_red[0];
+  }
+  template <typename T>
+  void dot2_async(const T* a, const T* b, int64_t len, double* out_dev) {
+    hipLaunchKernelGGL((k_dot_partial<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, a, b, len, red_part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, 1, out_dev);
+  }
+  void mdot(const double* Vb, int k, const double* w, int64_t len, double* host_out) {
+    hipLaunchKernelGGL(k_mdot_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, Vb, w, k, len, red_part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, k, red_out);
+    HIPCHK(hipMemcpyAsync(host_out, red_out, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  double norm(const double* a, int64_t len) { return std::sqrt(dot(a, a, len)); }
+
+  // ------------------------------------------------------------ levels -----
+  template <typename T>
+  LevelWork<T>& work(DevLevel& L);
+
+  template <typename T>
+  void ensure_level_work(DevLevel& L, const Level& HL) {
+    LevelWork<T>& w = work<T>(L);
+    if (w.ready) return;
+    const int64_t nl = L.n;
+    w.state = dalloc<T>(3 * nl);
+    w.d = dalloc<T>(3 * nl);
+    for (int i = 0; i < 2; ++i) { w.x[i] = dalloc<T>(3 * nl); w.dir[i] = dalloc<T>(3 * nl); }
+    w.dinv = dalloc<T>(3 * nl);
+    if (!HL.P.val.empty()) {
+      std::vector<T> pv(HL.P.val.begin(), HL.P.val.end()), ptv(HL.PT.val.begin(), HL.PT.val.end());
+      w.Pval = upload(pv);
+      w.PTval = upload(ptv);
+    }
+    w.ready = true;
+  }
+
+  template <typename T>
+  void level_apply(int l, const T* x, T* dst, int epi, const T* b, const T* dold, T* xnew, const T c1[2],
+                   const T c2[2]) {
+    DevLevel& L = lv[l];
+    LevelWork<T>& w = work<T>(L);
+    TileArgs<T> a{};
+    a.src = x;
+    a.dst = dst;
+    a.st[0] = w.state;
+    a.st[1] = w.state + L.n;
+    a.st[2] = w.state + 2 * L.n;
+    a.b = b;
+    a.dold = dold;
+    a.dinv = w.dinv;
+    a.xnew = xnew;
+    for (int i = 0; i < 2; ++i) { a.c1[i] = c1 ? c1[i] : T(0); a.c2[i] = c2 ? c2[i] : T(0); }
+    if (epi == EPI_PLAIN) launch_tile<T, MODE_LEVEL, EPI_PLAIN>(L.tiles, L.flags, L.n, a);
+    else if (epi == EPI_RESID) launch_tile<T, MODE_LEVEL, EPI_RESID>(L.tiles, L.flags, L.n, a);
+    else launch_tile<T, MODE_LEVEL, EPI_CHEB>(L.tiles, L.flags, L.n, a);
+  }
+
+  template <typename T>
+  void level_diag(int l) {
+    DevLevel& L = lv[l];
+    LevelWork<T>& w = work<T>(L);
+    TileArgs<T> a{};
+    a.dst = w.dinv;
+    a.st[0] = w.state;
+    a.st[1] = w.state + L.n;
+    a.st[2] = w.state + 2 * L.n;
+    launch_tile<T, MODE_DIAG_LEVEL, EPI_PLAIN>(L.tiles, L.flags, L.n, a);
+  }
+
+  // smoothing interval per block on level l
+  void interval(int l, double lo[2], double hi[2]) const {
+    const DevLevel& L = lv[l];
+    for (int b = 0; b < 2; ++b) {
+      if (l == 0 && prm.coarse_mode == 0) {
+        lo[b] = L.lam_min[b];
+        hi[b] = prm.upper_factor * L.lam_max[b];
+      } else {
+        lo[b] = prm.smooth_range * L.lam_max[b];
+        hi[b] = prm.upper_factor * L.lam_max[b];
+      }
+    }
+  }
+
+  // Chebyshev-Jacobi smoothing (Saad, Alg. 12.1 on D^{-1}A; residual from its
+  // definition at every update). x_in = nullptr: start from x = 0. Result in
+  // w.x[*out_idx].
+  template <typename T>
+  int chebyshev(int l, const T* b, int x_in_idx, int degree) {
+    DevLevel& L = lv[l];
+    LevelWork<T>& w = work<T>(L);
+    double lo[2], hi[2];
+    interval(l, lo, hi);
+    double theta[2], delta[2], rho_prev[2];
+    for (int k = 0; k < 2; ++k) {
+      theta[k] = 0.5 * (hi[k] + lo[k]);
+      delta[k] = 0.5 * (hi[k] - lo[k]);
+      rho_prev[k] = delta[k] / theta[k];
+    }
+    const int64_t nl = L.n;
+    int xi, di = 0;
+    T c1[2], c2[2];
+    if (x_in_idx < 0) {
+      xi = 0;
+      hipLaunchKernelGGL((k_cheb_first<T>), dim3(grid_for(3 * nl)), dim3(256), 0, s, w.x[0], w.dir[0], b, w.dinv,
+                         nl, T(1.0 / theta[0]), T(1.0 / theta[1]));
+    } else {
+      xi = x_in_idx;
+      for (int k = 0; k < 2; ++k) { c1[k] = T(0); c2[k] = T(1.0 / theta[k]); }
+      level_apply<T>(l, w.x[xi], w.dir[0], EPI_CHEB, b, nullptr, w.x[1 - xi], c1, c2);
+      xi = 1 - xi;
+    }
+    for (int j = 1; j < degree; ++j) {
+      for (int k = 0; k < 2; ++k) {
+        const double rho = 1.0 / (2.0 * theta[k] / delta[k] - rho_prev[k]);
+        c1[k] = T(rho * rho_prev[k]);
+        c2[k] = T(2.0 * rho / delta[k]);
+        rho_prev[k] = rho;
+      }
+      level_apply<T>(l, w.x[xi], w.dir[1 - di], EPI_CHEB, b, w.dir[di], w.x[1 - xi], c1, c2);
+      xi = 1 - xi;
+      di = 1 - di;
+    }
+    return xi;
+  }
+
+  template <typename T>
+  void vcycle_impl(double* dst, const double* src) {
+    const int L = int(lv.size()) - 1;
+    const int k = prm.cheb_degree;
+    std::vector<int> xi(L + 1, 0);
+    for (int l = 0; l <= L; ++l) {
+      DevLevel& D = lv[l];
+      LevelWork<T>& w = work<T>(D);
+      hipLaunchKernelGGL((k_copy_to_level<T>), dim3(grid_for(3 * D.n)), dim3(256), 0, s, w.d, D.n, D.flags,
+                         D.leaf_index, src, flags, n);
+    }
+    for (int l = L; l >= 1; --l) {
+      DevLevel& D = lv[l];
+      LevelWork<T>& w = work<T>(D);
+      xi[l] = chebyshev<T>(l, w.d, -1, k);
+      // t = d - A x (all rows) into the free direction buffer
+      T* t = w.dir[0];
+      level_apply<T>(l, w.x[xi[l]], t, EPI_RESID, w.d, nullptr, nullptr, nullptr, nullptr);
+      DevLevel& C = lv[l - 1];
+      LevelWork<T>& wc = work<T>(C);
+      hipLaunchKernelGGL((k_restrict_add<T>), dim3(grid_for(C.n)), dim3(256), 0, s, wc.d, t, C.n, D.n, D.PT_ptr,
+                         D.PT_col, w.PTval);
+    }
+    {
+      LevelWork<T>& w0 = work<T>(lv[0]);
+      xi[0] = chebyshev<T>(0, w0.d, -1, prm.coarse_its);
+    }
+    for (int l = 1; l <= L; ++l) {
+      DevLevel& D = lv[l];
+      LevelWork<T>& w = work<T>(D);
+      LevelWork<T>& wc = work<T>(lv[l - 1]);
+      hipLaunchKernelGGL((k_prolong_add<T>), dim3(grid_for(D.n)), dim3(256), 0, s, w.x[xi[l]], wc.x[xi[l - 1]], D.n,
+                         lv[l - 1].n, D.P_ptr, D.P_col, w.Pval);
+      xi[l] = chebyshev<T>(l, w.d, xi[l], k);
+    }
+    for (int l = 0; l <= L; ++l) {
+      DevLevel& D = lv[l];
+      LevelWork<T>& w = work<T>(D);
+      hipLaunchKernelGGL((k_copy_from_level<T>), dim3(grid_for(3 * D.n)), dim3(256), 0, s, dst, w.x[xi[l]], D.n,
+                         D.flags, D.leaf_index, src, flags, n);
+    }
+    if (n_hang)
+      hipLaunchKernelGGL(k_copy_hanging, dim3(grid_for(3 * n_hang)), dim3(256), 0, s, dst, src, n, hang, n_hang);
+    HIPCHK(hipGetLastError());
+  }
+
+  // Extreme Ritz values of D^{-1} A (free unknowns of one block) from
+  // `its` Jacobi-preconditioned CG steps on A x = 1.
+  void eig_estimate(int l, int its) {
+    DevLevel& L = lv[l];
+    LevelWork<double>& w = w64of(L);
+    const int64_t nl = L.n;
+    double* r = w.x[0];
+    double* z = w.x[1];
+    double* pv = w.dir[0];
+    double* q = w.dir[1];
+    for (int blk = 0; blk < 2; ++blk) {
+      const int64_t off = blk == 0 ? 0 : 2 * nl, len = blk == 0 ? 2 * nl : nl;
+      // r = 1 on free unknowns of the block (dinv != 0 exactly there), else 0
+      hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(3 * nl)), dim3(256), 0, s, r, 0.0, 3 * nl);
+      hipLaunchKernelGGL(k_free_ones, dim3(grid_for(len)), dim3(256), 0, s, r + off, w.dinv + off, len);
+      hipLaunchKernelGGL(k_mul, dim3(grid_for(3 * nl)), dim3(256), 0, s, z, w.dinv, r, 3 * nl);
+      HIPCHK(hipMemcpyAsync(pv, z, sizeof(double) * 3 * nl, hipMemcpyDeviceToDevice, s));
+      double rz = dot(r + off, z + off, len);
+      std::vector<double> al, be;
+      for (int it = 0; it < its && rz > 0.0; ++it) {
+        level_apply<double>(l, pv, q, EPI_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr);
+        // only the block's free rows matter: p is zero elsewhere
+        const double pq = dot(pv + off, q + off, len);
+        if (!(pq > 0.0)) break;
+        const double alpha = rz / pq;
+        hipLaunchKernelGGL(k_cg_update, dim3(grid_for(len)), dim3(256), 0, s, r + off, z + off, q + off,
+                           w.dinv + off, alpha, len);
+        const double rz2 = dot(r + off, z + off, len);
+        const double beta = rz2 / rz;
+        al.push_back(alpha);
+        be.push_back(beta);
+        hipLaunchKernelGGL(k_waxpy, dim3(grid_for(len)), dim3(256), 0, s, pv + off, z + off, pv + off, beta, len);
+        rz = rz2;
+      }
+      const int m = int(al.size());
+      double lo = 1.0, hi = 1.0;
+      if (m > 0) {
+        std::vector<double> dg(m), of(m > 1 ? m - 1 : 0);
+        for (int j = 0; j < m; ++j) dg[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+        for (int j = 0; j + 1 < m; ++j) of[j] = std::sqrt(be[j]) / al[j];
+        tridiag_extremes(dg, of, &lo, &hi);
+      }
+      L.lam_max[blk] = hi;
+      L.lam_min[blk] = lo;
+    }
+  }
+
+  // Smallest and largest eigenvalue of a symmetric tridiagonal matrix by
+  // bisection on the Sturm sequence count.
+  static void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e, double* lo, double* hi) {
+    const int m = int(d.size());
+    double a = d[0], b = d[0];
+    for (int i = 0; i < m; ++i) {
+      double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(e[i]) : 0.0);
+      a = std::min(a, d[i] - r);
+      b = std::max(b, d[i] + r);
+    }
+    auto count_below = [&](double x) {
+      int c = 0;
+      double q = d[0] - x;
+      if (q < 0) ++c;
+      for (int i = 1; i < m; ++i) {
+        const double qq = (q == 0.0) ? 1e-300 : q;
+        q = d[i] - x - e[i - 1] * e[i - 1] / qq;
+        if (q < 0) ++c;
+      }
+      return c;
+    };
+    auto kth = [&](int k) {  // k-th smallest (0-based)
+      double l = a, u = b;
+      for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (l + u);
+        if (mid == l || mid == u) break;
+        if (count_below(mid) > k) u = mid; else l = mid;
+      }
+      return 0.5 * (l + u);
+    };
+    *lo = kth(0);
+    *hi = kth(m - 1);
+  }
+
+  LevelWork<double>& w64of(DevLevel& L) { return L.w64; }
+
+  template <typename T>
+  void setup_levels() {
+    for (int l = 0; l < int(lv.size()); ++l) {
+      ensure_level_work<T>(lv[l], mesh.levels[l]);
+      LevelWork<T>& w = work<T>(lv[l]);
+      hipLaunchKernelGGL((k_inject<T>), dim3(grid_for(lv[l].n)), dim3(256), 0, s, w.state, lv[l].n,
+                         lv[l].leaf_index, U, phit, n);
+    }
+    for (int l = 0; l < int(lv.size()); ++l) level_diag<T>(l);
+    HIPCHK(hipGetLastError());
+  }
+
+  void level_active_sets() {
+    const int L = int(lv.size()) - 1;
+    for (int l = L; l >= 0; --l) {
+      const int64_t* ptp = l < L ? lv[l + 1].PT_ptr : nullptr;
+      const int32_t* ptc = l < L ? lv[l + 1].PT_col : nullptr;
+      const uint8_t* ff = l < L ? lv[l + 1].flags : nullptr;
+      hipLaunchKernelGGL(k_level_active, dim3(grid_for(lv[l].n)), dim3(256), 0, s, lv[l].flags, lv[l].n,
+                         lv[l].leaf_index, flags, ptp, ptc, ff);
+    }
+    HIPCHK(hipGetLastError());
+  }
+
+  void setup_mg() {
+    level_active_sets();
+    setup_levels<double>();
+    if (!eig_fixed)
+      for (int l = 0; l < int(lv.size()); ++l) eig_estimate(l, l == 0 ? prm.coarse_eig_its : prm.eig_cg_its);
+    if (prm.vcycle_fp32) setup_levels<float>();
+    mg_ready = true;
+  }
+
+  void residual(double* R, const double* Ust) {
+    const double* st[4] = {phit, nullptr, nullptr, nullptr};
+    leaf_op<MODE_RESID>(R, Ust, st);
+  }
+
+  // ---------------------------------------------------------------- GMRES --
+  void apply_A(double* dst, const double* src, bool transpose) {
+    const double* st[4];
+    leaf_state4(st);
+    if (transpose) leaf_op<MODE_JT>(dst, src, st);
+    else leaf_op<MODE_J>(dst, src, st);
+  }
+  void apply_Minv(double* dst, const double* src, bool fp32) {
+    if (fp32) {
+      if (!lv[0].w32.ready) setup_levels<float>();
+      vcycle_impl<float>(dst, src);
+    } else {
+      vcycle_impl<double>(dst, src);
+    }
+  }
+
+  int gmres(double* x, const double* b, bool transpose, double tol, pff_gmres_info* info, bool fp32) {
+    const int64_t N = 3 * n;
+    const int m = std::max(1, prm.gmres_restart);
+    if (V_cap < m + 1) {
+      if (V) hipFree(V);
+      V = dalloc<double>(int64_t(m + 1) * N);
+      V_cap = m + 1;
+    }
+    double* w = wv[0];
+    double* t = wv[1];
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+    apply_Minv(V, b, fp32);
+    double beta = norm(V, N);
+    pff_gmres_info inf{};
+    inf.initial_residual = beta;
+    inf.final_residual = beta;
+    inf.tolerance = tol;
+    int its = 0;
+    bool conv = beta <= tol;
+    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), h1(m + 1), h2(m + 1);
+    double* hdev = red_out + 64;
+    while (!conv && its < prm.gmres_max_its) {
+      hipLaunchKernelGGL(k_scale, dim3(grid_for(N)), dim3(256), 0, s, V, V, 1.0 / beta, N);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int jdone = 0;
+      double resid = beta;
+      for (int j = 0; j < m; ++j) {
+        double* vj = V + int64_t(j) * N;
+        double* vn = V + int64_t(j + 1) * N;
+        apply_A(t, vj, transpose);
+        apply_Minv(vn, t, fp32);
+        // classical Gram-Schmidt, twice
+        for (int pass = 0; pass < 2; ++pass) {
+          std::vector<double>& h = pass == 0 ? h1 : h2;
+          mdot(V, j + 1, vn, N, h.data());
+          HIPCHK(hipMemcpyAsync(hdev, h.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, s));
+          hipLaunchKernelGGL(k_mcombine, dim3(grid_for(N)), dim3(256), 0, s, vn, V, hdev, j + 1, N, -1.0);
+        }
+        double hn = norm(vn, N);
+        std::vector<double> h(j + 2);
+        for (int i = 0; i <= j; ++i) h[i] = h1[i] + h2[i];
+        for (int i = 0; i < j; ++i) {
+          const double tt = cs[i] * h[i] + sn[i] * h[i + 1];
+          h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+          h[i] = tt;
+        }
+        const double den = std::hypot(h[j], hn);
+        cs[j] = h[j] / den;
+        sn[j] = hn / den;
+        h[j] = den;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = h[i];
+        resid = std::fabs(g[j + 1]);
+        ++its;
+        jdone = j + 1;
+        if (hn > 0.0) hipLaunchKernelGGL(k_scale, dim3(grid_for(N)), dim3(256), 0, s, vn, vn, 1.0 / hn, N);
+        if (resid <= tol || its >= prm.gmres_max_its || hn == 0.0) break;
+      }
+      std::vector<double> y(jdone);
+      for (int i = jdone - 1; i >= 0; --i) {
+        double sum = g[i];
+        for (int k = i + 1; k < jdone; ++k) sum -= H[size_t(i) * m + k] * y[k];
+        y[i] = sum / H[size_t(i) * m + i];
+      }
+      HIPCHK(hipMemcpyAsync(hdev, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_mcombine, dim3(grid_for(N)), dim3(256), 0, s, x, V, hdev, jdone, N, 1.0);
+      inf.final_residual = resid;
+      if (resid <= tol) { conv = true; break; }
+      if (its >= prm.gmres_max_its) break;
+      // restart: V_0 = Minv (b - A x)
+      apply_A(t, x, transpose);
+      hipLaunchKernelGGL(k_sub, dim3(grid_for(N)), dim3(256), 0, s, w, b, t, N);
+      apply_Minv(V, w, fp32);
+      beta = norm(V, N);
+      inf.final_residual = beta;
+      if (beta <= tol) { conv = true; break; }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    inf.iterations = its;
+    inf.converged = conv ? 1 : 0;
+    if (info) *info = inf;
+    return conv ? PFF_OK : PFF_W_NOCONV;
+  }
+};
+
+template <>
+LevelWork<double>& pff_ctx::work<double>(DevLevel& L) { return L.w64; }
+template <>
+LevelWork<float>& pff_ctx::work<float>(DevLevel& L) { return L.w32; }
+
+// ------------------------------------------------------------------ C ABI --
+#define GUARD_BEGIN try {
+#define GUARD_END(ctx)                                      \
+  }                                                         \
+  catch (const std::bad_alloc&) {                           \
+    if (ctx) (ctx)->err = "device allocation failed";       \
+    return PFF_E_NOMEM;                                     \
+  }                                                         \
+  catch (const std::exception& e) {                         \
+    if (ctx) (ctx)->err = e.what();                         \
+    return PFF_E_HIP;                                       \
+  }
+
+extern "C" {
+
+int pff_default_params(pff_params* p) {
+  if (!p) return PFF_E_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->E = 1.0;
+  p->nu = 0.2;
+  p->Gc = 1.0;
+  p->pressure = 1e-3;
+  p->kappa = 1e-10;
+  p->ell = 0.1;
+  p->cheb_degree = 3;
+  p->smooth_range = 0.08;
+  p->upper_factor = 1.2;
+  p->eig_cg_its = 10;
+  p->coarse_mode = 0;
+  p->coarse_its = 30;
+  p->coarse_eig_its = 40;
+  p->gmres_restart = 30;
+  p->gmres_max_its = 300;
+  p->gmres_rtol = 1e-8;
+  p->gmres_atol = 1e-12;
+  p->ls_omega = 0.5;
+  p->ls_max = 10;
+  p->vcycle_fp32 = 0;
+  return PFF_OK;
+}
+
+int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** out) {
+  if (!spec || !params || !out) return PFF_E_ARG;
+  *out = nullptr;
+  std::unique_ptr<pff_ctx> c(new pff_ctx());
+  MeshSpec ms;
+  ms.n_base = spec->n_base;
+  ms.n_local = spec->n_local;
+  ms.degree = spec->degree;
+  ms.coarse = spec->coarse > 0 ? spec->coarse : 16;
+  ms.band_x = spec->band_x;
+  ms.band_y = spec->band_y;
+  ms.tile_x = spec->tile_x;
+  ms.tile_y = spec->tile_y;
+  if (params->cheb_degree < 1 || params->coarse_its < 1 || params->gmres_restart < 1 ||
+      params->gmres_restart > 60 || params->coarse_mode != 0)
+    return PFF_E_ARG;
+  try {
+    if (!c->mesh.build(ms)) {
+      static thread_local std::string msg;
+      msg = c->mesh.error;
+      return PFF_E_MESH;
+    }
+    if (c->mesh.n_levels > 16) return PFF_E_ARG;
+    for (const Level& L : c->mesh.levels)
+      if (L.tiles.max_local > 65535) return PFF_E_MESH;
+    if (c->mesh.tiles.max_local > 65535) return PFF_E_MESH;
+    c->prm = *params;
+    c->p = ms.degree;
+    c->n = c->mesh.n_nodes;
+    const int64_t n = c->n;
+    c->tiles = upload_tiles(c->mesh.tiles);
+    c->flags = upload(c->mesh.flags);
+    c->hang = upload(c->mesh.hanging);
+    c->n_hang = int(c->mesh.hanging.size());
+    c->lv.resize(c->mesh.levels.size());
+    for (size_t l = 0; l < c->lv.size(); ++l) {
+      const Level& HL = c->mesh.levels[l];
+      DevLevel& D = c->lv[l];
+      D.n = HL.n;
+      D.tiles = upload_tiles(HL.tiles);
+      D.flags = upload(HL.flags);
+      D.leaf_index = upload(HL.leaf_index);
+      if (l > 0) {
+        D.P_ptr = upload(HL.P.ptr);
+        D.P_col = upload(HL.P.col);
+        D.PT_ptr = upload(HL.PT.ptr);
+        D.PT_col = upload(HL.PT.col);
+      }
+    }
+    c->U = dalloc<double>(3 * n);
+    c->phio = dalloc<double>(n);
+    c->phit = dalloc<double>(n);
+    c->mass = dalloc<double>(3 * n);
+    for (int i = 0; i < 8; ++i) c->wv[i] = dalloc<double>(3 * n);
+    c->red_part = dalloc<double>(RED_BLOCKS * 64);
+    c->red_out = dalloc<double>(256);
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->host_red), 256 * sizeof(double), hipHostMallocDefault));
+    // lumped phase-field mass (the B of Alg. 2)
+    c->leaf_op<MODE_MASS>(c->mass, nullptr, nullptr);
+    HIPCHK(hipStreamSynchronize(c->s));
+  } catch (const std::bad_alloc&) {
+    return PFF_E_NOMEM;
+  } catch (const std::exception&) {
+    return PFF_E_HIP;
+  }
+  *out = c.release();
+  return PFF_OK;
+}
+
+int pff_destroy(pff_ctx* c) {
+  if (!c) return PFF_E_ARG;
+  auto f = [](void* p) { if (p) hipFree(p); };
+  auto ft = [&](DevTiles& t) { f(t.info); f(t.halo); f(t.loc); f(t.cinfo); };
+  ft(c->tiles);
+  f(c->flags);
+  f(c->hang);
+  for (DevLevel& D : c->lv) {
+    ft(D.tiles);
+    f(D.flags); f(D.leaf_index); f(D.P_ptr); f(D.P_col); f(D.PT_ptr); f(D.PT_col);
+    for (auto* w : {&D.w64}) {
+      f(w->state); f(w->d); f(w->x[0]); f(w->x[1]); f(w->dir[0]); f(w->dir[1]); f(w->dinv); f(w->Pval); f(w->PTval);
+    }
+    LevelWork<float>& w = D.w32;
+    f(w.state); f(w.d); f(w.x[0]); f(w.x[1]); f(w.dir[0]); f(w.dir[1]); f(w.dinv); f(w.Pval); f(w.PTval);
+  }
+  f(c->U); f(c->phio); f(c->phit); f(c->mass);
+  for (int i = 0; i < 8; ++i) f(c->wv[i]);
+  f(c->red_part); f(c->red_out); f(c->V);
+  if (c->host_red) hipHostFree(c->host_red);
+  delete c;
+  return PFF_OK;
+}
+
+int pff_set_params(pff_ctx* c, const pff_params* p) {
+  if (!c || !p) return PFF_E_ARG;
+  if (p->cheb_degree < 1 || p->coarse_its < 1 || p->gmres_restart < 1 || p->gmres_restart > 60 ||
+      p->coarse_mode != 0)
+    return PFF_E_ARG;
+  c->prm = *p;
+  c->mg_ready = false;
+  return PFF_OK;
+}
+
+int pff_sizes(const pff_ctx* c, int64_t* n_nodes, int32_t* n_levels, int64_t* level_nodes) {
+  if (!c) return PFF_E_ARG;
+  if (n_nodes) *n_nodes = c->n;
+  if (n_levels) *n_levels = int32_t(c->lv.size());
+  if (level_nodes)
+    for (size_t l = 0; l < c->lv.size(); ++l) level_nodes[l] = c->lv[l].n;
+  return PFF_OK;
+}
+
+int pff_lattice(const pff_ctx* c, int64_t* M) {
+  if (!c || !M) return PFF_E_ARG;
+  *M = c->mesh.M;
+  return PFF_OK;
+}
+
+int pff_node_coords(const pff_ctx* c, int32_t level, int32_t* xy) {
+  if (!c || !xy || level < -1 || level >= int32_t(c->lv.size())) return PFF_E_ARG;
+  const std::vector<int32_t>& X = level < 0 ? c->mesh.NX : c->mesh.levels[level].NX;
+  const std::vector<int32_t>& Y = level < 0 ? c->mesh.NY : c->mesh.levels[level].NY;
+  std::memcpy(xy, X.data(), X.size() * sizeof(int32_t));
+  std::memcpy(xy + X.size(), Y.data(), Y.size() * sizeof(int32_t));
+  return PFF_OK;
+}
+
+int pff_node_flags(const pff_ctx* c, int32_t level, uint8_t* out) {
+  if (!c || !out || level < -1 || level >= int32_t(c->lv.size())) return PFF_E_ARG;
+  const int64_t nn = level < 0 ? c->n : c->lv[level].n;
+  const uint8_t* src = level < 0 ? c->flags : c->lv[level].flags;
+  if (hipMemcpy(out, src, size_t(nn), hipMemcpyDeviceToHost) != hipSuccess) return PFF_E_HIP;
+  return PFF_OK;
+}
+
+int pff_tile_stats(const pff_ctx* c, int32_t level, int64_t* n_tiles, int64_t* n_records, int64_t* max_cells) {
+  if (!c || level < -1 || level >= int32_t(c->lv.size())) return PFF_E_ARG;
+  const DevTiles& t = level < 0 ? c->tiles : c->lv[level].tiles;
+  if (n_tiles) *n_tiles = t.n_tiles;
+  if (n_records) *n_records = t.n_rec;
+  if (max_cells) *max_cells = t.max_cells;
+  return PFF_OK;
+}
+
+int pff_set_state(pff_ctx* c, const double* U, const double* phi_old, const double* phi_tilde,
+                  const uint8_t* active, int32_t setup_mg, void* stream) {
+  if (!c || !U || !phi_old || !phi_tilde) return PFF_E_ARG;
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  const int64_t n = c->n;
+  HIPCHK(hipMemcpyAsync(c->U, U, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(c->phio, phi_old, sizeof(double) * n, hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(c->phit, phi_tilde, sizeof(double) * n, hipMemcpyDeviceToDevice, c->s));
+  if (c->n_hang) {
+    const int np1 = c->p + 1;
+    hipLaunchKernelGGL((k_distribute<double>), dim3(grid_for(3 * c->n_hang)), dim3(256), 0, c->s, c->U, n, 3, c->hang,
+                       c->n_hang, np1);
+    hipLaunchKernelGGL((k_distribute<double>), dim3(grid_for(c->n_hang)), dim3(256), 0, c->s, c->phit, n, 1, c->hang,
+                       c->n_hang, np1);
+    hipLaunchKernelGGL((k_distribute<double>), dim3(grid_for(c->n_hang)), dim3(256), 0, c->s, c->phio, n, 1, c->hang,
+                       c->n_hang, np1);
+  }
+  if (active) {
+    hipLaunchKernelGGL(k_set_active, dim3(grid_for(n)), dim3(256), 0, c->s, c->flags, active, n);
+  } else {
+    double* R = c->wv[2];
+    c->residual(R, c->U);
+    hipLaunchKernelGGL(k_active_rule, dim3(grid_for(n)), dim3(256), 0, c->s, c->flags, R, c->mass + 2 * n,
+                       c->U + 2 * n, c->phio, n);
+  }
+  HIPCHK(hipGetLastError());
+  c->has_state = true;
+  c->mg_ready = false;
+  if (setup_mg) {
+    c->setup_mg();
+    HIPCHK(hipStreamSynchronize(c->s));
+  }
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_get_active(pff_ctx* c, uint8_t* active, void* stream) {
+  if (!c || !active) return PFF_E_ARG;
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_get_active, dim3(grid_for(c->n)), dim3(256), 0, c->s, active, c->flags, c->n);
+  HIPCHK(hipGetLastError());
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_vmult(pff_ctx* c, double* dst, const double* src, void* stream) {
+  if (!c || !dst || !src || dst == src) return PFF_E_ARG;
+  if (!c->has_state) { c->err = "vmult needs a state"; return PFF_E_STATE; }
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  c->apply_A(dst, src, false);
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_vmult_T(pff_ctx* c, double* dst, const double* src, int32_t batch, void* stream) {
+  if (!c || !dst || !src || dst == src || batch < 1) return PFF_E_ARG;
+  if (!c->has_state) { c->err = "vmult_T needs a state"; return PFF_E_STATE; }
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  for (int b = 0; b < batch; ++b) c->apply_A(dst + int64_t(b) * 3 * c->n, src + int64_t(b) * 3 * c->n, true);
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_inverse_diagonal(pff_ctx* c, int32_t level, void* dst, int32_t fp32, void* stream) {
+  if (!c || !dst || level < -1 || level >= int32_t(c->lv.size())) return PFF_E_ARG;
+  if (!c->has_state) { c->err = "inverse_diagonal needs a state"; return PFF_E_STATE; }
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  if (level < 0) {
+    const double* st[4];
+    c->leaf_state4(st);
+    TileArgs<double> a{};
+    a.dst = static_cast<double*>(dst);
+    for (int i = 0; i < 4; ++i) a.st[i] = st[i];
+    c->launch_tile<double, MODE_DIAG_LEAF, EPI_PLAIN>(c->tiles, c->flags, c->n, a);
+    return PFF_OK;
+  }
+  if (!c->mg_ready) { c->err = "level diagonals need set_state with setup_mg"; return PFF_E_STATE; }
+  DevLevel& D = c->lv[level];
+  if (fp32) {
+    if (!D.w32.ready) c->setup_levels<float>();
+    HIPCHK(hipMemcpyAsync(dst, D.w32.dinv, sizeof(float) * 3 * D.n, hipMemcpyDeviceToDevice, c->s));
+  } else {
+    HIPCHK(hipMemcpyAsync(dst, D.w64.dinv, sizeof(double) * 3 * D.n, hipMemcpyDeviceToDevice, c->s));
+  }
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_vcycle(pff_ctx* c, double* dst, const double* src, int32_t fp32, void* stream) {
+  if (!c || !dst || !src || dst == src) return PFF_E_ARG;
+  if (!c->has_state || !c->mg_ready) { c->err = "vcycle needs set_state with setup_mg"; return PFF_E_STATE; }
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  c->apply_Minv(dst, src, fp32 != 0);
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_get_eigen(const pff_ctx* c, double* lam_max, double* lam_min0) {
+  if (!c) return PFF_E_ARG;
+  for (size_t l = 0; l < c->lv.size(); ++l)
+    for (int b = 0; b < 2; ++b)
+      if (lam_max) lam_max[2 * l + b] = c->lv[l].lam_max[b];
+  if (lam_min0)
+    for (int b = 0; b < 2; ++b) lam_min0[b] = c->lv[0].lam_min[b];
+  return PFF_OK;
+}
+
+int pff_set_eigen(pff_ctx* c, const double* lam_max, const double* lam_min0) {
+  if (!c) return PFF_E_ARG;
+  if (!lam_max) { c->eig_fixed = false; return PFF_OK; }
+  for (size_t l = 0; l < c->lv.size(); ++l)
+    for (int b = 0; b < 2; ++b) c->lv[l].lam_max[b] = lam_max[2 * l + b];
+  if (lam_min0)
+    for (int b = 0; b < 2; ++b) c->lv[0].lam_min[b] = lam_min0[b];
+  c->eig_fixed = true;
+  return PFF_OK;
+}
+
+int pff_gmres_solve(pff_ctx* c, double* x, const double* b, int32_t transpose, double tol_override,
+                    pff_gmres_info* info, void* stream) {
+  if (!c || !x || !b || x == b) return PFF_E_ARG;
+  if (!c->has_state || !c->mg_ready) { c->err = "gmres needs set_state with setup_mg"; return PFF_E_STATE; }
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  double tol = tol_override;
+  if (!(tol > 0.0)) tol = std::max(c->prm.gmres_atol, c->prm.gmres_rtol * c->norm(b, 3 * c->n));
+  return c->gmres(x, b, transpose != 0, tol, info, c->prm.vcycle_fp32 != 0);
+  GUARD_END(c)
+}
+
+int pff_residual(pff_ctx* c, double* R, const double* U, int32_t masked, void* stream) {
+  if (!c || !R || !U || R == U) return PFF_E_ARG;
+  if (!c->has_state) { c->err = "residual needs a state"; return PFF_E_STATE; }
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  c->residual(R, U);
+  if (masked) hipLaunchKernelGGL(k_mask_leaf, dim3(grid_for(3 * c->n)), dim3(256), 0, c->s, R, c->flags, c->n);
+  HIPCHK(hipGetLastError());
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_newton_step(pff_ctx* c, double* U, const double* phi_old, const double* phi_tilde, uint8_t* active_inout,
+                    pff_newton_info* info, void* stream) {
+  if (!c || !U || !phi_old || !phi_tilde) return PFF_E_ARG;
+  GUARD_BEGIN
+  using clk = std::chrono::steady_clock;
+  auto t0 = clk::now();
+  c->s = static_cast<hipStream_t>(stream);
+  const int64_t n = c->n, N = 3 * n;
+  pff_newton_info inf{};
+  // state at U (hanging entries distributed), residual, active set
+  int rc = pff_set_state(c, U, phi_old, phi_tilde, nullptr, 0, stream);
+  if (rc) return rc;
+  double* R = c->wv[2];
+  double* Uc = c->wv[3];
+  double* dU = c->wv[4];
+  double* trial = c->wv[5];
+  double* Rt = c->wv[6];
+  c->residual(R, c->U);
+  // counts of active entries and changes
+  hipLaunchKernelGGL(k_count_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->s, c->flags, active_inout, n,
+                     c->red_part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, c->s, c->red_part, RED_BLOCKS, 2, c->red_out);
+  HIPCHK(hipMemcpyAsync(c->host_red, c->red_out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  inf.n_active = int64_t(c->host_red[0]);
+  inf.active_changed = int64_t(c->host_red[1]);
+  // baseline |R~(U)|
+  hipLaunchKernelGGL(k_mask_leaf, dim3(grid_for(N)), dim3(256), 0, c->s, R, c->flags, n);
+  const double base = c->norm(R, N);
+  inf.residual_before = base;
+  // U_c and the right-hand side R~(U_c)
+  HIPCHK(hipMemcpyAsync(Uc, c->U, sizeof(double) * N, hipMemcpyDeviceToDevice, c->s));
+  hipLaunchKernelGGL(k_apply_active, dim3(grid_for(n)), dim3(256), 0, c->s, Uc, c->phio, c->flags, n);
+  c->residual(Rt, Uc);
+  hipLaunchKernelGGL(k_mask_leaf, dim3(grid_for(N)), dim3(256), 0, c->s, Rt, c->flags, n);
+  inf.rhs_norm = c->norm(Rt, N);
+  // multigrid setup at U
+  c->setup_mg();
+  HIPCHK(hipStreamSynchronize(c->s));
+  auto t1 = clk::now();
+  // GMRES
+  const double tol = std::max(c->prm.gmres_atol, c->prm.gmres_rtol * inf.rhs_norm);
+  pff_gmres_info gi{};
+  int grc = c->gmres(dU, Rt, false, tol, &gi, c->prm.vcycle_fp32 != 0);
+  inf.gmres_iterations = gi.iterations;
+  inf.gmres_converged = gi.converged;
+  auto t2 = clk::now();
+  // dU = (U_c - U) + dU_f, hanging entries from masters
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(N)), dim3(256), 0, c->s, dU, Uc, 1.0, N);
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(N)), dim3(256), 0, c->s, dU, c->U, -1.0, N);
+  if (c->n_hang)
+    hipLaunchKernelGGL((k_distribute<double>), dim3(grid_for(3 * c->n_hang)), dim3(256), 0, c->s, dU, n, 3, c->hang,
+                       c->n_hang, c->p + 1);
+  // line search: trial = U + omega^(l-1) dU
+  int ls = 0;
+  double rn = base;
+  bool decreased = false;
+  for (int l = 1; l <= c->prm.ls_max; ++l) {
+    const double om = std::pow(c->prm.ls_omega, double(l - 1));
+    hipLaunchKernelGGL(k_waxpy, dim3(grid_for(N)), dim3(256), 0, c->s, trial, c->U, dU, om, N);
+    c->residual(Rt, trial);
+    hipLaunchKernelGGL(k_mask_leaf, dim3(grid_for(N)), dim3(256), 0, c->s, Rt, c->flags, n);
+    rn = c->norm(Rt, N);
+    ls = l;
+    if (rn < base) { decreased = true; break; }
+  }
+  HIPCHK(hipMemcpyAsync(U, trial, sizeof(double) * N, hipMemcpyDeviceToDevice, c->s));
+  if (active_inout)
+    hipLaunchKernelGGL(k_get_active, dim3(grid_for(n)), dim3(256), 0, c->s, active_inout, c->flags, n);
+  HIPCHK(hipStreamSynchronize(c->s));
+  auto t3 = clk::now();
+  inf.residual_after = rn;
+  inf.ls_trials = ls;
+  inf.setup_seconds = std::chrono::duration<double>(t1 - t0).count();
+  inf.solve_seconds = std::chrono::duration<double>(t2 - t1).count();
+  inf.linesearch_seconds = std::chrono::duration<double>(t3 - t2).count();
+  if (info) *info = inf;
+  if (grc) return grc;
+  return decreased ? PFF_OK : PFF_W_LINESEARCH;
+  GUARD_END(c)
+}
+
+int pff_tcv(pff_ctx* c, const double* U, double* tcv, double* dTCVdU, void* stream) {
+  if (!c || !U) return PFF_E_ARG;
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  double* g = dTCVdU ? dTCVdU : c->wv[7];
+  c->leaf_op<MODE_TCVGRAD>(g, U, nullptr);
+  // TCV is bilinear: int u . grad phi = (dTCV/dphi) . phi over master nodes
+  if (tcv) *tcv = c->dot(g + 2 * c->n, U + 2 * c->n, c->n);
+  HIPCHK(hipStreamSynchronize(c->s));
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_param_grad(pff_ctx* c, const double* z, double* out, void* stream) {
+  if (!c || !z || !out) return PFF_E_ARG;
+  if (!c->has_state) { c->err = "param_grad needs a state"; return PFF_E_STATE; }
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  const int64_t N = 3 * c->n;
+  double* v = c->wv[7];
+  double* zm = c->wv[6];
+  HIPCHK(hipMemcpyAsync(zm, z, sizeof(double) * N, hipMemcpyDeviceToDevice, c->s));
+  hipLaunchKernelGGL(k_mask_leaf, dim3(grid_for(N)), dim3(256), 0, c->s, zm, c->flags, c->n);
+  const double* st[4] = {c->phit, nullptr, nullptr, nullptr};
+  c->leaf_op<MODE_DGC>(v, c->U, st);
+  out[0] = c->dot(zm, v, N);
+  c->leaf_op<MODE_DE>(v, c->U, st);
+  out[1] = c->dot(zm, v, N);
+  c->leaf_op<MODE_DP>(v, c->U, st);
+  out[2] = c->dot(zm, v, N);
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_distribute(pff_ctx* c, double* v, int32_t ncomp, void* stream) {
+  if (!c || !v || ncomp < 1 || ncomp > 3) return PFF_E_ARG;
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  if (c->n_hang)
+    hipLaunchKernelGGL((k_distribute<double>), dim3(grid_for(int64_t(ncomp) * c->n_hang)), dim3(256), 0, c->s, v, c->n,
+                       ncomp, c->hang, c->n_hang, c->p + 1);
+  HIPCHK(hipGetLastError());
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_dot(pff_ctx* c, const double* a, const double* b, int64_t len, double* out, void* stream) {
+  if (!c || !a || !b || !out || len < 0) return PFF_E_ARG;
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  *out = c->dot(a, b, len);
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+const char* pff_last_error(const pff_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

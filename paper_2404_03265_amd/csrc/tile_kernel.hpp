@@ -1,0 +1,405 @@
+// Owner-computes tile kernel for every cell-based operator of the solver.
+//
+// A tile owns a contiguous range of nodes and lists every cell whose
+// footprint touches them (its own cells plus a ring of halo cells). One
+// workgroup per tile:
+//   1. stage the tile's local nodes (owned range, then halo list) into LDS,
+//      masking constrained columns;
+//   2. one thread per cell: gather the cell's nodal values from LDS, apply
+//      hanging-node interpolation, run the sum-factorised pointwise law,
+//      integrate, apply the transposed hanging-node map;
+//   3. colour-phased accumulation into LDS accumulators of the owned nodes
+//      (cells of one colour share no owned node: deterministic, no atomics);
+//   4. one coalesced write of the owned nodes through the mode's epilogue.
+// Contributions of halo cells to nodes owned by other tiles are recomputed
+// there and dropped here, so every output is written exactly once.
+#pragma once
+
+#include "cell.hpp"
+#include "mesh.hpp"
+
+namespace pff {
+
+enum Mode : int {
+  MODE_J = 0,      // leaf Jacobian (Sec. 3.1), identity on constrained rows
+  MODE_JT,         // its transpose
+  MODE_LEVEL,      // level block operator diag(G_uu, G_phiphi) (Sec. 3.2)
+  MODE_RESID,      // leaf residual R = -F(U) condensed (Problem 2)
+  MODE_DIAG_LEAF,  // inverse diagonal of the leaf operator
+  MODE_DIAG_LEVEL, // inverse diagonal of a level operator
+  MODE_TCVGRAD,    // d TCV / dU (Sec. 4)
+  MODE_DGC,        // dF/dGc
+  MODE_DE,         // dF/dE
+  MODE_DP,         // dF/dp
+  MODE_MASS,       // lumped phase-field mass (row sums)
+};
+
+enum Epi : int { EPI_PLAIN = 0, EPI_RESID = 1, EPI_CHEB = 2 };
+
+template <typename T>
+struct TileArgs {
+  const int32_t* tile_info;
+  const int32_t* halo;
+  const uint16_t* cell_loc;
+  const uint16_t* cell_info;
+  const uint8_t* flags;
+  int64_t n;
+  int max_local;
+  int max_owned;
+  T H[16];
+  Basis<T> B;
+  Material mat;
+  const T* src;      // 3n input (operand / state U)
+  const T* st[4];    // state fields: leaf (ux, uy, phi, phit); level (ux, uy, phit)
+  T* dst;            // 3n output
+  // level epilogues
+  const T* b;        // right-hand side (EPI_RESID, EPI_CHEB)
+  const T* dold;     // previous Chebyshev direction (nullable)
+  const T* dinv;     // inverse diagonal
+  T* xnew;
+  T c1[2], c2[2];    // Chebyshev coefficients per block (u, phi)
+};
+
+template <int MODE>
+struct ModeTraits {
+  static constexpr bool leaf = !(MODE == MODE_LEVEL || MODE == MODE_DIAG_LEVEL);
+  static constexpr int n_src = (MODE == MODE_J || MODE == MODE_JT || MODE == MODE_LEVEL) ? 3
+                               : (MODE == MODE_RESID || MODE == MODE_TCVGRAD || MODE == MODE_DGC ||
+                                  MODE == MODE_DE || MODE == MODE_DP) ? 3 : 0;
+  // state fields staged besides src
+  static constexpr int n_state = (MODE == MODE_J || MODE == MODE_JT || MODE == MODE_DIAG_LEAF) ? 4
+                                 : (MODE == MODE_LEVEL || MODE == MODE_DIAG_LEVEL) ? 3
+                                 : (MODE == MODE_RESID || MODE == MODE_DGC || MODE == MODE_DE || MODE == MODE_DP) ? 1
+                                 : 0;
+  // src columns are masked (constrained columns of the operator)
+  static constexpr bool mask_src = (MODE == MODE_J || MODE == MODE_JT || MODE == MODE_LEVEL);
+};
+
+template <int P, typename T, int MODE, int EPI>
+__global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
+  constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
+  using TR = ModeTraits<MODE>;
+  constexpr int NF = TR::n_src + TR::n_state;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int ML = a.max_local;
+  T* acc = lds + (NF > 0 ? NF : 1) * ML;   // [3][max_owned]
+  const int MO = a.max_owned;
+
+  const int tile = blockIdx.x;
+  const int32_t* ti = a.tile_info + 8 * tile;
+  const int o0 = ti[TILE_OWNED0], no = ti[TILE_NOWNED];
+  const int h0 = ti[TILE_HALO0], nh = ti[TILE_NHALO];
+  const int c0 = ti[TILE_CELL0], nc = ti[TILE_NCELL];
+  const int ncol = ti[TILE_NCOLOR];
+  const int nloc = no + nh;
+  const int64_t n = a.n;
+  const Material& m = a.mat;
+  const T kap = T(m.kappa), pr = T(m.pressure), Gc = T(m.Gc), ell = T(m.ell);
+  const T mu = T(m.mu), lam = T(m.lam);
+
+  // 1. stage local nodes
+  for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
+    const int64_t g = l < no ? int64_t(o0 + l) : int64_t(a.halo[h0 + l - no]);
+    if constexpr (NF > 0) {
+      const uint8_t f = a.flags[g];
+      if constexpr (TR::n_src > 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T v = a.src[c * n + g];
+          if constexpr (TR::mask_src) {
+            const bool fixed = (c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
+            if (fixed) v = T(0);
+          }
+          lds[c * ML + l] = v;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < TR::n_state; ++s) lds[(TR::n_src + s) * ML + l] = a.st[s][g];
+    }
+  }
+  for (int l = threadIdx.x; l < 3 * MO; l += blockDim.x) acc[l] = T(0);
+  __syncthreads();
+
+  // 2./3. cells, colour-phased accumulation
+  for (int base = 0; base < nc; base += blockDim.x) {
+    const int cell = base + threadIdx.x;
+    const bool live = cell < nc;
+    T out[3][NL];
+    int loc[NL];
+    unsigned info = 0;
+    int color = -1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int k = 0; k < NL; ++k) out[c][k] = T(0);
+    if (live) {
+      const int64_t rec = int64_t(c0) + cell;
+#pragma unroll
+      for (int k = 0; k < NL; ++k) loc[k] = a.cell_loc[rec * NL + k];
+      info = a.cell_info[rec];
+      color = int((info >> CELL_COLOR_SHIFT) & 15u);
+      const int lev = int((info >> CELL_LEVEL_SHIFT) & 31u);
+      const T H = a.H[lev];
+      const bool hang = TR::leaf && (info & 15u);
+      auto gather = [&](int field, T(&u)[NL]) {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) u[k] = lds[field * ML + loc[k]];
+        if (hang) hang_apply<P, T>(a.B, u, info);
+      };
+      T wq[NQ];
+#pragma unroll
+      for (int qy = 0; qy < N1; ++qy)
+#pragma unroll
+        for (int qx = 0; qx < N1; ++qx) wq[qy * N1 + qx] = a.B.w[qx] * a.B.w[qy];
+      const T invH = T(1) / H;
+
+      if constexpr (MODE == MODE_J || MODE == MODE_JT || MODE == MODE_LEVEL || MODE == MODE_DIAG_LEAF ||
+                    MODE == MODE_DIAG_LEVEL) {
+        // state-derived coefficients at the Gauss points:
+        //   g = (1-k) phit^2 + k, c1 = (1-k) S + 2 p tr e(u) + Gc/l,
+        //   Bt = 2 (1-k) phi sigma(u) + 2 p phi I (coupling, leaf only)
+        constexpr int SU = TR::n_src;
+        T cg[NQ], cc1[NQ], bxx[NQ], byy[NQ], bxy[NQ];
+        {
+          T u[NL], gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pq[NQ], tq[NQ];
+          gather(SU + 0, u);
+          interp_g<P, T>(a.B, u, gx1, gy1);
+          gather(SU + 1, u);
+          interp_g<P, T>(a.B, u, gx2, gy2);
+          if constexpr (TR::leaf) {
+            gather(SU + 2, u);
+            interp_v<P, T>(a.B, u, pq);
+            gather(SU + 3, u);
+            interp_v<P, T>(a.B, u, tq);
+          } else {
+            gather(SU + 2, u);
+            interp_v<P, T>(a.B, u, tq);
+          }
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
+            const T tr = exx + eyy;
+            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+            const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
+            cg[q] = (T(1) - kap) * tq[q] * tq[q] + kap;
+            cc1[q] = (T(1) - kap) * S + T(2) * pr * tr + Gc / ell;
+            if constexpr (TR::leaf) {
+              const T ph = pq[q];
+              bxx[q] = T(2) * (T(1) - kap) * ph * sxx + T(2) * pr * ph;
+              byy[q] = T(2) * (T(1) - kap) * ph * syy + T(2) * pr * ph;
+              bxy[q] = T(2) * (T(1) - kap) * ph * sxy;
+            } else {
+              bxx[q] = byy[q] = bxy[q] = T(0);
+            }
+          }
+        }
+        if constexpr (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
+          // diagonal of the block-diagonal part for each local master dof:
+          // interpolate the (hanging-mapped) unit vector and evaluate the forms
+#pragma unroll
+          for (int k = 0; k < NL; ++k) {
+            T u[NL], vq[NQ], gxq[NQ], gyq[NQ];
+#pragma unroll
+            for (int j = 0; j < NL; ++j) u[j] = (j == k) ? T(1) : T(0);
+            if (hang) hang_apply<P, T>(a.B, u, info);
+            interp_vg<P, T>(a.B, u, vq, gxq, gyq);
+            T dux = T(0), duy = T(0), dph = T(0);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              const T gx = gxq[q] * invH, gy = gyq[q] * invH, JxW = H * H * wq[q];
+              dux += JxW * cg[q] * ((T(2) * mu + lam) * gx * gx + mu * gy * gy);
+              duy += JxW * cg[q] * (mu * gx * gx + (T(2) * mu + lam) * gy * gy);
+              dph += JxW * (cc1[q] * vq[q] * vq[q] + Gc * ell * (gx * gx + gy * gy));
+            }
+            out[0][k] = dux;
+            out[1][k] = duy;
+            out[2][k] = dph;
+          }
+        } else {
+          T gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pv[NQ], px[NQ], py[NQ];
+          {
+            T u[NL];
+            gather(0, u);
+            interp_g<P, T>(a.B, u, gx1, gy1);
+            gather(1, u);
+            interp_g<P, T>(a.B, u, gx2, gy2);
+            gather(2, u);
+            interp_vg<P, T>(a.B, u, pv, px, py);
+          }
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
+            const T tr = exx + eyy;
+            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+            const T wg = H * wq[q];       // gradient tests: JxW / H
+            const T wv = H * H * wq[q];   // value tests: JxW
+            const T gq = cg[q];
+            T fxu = gq * sxx, fyu = gq * sxy, fxv = gq * sxy, fyv = gq * syy;
+            T val = cc1[q] * pv[q];
+            if constexpr (MODE == MODE_J) {
+              val += bxx[q] * exx + byy[q] * eyy + T(2) * bxy[q] * exy;
+            } else if constexpr (MODE == MODE_JT) {
+              fxu += pv[q] * bxx[q];
+              fyu += pv[q] * bxy[q];
+              fxv += pv[q] * bxy[q];
+              fyv += pv[q] * byy[q];
+            }
+            gx1[q] = wg * fxu;
+            gy1[q] = wg * fyu;
+            gx2[q] = wg * fxv;
+            gy2[q] = wg * fyv;
+            pv[q] = wv * val;
+            px[q] = wq[q] * Gc * ell * px[q];
+            py[q] = wq[q] * Gc * ell * py[q];
+          }
+          integrate_g<P, T>(a.B, gx1, gy1, out[0]);
+          integrate_g<P, T>(a.B, gx2, gy2, out[1]);
+          integrate<P, T>(a.B, pv, px, py, out[2]);
+        }
+      } else if constexpr (MODE == MODE_RESID || MODE == MODE_DGC || MODE == MODE_DE || MODE == MODE_DP) {
+        // residual F(U) of Problem 2 (phi~ in degradation and u-pressure):
+        //   u rows:   g(phit) sigma(u) : e(psi) + p phit^2 div psi
+        //   phi rows: (1-k) phi S + 2 p phi tr e(u) - (Gc/l)(1 - phi), Gc l grad phi
+        // the parameter derivatives keep the terms linear in Gc, E or p.
+        T gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pv[NQ], px[NQ], py[NQ], tq[NQ];
+        {
+          T u[NL];
+          gather(0, u);
+          interp_g<P, T>(a.B, u, gx1, gy1);
+          gather(1, u);
+          interp_g<P, T>(a.B, u, gx2, gy2);
+          gather(2, u);
+          interp_vg<P, T>(a.B, u, pv, px, py);
+          gather(3, u);
+          interp_v<P, T>(a.B, u, tq);
+        }
+        constexpr T sig = (MODE == MODE_RESID || MODE == MODE_DE) ? T(1) : T(0);
+        const T spr = (MODE == MODE_RESID) ? pr : (MODE == MODE_DP ? T(1) : T(0));
+        const T sgc = (MODE == MODE_RESID) ? Gc : (MODE == MODE_DGC ? T(1) : T(0));
+        const T invE = (MODE == MODE_DE) ? T(1.0 / m.E) : T(1);   // sigma is linear in E at fixed nu
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
+          const T tr = exx + eyy;
+          const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+          const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
+          const T g = (T(1) - kap) * tq[q] * tq[q] + kap;
+          const T ph = pv[q];
+          const T wg = H * wq[q], wv = H * H * wq[q];
+          const T pt2 = spr * tq[q] * tq[q];
+          gx1[q] = wg * (sig * invE * g * sxx + pt2);
+          gy1[q] = wg * (sig * invE * g * sxy);
+          gx2[q] = wg * (sig * invE * g * sxy);
+          gy2[q] = wg * (sig * invE * g * syy + pt2);
+          pv[q] = wv * (sig * invE * (T(1) - kap) * ph * S + spr * T(2) * ph * tr - sgc / ell * (T(1) - ph));
+          px[q] = wq[q] * sgc * ell * px[q];
+          py[q] = wq[q] * sgc * ell * py[q];
+        }
+        integrate_g<P, T>(a.B, gx1, gy1, out[0]);
+        integrate_g<P, T>(a.B, gx2, gy2, out[1]);
+        integrate<P, T>(a.B, pv, px, py, out[2]);
+      } else if constexpr (MODE == MODE_TCVGRAD) {
+        // TCV = int u . grad phi; derivative: (v . grad phi) for u, (u . grad psi) for phi
+        T vx[NQ], vy[NQ], px[NQ], py[NQ], zero[NQ];
+        {
+          T u[NL], d1[NQ], d2[NQ];
+          gather(0, u);
+          interp_v<P, T>(a.B, u, vx);
+          gather(1, u);
+          interp_v<P, T>(a.B, u, vy);
+          gather(2, u);
+          interp_g<P, T>(a.B, u, px, py);
+          (void)d1;
+          (void)d2;
+        }
+        T f0[NQ], f1[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          zero[q] = T(0);
+          const T wv = H * H * wq[q], wg = H * wq[q];
+          f0[q] = wv * px[q] * invH;
+          f1[q] = wv * py[q] * invH;
+          px[q] = wg * vx[q];
+          py[q] = wg * vy[q];
+        }
+        integrate<P, T>(a.B, f0, zero, zero, out[0]);
+        integrate<P, T>(a.B, f1, zero, zero, out[1]);
+        integrate<P, T>(a.B, zero, px, py, out[2]);
+      } else if constexpr (MODE == MODE_MASS) {
+        T f[NQ], zero[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          f[q] = H * H * wq[q];
+          zero[q] = T(0);
+        }
+        integrate<P, T>(a.B, f, zero, zero, out[2]);
+      }
+      if (hang && MODE != MODE_DIAG_LEAF) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) hang_apply_T<P, T>(a.B, out[c], info);
+      }
+    }
+    for (int col = 0; col < ncol; ++col) {
+      __syncthreads();
+      if (live && color == col) {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+          const int l = loc[k];
+          if (l < no) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c * MO + l] += out[c][k];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // 4. epilogue over owned nodes
+  for (int l = threadIdx.x; l < no; l += blockDim.x) {
+    const int64_t g = o0 + l;
+    const uint8_t f = a.flags[g];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T v = acc[c * MO + l];
+      const int64_t i = c * n + g;
+      if constexpr (MODE == MODE_J || MODE == MODE_JT) {
+        const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
+        a.dst[i] = cons ? a.src[i] : v;
+      } else if constexpr (MODE == MODE_LEVEL) {
+        if constexpr (EPI == EPI_PLAIN) {
+          a.dst[i] = v;
+        } else if constexpr (EPI == EPI_RESID) {
+          a.dst[i] = a.b[i] - v;
+        } else {
+          const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
+          const int blk = c < 2 ? 0 : 1;
+          const T x = a.src[i];
+          if (fixed) {
+            a.dst[i] = T(0);
+            a.xnew[i] = x;
+          } else {
+            const T r = a.b[i] - v;
+            const T dp = a.dold ? a.dold[i] : T(0);
+            const T dn = a.c1[blk] * dp + a.c2[blk] * a.dinv[i] * r;
+            a.dst[i] = dn;
+            a.xnew[i] = x + dn;
+          }
+        }
+      } else if constexpr (MODE == MODE_RESID) {
+        a.dst[i] = (f & NODE_HANGING) ? T(0) : -v;
+      } else if constexpr (MODE == MODE_DIAG_LEAF) {
+        const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
+        a.dst[i] = cons ? T(1) : T(1) / v;
+      } else if constexpr (MODE == MODE_DIAG_LEVEL) {
+        const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
+        a.dst[i] = fixed ? T(0) : T(1) / v;
+      } else {
+        a.dst[i] = (f & NODE_HANGING) ? T(0) : v;
+      }
+    }
+  }
+}
+
+}  // namespace pff

@@ -1,0 +1,325 @@
+// Elementwise, transfer and reduction kernels of the solver. Grid-stride
+// loops over nodes; reductions are two-stage with a fixed summation order so
+// that results repeat bit for bit for a given size.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "mesh.hpp"
+
+namespace pff {
+
+constexpr int RED_BLOCKS = 512;
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ bool leaf_constrained(uint8_t f, int c) {
+  return c < 2 ? (f & (NODE_DIRICHLET | NODE_HANGING)) != 0 : (f & (NODE_ACTIVE | NODE_HANGING)) != 0;
+}
+__device__ __forceinline__ bool level_fixed(uint8_t f, int c) {
+  return c < 2 ? (f & (NODE_DIRICHLET | NODE_EDGE)) != 0 : (f & (NODE_ACTIVE | NODE_EDGE)) != 0;
+}
+
+#define GRID_LOOP(i, N) for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < (N); i += int64_t(gridDim.x) * blockDim.x)
+
+// hanging entries from their masters (Sec. 3.2: hanging-node constraints)
+template <typename T>
+__global__ void k_distribute(T* v, int64_t n, int ncomp, const Hanging* h, int nh, int np1) {
+  GRID_LOOP(i, int64_t(nh) * ncomp) {
+    const int c = int(i / nh);
+    const Hanging& hg = h[i % nh];
+    T s = T(0);
+    for (int k = 0; k < np1; ++k) s += T(hg.weight[k]) * v[c * n + hg.master[k]];
+    v[c * n + hg.node] = s;
+  }
+}
+
+// identity on hanging rows: out = in
+__global__ void k_copy_hanging(double* out, const double* in, int64_t n, const Hanging* h, int nh) {
+  GRID_LOOP(i, int64_t(nh) * 3) {
+    const int c = int(i / nh);
+    const int64_t g = h[i % nh].node;
+    out[c * n + g] = in[c * n + g];
+  }
+}
+
+// active flags from a caller's byte array (hanging unknowns never active)
+__global__ void k_set_active(uint8_t* flags, const uint8_t* active, int64_t n) {
+  GRID_LOOP(i, n) {
+    uint8_t f = flags[i] & uint8_t(~NODE_ACTIVE);
+    if (active[i] && !(f & NODE_HANGING)) f |= NODE_ACTIVE;
+    flags[i] = f;
+  }
+}
+
+// Active-set rule of Alg. 2 with c_i = 2 |lambda_i / (phi_i - phi_old_i)|
+// (c_i * 0 := 0), lambda = R_phi / B.
+__global__ void k_active_rule(uint8_t* flags, const double* R, const double* mass, const double* phi,
+                              const double* phio, int64_t n) {
+  GRID_LOOP(i, n) {
+    uint8_t f = flags[i] & uint8_t(~NODE_ACTIVE);
+    if (!(f & NODE_HANGING)) {
+      const double lam = R[2 * n + i] / mass[i];
+      const double diff = phi[i] - phio[i];
+      const double c = diff != 0.0 ? 2.0 * fabs(lam / diff) : 0.0;
+      const double val = lam + c * diff;
+      if (val > 0.0) f |= NODE_ACTIVE;
+    }
+    flags[i] = f;
+  }
+}
+
+__global__ void k_get_active(uint8_t* out, const uint8_t* flags, int64_t n) {
+  GRID_LOOP(i, n) out[i] = (flags[i] & NODE_ACTIVE) ? 1 : 0;
+}
+
+// per-block partial counts of active entries and of entries that differ
+// from `prev` (part[2 * blk], part[2 * blk + 1]); reduced by k_reduce_final
+__global__ void __launch_bounds__(RED_THREADS) k_count_partial(const uint8_t* flags, const uint8_t* prev,
+                                                                 int64_t n, double* part) {
+  __shared__ double sa[RED_THREADS], sc[RED_THREADS];
+  double a = 0.0, c = 0.0;
+  GRID_LOOP(i, n) {
+    const bool act = (flags[i] & NODE_ACTIVE) != 0;
+    a += act ? 1.0 : 0.0;
+    if (prev) c += (act != (prev[i] != 0)) ? 1.0 : 0.0;
+  }
+  sa[threadIdx.x] = a;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+      sc[threadIdx.x] += sc[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sa[0];
+    part[2 * blockIdx.x + 1] = sc[0];
+  }
+}
+
+// U_c: phase field set to phi_old on the active set
+__global__ void k_apply_active(double* U, const double* phio, const uint8_t* flags, int64_t n) {
+  GRID_LOOP(i, n) if (flags[i] & NODE_ACTIVE) U[2 * n + i] = phio[i];
+}
+
+// zero constrained rows of a leaf vector
+__global__ void k_mask_leaf(double* v, const uint8_t* flags, int64_t n) {
+  GRID_LOOP(i, 3 * n) {
+    const int c = int(i / n);
+    if (leaf_constrained(flags[i % n], c)) v[i] = 0.0;
+  }
+}
+
+// level state injection: (u_x, u_y, phit) at the coinciding leaf position
+template <typename T>
+__global__ void k_inject(T* st, int64_t nl, const int32_t* leaf_index, const double* U, const double* phit,
+                         int64_t n) {
+  GRID_LOOP(i, nl) {
+    const int64_t g = leaf_index[i];
+    st[i] = T(U[g]);
+    st[nl + i] = T(U[n + g]);
+    st[2 * nl + i] = T(phit[g]);
+  }
+}
+
+// Level active set (Sec. 3.2): the leaf flag on nodes of level leaf cells, or
+// any active fine node reached through the prolongation stencil.
+__global__ void k_level_active(uint8_t* fl, int64_t nl, const int32_t* leaf_index, const uint8_t* leaf_flags,
+                               const int64_t* PT_ptr, const int32_t* PT_col, const uint8_t* fine_flags) {
+  GRID_LOOP(i, nl) {
+    uint8_t f = fl[i] & uint8_t(~NODE_ACTIVE);
+    bool act = (f & NODE_LEAFCELL) && (leaf_flags[leaf_index[i]] & NODE_ACTIVE);
+    if (PT_ptr && !act)
+      for (int64_t e = PT_ptr[i]; e < PT_ptr[i + 1]; ++e)
+        if (fine_flags[PT_col[e]] & NODE_ACTIVE) { act = true; break; }
+    if (act) f |= NODE_ACTIVE;
+    fl[i] = f;
+  }
+}
+
+// leaf -> level: every free non-hanging leaf unknown goes to the coarsest
+// level whose leaf cells own it (the level nodes flagged NODE_COPY)
+template <typename T>
+__global__ void k_copy_to_level(T* d, int64_t nl, const uint8_t* fl, const int32_t* leaf_index,
+                                const double* b, const uint8_t* leaf_flags, int64_t n) {
+  GRID_LOOP(i, 3 * nl) {
+    const int c = int(i / nl);
+    const int64_t k = i % nl;
+    T v = T(0);
+    if (fl[k] & NODE_COPY) {
+      const int64_t g = leaf_index[k];
+      if (!leaf_constrained(leaf_flags[g], c)) v = T(b[c * n + g]);
+    }
+    d[i] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_copy_from_level(double* out, const T* x, int64_t nl, const uint8_t* fl,
+                                  const int32_t* leaf_index, const double* b, const uint8_t* leaf_flags,
+                                  int64_t n) {
+  GRID_LOOP(i, 3 * nl) {
+    const int c = int(i / nl);
+    const int64_t k = i % nl;
+    if (fl[k] & NODE_COPY) {
+      const int64_t g = leaf_index[k];
+      out[c * n + g] = leaf_constrained(leaf_flags[g], c) ? b[c * n + g] : double(x[i]);
+    }
+  }
+}
+
+// x_f += P x_c (rows of P: fine nodes)
+template <typename T>
+__global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, const int64_t* ptr,
+                              const int32_t* col, const T* val) {
+  GRID_LOOP(i, nf) {
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+      const T w = val[e];
+      const int64_t j = col[e];
+      s0 += w * xc[j];
+      s1 += w * xc[nc + j];
+      s2 += w * xc[2 * nc + j];
+    }
+    xf[i] += s0;
+    xf[nf + i] += s1;
+    xf[2 * nf + i] += s2;
+  }
+}
+
+// d_c += P^T t_f (rows of P^T: coarse nodes)
+template <typename T>
+__global__ void k_restrict_add(T* dc, const T* tf, int64_t nc, int64_t nf, const int64_t* ptr,
+                               const int32_t* col, const T* val) {
+  GRID_LOOP(i, nc) {
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+      const T w = val[e];
+      const int64_t j = col[e];
+      s0 += w * tf[j];
+      s1 += w * tf[nf + j];
+      s2 += w * tf[2 * nf + j];
+    }
+    dc[i] += s0;
+    dc[nc + i] += s1;
+    dc[2 * nc + i] += s2;
+  }
+}
+
+// first Chebyshev update from x0 = 0: d = dinv b / theta, x = d
+template <typename T>
+__global__ void k_cheb_first(T* x, T* d, const T* b, const T* dinv, int64_t nl, T c2u, T c2p) {
+  GRID_LOOP(i, 3 * nl) {
+    const T c2 = (i < 2 * nl) ? c2u : c2p;
+    const T v = c2 * dinv[i] * b[i];
+    d[i] = v;
+    x[i] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_fill(T* v, T val, int64_t len) {
+  GRID_LOOP(i, len) v[i] = val;
+}
+
+template <typename TO, typename TI>
+__global__ void k_cast(TO* o, const TI* in, int64_t len) {
+  GRID_LOOP(i, len) o[i] = TO(in[i]);
+}
+
+// y = a x + y
+__global__ void k_axpy(double* y, const double* x, double a, int64_t len) {
+  GRID_LOOP(i, len) y[i] += a * x[i];
+}
+// y = x + a z
+__global__ void k_waxpy(double* y, const double* x, const double* z, double a, int64_t len) {
+  GRID_LOOP(i, len) y[i] = x[i] + a * z[i];
+}
+__global__ void k_scale(double* y, const double* x, double a, int64_t len) {
+  GRID_LOOP(i, len) y[i] = a * x[i];
+}
+__global__ void k_sub(double* y, const double* a, const double* b, int64_t len) {
+  GRID_LOOP(i, len) y[i] = a[i] - b[i];
+}
+// w -= sum_j h_j V_j (V: k vectors of length len, contiguous)
+__global__ void k_mcombine(double* w, const double* V, const double* h, int k, int64_t len, double sign) {
+  GRID_LOOP(i, len) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += h[j] * V[int64_t(j) * len + i];
+    w[i] += sign * s;
+  }
+}
+
+// CG helpers for the eigenvalue estimate: r = 1 on free unknowns
+// (inverse diagonal nonzero exactly there); z = a * b; r -= alpha q on free
+// unknowns and z = dinv r
+__global__ void k_free_ones(double* r, const double* dinv, int64_t len) {
+  GRID_LOOP(i, len) r[i] = dinv[i] != 0.0 ? 1.0 : 0.0;
+}
+__global__ void k_mul(double* z, const double* a, const double* b, int64_t len) {
+  GRID_LOOP(i, len) z[i] = a[i] * b[i];
+}
+__global__ void k_cg_update(double* r, double* z, const double* q, const double* dinv, double alpha, int64_t len) {
+  GRID_LOOP(i, len) {
+    if (dinv[i] != 0.0) r[i] -= alpha * q[i];
+    z[i] = dinv[i] * r[i];
+  }
+}
+
+// stage 1 of a dot product: one partial per block, fixed order
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) k_dot_partial(const T* a, const T* b, int64_t len, double* part) {
+  __shared__ double sh[RED_THREADS];
+  double s = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x)
+    s += double(a[i]) * double(b[i]);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// multi-dot: part[blk * k + j] = partial of V_j . w
+__global__ void __launch_bounds__(RED_THREADS) k_mdot_partial(const double* V, const double* w, int k,
+                                                                int64_t len, double* part) {
+  __shared__ double sh[RED_THREADS];
+  for (int j = 0; j < k; ++j) {
+    double s = 0.0;
+    const double* v = V + int64_t(j) * len;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x)
+      s += v[i] * w[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int ww = blockDim.x / 2; ww > 0; ww >>= 1) {
+      if (threadIdx.x < ww) sh[threadIdx.x] += sh[threadIdx.x + ww];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x * k + j] = sh[0];
+    __syncthreads();
+  }
+}
+
+// stage 2: out[j] = sum over nb blocks of part[blk * k + j]
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double* part, int nb, int k, double* out) {
+  __shared__ double sh[RED_THREADS];
+  for (int j = 0; j < k; ++j) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i * k + j];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = sh[0];
+    __syncthreads();
+  }
+}
+
+}  // namespace pff

@@ -1,0 +1,102 @@
+"""Shared set-up for GPU parity tests: one library context and one oracle
+problem on the same mesh, parameters and seeded inputs, with the map between
+the two node numberings taken from the integer lattice coordinates."""
+from __future__ import annotations
+
+import numpy as np
+
+import inputs
+from oracle.assemble import LeafProblem, Params
+from oracle.mesh import Mesh
+
+
+def torch_cuda():
+    import torch
+    return torch
+
+
+class Case:
+    """Library solver + oracle problem for one mesh / degree / state recipe."""
+
+    def __init__(self, n_base, n_local, p, coarse=16, band=(2.0, 0.5), seed=0, u_std=1e-4,
+                 mask="bernoulli", prm=None, solver_params=None, tile=(0, 0), build_oracle=True):
+        import torch
+        from paper_2404_03265_amd import PhaseFieldSolver, SolverParams
+        self.torch = torch
+        finest = 20.0 / (n_base * 2 ** n_local)
+        ell = 2.0 * np.sqrt(2.0) * finest
+        self.prm = prm or Params(E=1.0, nu=0.2, Gc=1.0, pressure=1e-3, kappa=1e-10, ell=ell)
+        sp_ = solver_params or SolverParams()
+        for k in ("E", "nu", "Gc", "pressure", "kappa", "ell"):
+            setattr(sp_, k, getattr(self.prm, k))
+        self.sp = sp_
+        self.g = PhaseFieldSolver(n_base, n_local, p, coarse=coarse, band=band, tile=tile, params=sp_)
+        X, Y = self.g.coords()
+        self.X, self.Y, self.M = X, Y, self.g.M
+        self.n = self.g.n
+        n = self.n
+        flags = self.g.flags()
+        dirichlet = (flags & 1) != 0
+        ux, uy, phi = inputs.sneddon_state(X, Y, self.M, seed=seed, u_std=u_std)
+        ux = np.where(dirichlet, 0.0, ux)
+        uy = np.where(dirichlet, 0.0, uy)
+        self.U_raw = np.concatenate([ux, uy, phi])
+        self.phi_old_raw = phi.copy()
+        self.phit_raw = phi.copy()
+        self.mask_kind = mask
+        if mask == "bernoulli":
+            self.active = inputs.bernoulli_mask(X, Y, 2, 0.1) & ((flags & 2) == 0)
+        else:
+            self.active = None
+        self.om = None
+        if build_oracle:
+            self.build_oracle(n_base, n_local, p, coarse, band)
+
+    def build_oracle(self, n_base, n_local, p, coarse, band):
+        self.om = Mesh(n_base, n_local, p, coarse=coarse, band=band)
+        om = self.om
+        assert om.n_nodes == self.n
+        key_o = om.NY.astype(np.int64) * (om.M + 1) + om.NX
+        key_g = self.Y.astype(np.int64) * (self.M + 1) + self.X
+        pos = {int(k): i for i, k in enumerate(key_o)}
+        self.g2o = np.array([pos[int(k)] for k in key_g])          # library node -> oracle node
+        self.o2g = np.empty_like(self.g2o)
+        self.o2g[self.g2o] = np.arange(self.n)
+        self.lp = LeafProblem(om, self.prm)
+        self.U_o = self.lp.distribute(self.to_o(self.U_raw))
+        self.phit_o = self.lp.distribute(self.to_o(self.phit_raw))
+        self.phio_o = self.lp.distribute(self.to_o(self.phi_old_raw))
+        if self.active is not None:
+            self.active_o = self.active[self.o2g]
+        else:
+            from oracle.newton import active_set
+            R = self.lp.residual(self.U_o, self.phit_o)
+            self.active_o = active_set(self.lp, R, self.U_o[2 * self.n:], self.phio_o)
+
+    # vectors: library order <-> oracle order (blocked, ncomp components)
+    def to_o(self, v):
+        v = np.asarray(v)
+        k = v.size // self.n
+        return np.concatenate([v[c * self.n:(c + 1) * self.n][self.o2g] for c in range(k)])
+
+    def to_g(self, v):
+        v = np.asarray(v)
+        k = v.size // self.n
+        return np.concatenate([v[c * self.n:(c + 1) * self.n][self.g2o] for c in range(k)])
+
+    def dev(self, a, dtype=None):
+        t = self.torch
+        return t.tensor(np.ascontiguousarray(a), dtype=dtype or t.float64, device="cuda")
+
+    def load_state(self, setup_mg=False):
+        t = self.torch
+        act = None if self.active is None else self.dev(self.active.astype(np.uint8), t.uint8)
+        self.g.set_state(self.dev(self.U_raw), self.dev(self.phi_old_raw), self.dev(self.phit_raw),
+                         act, setup_mg=setup_mg)
+        t.cuda.synchronize()
+
+
+def rel_err(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))

@@ -1,0 +1,129 @@
+"""GPU parity of the leaf operators against the FP64 oracle (element by
+element on the same seeded inputs): vmult, vmult_T, inverse diagonal,
+residual, crack volume and parameter derivatives.
+
+Tolerance: the operators are sums of O(10-100) products per entry in FP64;
+different summation orders give relative deviations of a few 1e-16 times the
+condition of the sums, so 1e-12 of the largest entry is the bar."""
+import numpy as np
+import pytest
+
+import inputs
+from tests.gpu_common import Case, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+MESHES = {
+    # 4x4 coarse grid, 16x16 base, two local levels in |x|<3, |y|<1: hanging nodes on both sides
+    "tiny": dict(n_base=16, n_local=2, coarse=4, band=(3.0, 1.0)),
+    # 32x32 base from the 16x16 coarse grid, two local levels in the Sneddon band
+    "small": dict(n_base=32, n_local=2, coarse=16, band=(2.0, 0.5)),
+}
+
+_cases = {}
+
+
+def case(name, p, mask="bernoulli"):
+    key = (name, p, mask)
+    if key not in _cases:
+        m = MESHES[name]
+        print(f"[case] {key}", flush=True)
+        c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask=mask,
+                 u_std=1e-2)
+        c.load_state()
+        _cases[key] = c
+    return _cases[key]
+
+
+PARAMS = [(n, p, mk) for n in MESHES for p in (1, 2) for mk in ("bernoulli", "rule")]
+
+
+@pytest.mark.parametrize("name,p,mask", PARAMS)
+def test_active_set_matches_rule(name, p, mask):
+    c = case(name, p, mask)
+    act = c.g.active().cpu().numpy().astype(bool)
+    if mask == "bernoulli":
+        assert np.array_equal(act, c.active)
+    else:
+        # the rule is a sign decision on lambda = R/B; both sides decide in FP64
+        # from residuals that differ by rounding only
+        ref = c.active_o[c.g2o]
+        diff = np.flatnonzero(act != ref)
+        R = c.lp.residual(c.U_o, c.phit_o)[2 * c.n:]
+        scale = np.abs(R).max()
+        assert np.all(np.abs(R[c.g2o][diff]) <= 1e-12 * scale), diff
+
+
+@pytest.mark.parametrize("name,p,mask", PARAMS)
+def test_vmult_matches_oracle(name, p, mask):
+    c = case(name, p, mask)
+    act_o = c.g.active().cpu().numpy().astype(bool)[c.o2g]
+    J = c.lp.masked_operator(c.U_o, c.phit_o, act_o)
+    src = inputs.random_vector(c.X, c.Y, 1)
+    dst = c.g.vmult(c.dev(src)).cpu().numpy()
+    ref = c.to_g(J @ c.to_o(src))
+    for b in range(3):
+        sl = slice(b * c.n, (b + 1) * c.n)
+        assert rel_err(dst[sl], ref[sl]) <= TOL, (b, rel_err(dst[sl], ref[sl]))
+    # deterministic: a second application is bitwise identical
+    dst2 = c.g.vmult(c.dev(src)).cpu().numpy()
+    assert np.array_equal(dst, dst2)
+
+
+@pytest.mark.parametrize("name,p", [(n, p) for n in MESHES for p in (1, 2)])
+def test_vmult_transpose_matches_oracle(name, p):
+    c = case(name, p)
+    J = c.lp.masked_operator(c.U_o, c.phit_o, c.active_o)
+    batch = 3
+    srcs = [inputs.random_vector(c.X, c.Y, 100 + i) for i in range(batch)]
+    out = c.g.vmult_T(c.dev(np.concatenate(srcs)), batch=batch).cpu().numpy()
+    for i in range(batch):
+        ref = c.to_g(J.T @ c.to_o(srcs[i]))
+        got = out[i * 3 * c.n:(i + 1) * 3 * c.n]
+        assert rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("name,p", [(n, p) for n in MESHES for p in (1, 2)])
+def test_inverse_diagonal_matches_oracle(name, p):
+    c = case(name, p)
+    J = c.lp.masked_operator(c.U_o, c.phit_o, c.active_o)
+    ref = c.to_g(1.0 / J.diagonal())
+    got = c.g.inverse_diagonal(-1).cpu().numpy()
+    assert rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("name,p", [(n, p) for n in MESHES for p in (1, 2)])
+def test_residual_matches_oracle(name, p):
+    c = case(name, p)
+    U = c.dev(c.to_g(c.U_o))
+    R = c.g.residual(U).cpu().numpy()
+    Ro = c.lp.residual(c.U_o, c.phit_o)
+    hang = c.om.hanging
+    Ro = Ro * np.concatenate([~hang] * 3)
+    ref = c.to_g(Ro)
+    assert rel_err(R, ref) <= TOL
+    Rm = c.g.residual(U, masked=True).cpu().numpy()
+    refm = c.to_g(Ro * c.lp.free_mask(c.active_o))
+    assert rel_err(Rm, refm) <= TOL
+
+
+@pytest.mark.parametrize("name,p", [(n, p) for n in MESHES for p in (1, 2)])
+def test_tcv_and_parameter_derivatives(name, p):
+    c = case(name, p)
+    U = c.dev(c.to_g(c.U_o))
+    tcv, g = c.g.tcv(U, grad=True)
+    ref = c.lp.tcv(c.U_o)
+    assert abs(tcv - ref) <= TOL * max(abs(ref), 1e-300) * 10
+    gref = c.to_g(c.lp.tcv_gradient(c.U_o) * np.concatenate([~c.om.hanging] * 3))
+    assert rel_err(g.cpu().numpy(), gref) <= TOL
+    z = inputs.random_vector(c.X, c.Y, 55)
+    out = c.g.param_grad(c.dev(z))
+    free = c.lp.free_mask(c.active_o)
+    d = c.lp.param_derivatives(c.U_o, c.phit_o)
+    zo = c.to_o(z) * free
+    for i, k in enumerate(("Gc", "E", "p")):
+        r = zo @ (d[k] * free)
+        scale = np.abs(zo).sum() * np.abs(d[k]).max()
+        assert abs(out[i] - r) <= 1e-13 * scale, (k, out[i], r)
