@@ -1,0 +1,259 @@
+"""Benchmark: matrix-free phase-field Jacobian on one MI355X.
+
+Workload (default): Sneddon-type mesh, 1024 x 1024 base cells + 3 local
+refinement levels in the band |x| < 2, |y| < 0.5, Q2 (20.5 M unknowns), FP64.
+
+Reported (one JSON line on stdout):
+  value        GDoF/s of the leaf Jacobian vmult (N_dof / time per call, HIP
+               events on the launch stream, inputs resident in HBM)
+  ms_per_step  one Newton / primal-dual active set iteration (residual, active
+               set, multigrid setup, GMRES with the block V-cycle, line search)
+               in FP64, timed over --steps steps after --warmup steps
+  newton_s     FP64 and mixed-precision (FP32 V-cycle) Newton step times
+  roofline     algorithmic bytes of one vmult / its duration vs 8 TB/s HBM
+  cpu_baseline the FP64 oracle (assembled Jacobian, one SpMV) on a bounded
+               sample mesh of the same family, on the host cores
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vmult_traffic.json")
+KERNEL_SOURCES = ["paper_2404_03265_amd/csrc/tile_kernel.hpp", "paper_2404_03265_amd/csrc/cell.hpp",
+                  "paper_2404_03265_amd/csrc/mesh.cpp"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(n_nodes: int, n_cells: int, degree: int) -> int:
+    """Bytes one vmult must move: src and dst (3 comps, 8 B each), the state
+    (u_x, u_y, phi, phit: 4 x 8 B per node) and an int32 dof map per cell."""
+    return 16 * 3 * n_nodes + 32 * n_nodes + 4 * (degree + 1) ** 2 * n_cells
+
+
+def make_state(g, spec, seed=0, random=True):
+    import numpy as np
+    import torch
+
+    import inputs
+    X, Y = g.coords()
+    fl = g.flags()
+    ux, uy, phi = inputs.sneddon_state(X, Y, g.M, seed=seed, random=random)
+    d = (fl & 1) != 0
+    U = np.concatenate([np.where(d, 0.0, ux), np.where(d, 0.0, uy), phi])
+    return (torch.tensor(U, device="cuda"), torch.tensor(phi, device="cuda"), X, Y)
+
+
+def time_calls(fn, reps, warm=5):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps   # ms
+
+
+def cpu_baseline(sample_base=256, sample_local=3, degree=2):
+    """The oracle as it stands: assemble the masked Jacobian, apply it once."""
+    import numpy as np
+
+    import inputs
+    from oracle.assemble import LeafProblem, Params
+    from oracle.mesh import Mesh
+    spec = inputs.WorkloadSpec(name="sample", n_base=sample_base, n_local=sample_local, degree=degree)
+    m = Mesh(sample_base, sample_local, degree)
+    lp = LeafProblem(m, Params(E=spec.E, nu=spec.nu, Gc=spec.Gc, pressure=spec.pressure,
+                               kappa=spec.kappa, ell=spec.ell))
+    ux, uy, phi = inputs.sneddon_state(m.NX, m.NY, m.M, seed=0)
+    U = lp.distribute(np.concatenate([ux, uy, phi]))
+    act = inputs.bernoulli_mask(m.NX, m.NY, 2, 0.1) & ~m.hanging
+    src = inputs.random_vector(m.NX, m.NY, 1)
+    t0 = time.perf_counter()
+    J = lp.masked_operator(U, phi, act)
+    t1 = time.perf_counter()
+    y = J @ src
+    t2 = time.perf_counter()
+    n_dof = 3 * m.n_nodes
+    threads = 1
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        threads = max([1] + [i.get("num_threads", 1) for i in info])
+    except Exception:
+        pass
+    return {
+        "value": n_dof / (t2 - t0) / 1e9,
+        "unit": "GDoF/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"sneddon {sample_base}x{sample_base} + {sample_local} local levels, Q{degree}, "
+                   f"{n_dof} unknowns: assemble masked Jacobian ({t1 - t0:.2f} s) + one CSR SpMV "
+                   f"({(t2 - t1) * 1e3:.1f} ms); SpMV alone {n_dof / (t2 - t1) / 1e9:.3f} GDoF/s"),
+        "host_cpus": os.cpu_count(),
+        "_check": float(abs(y).sum()),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sneddon_1024x1024_L3_Q2")
+    ap.add_argument("--vmult-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-newton", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_2404_03265_amd import PhaseFieldSolver, SolverParams
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    spec = inputs.WORKLOADS[args.workload]
+    sp_ = SolverParams(E=spec.E, nu=spec.nu, Gc=spec.Gc, pressure=spec.pressure, kappa=spec.kappa,
+                       ell=spec.ell)
+    t0 = time.time()
+    g = PhaseFieldSolver(spec.n_base, spec.n_local, spec.degree, params=sp_)
+    n_tiles, n_rec, _ = g.tile_stats()
+    log(f"{spec.name}: {3 * g.n} unknowns, {g.n_levels} levels, {n_tiles} tiles, "
+        f"built in {time.time() - t0:.1f}s")
+    n_dof = 3 * g.n
+
+    # ---- vmult at a random state, active set from the rule ----------------
+    U, phi, X, Y = make_state(g, spec, random=True)
+    g.set_state(U, phi, phi, None, setup_mg=False)
+    src = torch.tensor(inputs.random_vector(X, Y, 1), device="cuda")
+    dst = torch.empty_like(src)
+    ms_vmult = time_calls(lambda: g.vmult(src, dst), args.vmult_reps)
+    gdofs = n_dof / (ms_vmult * 1e-3) / 1e9
+    n_cells_leaf = leaf_cell_count(spec)
+    algo = algorithmic_bytes(g.n, n_cells_leaf, spec.degree)
+    achieved = algo / (ms_vmult * 1e-3) / 1e9
+    log(f"vmult {ms_vmult * 1e3:.1f} us -> {gdofs:.2f} GDoF/s, {achieved:.0f} GB/s algorithmic")
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == spec.name:
+            traffic = tr.get("bytes_per_launch")
+
+    # ---- V-cycle and Newton steps --------------------------------------------
+    extra = {}
+    ms_step = None
+    if not args.no_newton:
+        U0, phi0, _, _ = make_state(g, spec, random=False)
+        act = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+        Uw = U0.clone()
+        newton = {}
+        its = {}
+        for mode in ("fp64", "mixed"):
+            sp_.vcycle_fp32 = 1 if mode == "mixed" else 0
+            g.set_params(sp_)
+            infos = []
+
+            def step():
+                Uw.copy_(U0)
+                act.zero_()
+                info, rc = g.newton_step(Uw, phi0, phi0, act)
+                infos.append(info)
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            infos.clear()
+            t_a = time.perf_counter()
+            for _ in range(args.steps):
+                step()
+            torch.cuda.synchronize()
+            t_b = time.perf_counter()
+            newton[mode] = (t_b - t_a) / args.steps
+            its[mode] = infos[-1]["gmres_iterations"]
+            log(f"newton {mode}: {newton[mode] * 1e3:.1f} ms/step, gmres its {its[mode]}, "
+                f"setup {infos[-1]['setup_seconds'] * 1e3:.1f} ms, solve {infos[-1]['solve_seconds'] * 1e3:.1f} ms")
+            if mode == "fp64":
+                ms_step = newton[mode] * 1e3
+                r_fp64 = infos[-1]["residual_after"]
+            else:
+                r_mixed = infos[-1]["residual_after"]
+        # V-cycle times at the state left by the last step
+        vsrc = torch.tensor(inputs.random_vector(X, Y, 3), device="cuda")
+        vdst = torch.empty_like(vsrc)
+        vc = {}
+        for mode, fp32 in (("fp64", 0), ("fp32", 1)):
+            vc[mode] = time_calls(lambda: g.vcycle(vsrc, fp32=bool(fp32), out=vdst), 5, warm=2)
+        extra = {
+            "newton_s": {"fp64": newton["fp64"], "mixed": newton["mixed"]},
+            "gmres_iterations": its,
+            "newton_residual_after": {"fp64": r_fp64, "mixed": r_mixed},
+            "vcycle_ms": vc,
+        }
+    if ms_step is None:
+        ms_step = ms_vmult
+
+    out = {
+        "metric": "GDoF/s of matrix-free Jacobian vmult",
+        "value": gdofs,
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "unknowns": n_dof, "degree": spec.degree,
+                   "step": "one Newton/PDAS iteration: residual, active set, MG setup, "
+                           "GMRES(30) with block V-cycle, line search"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "tile_kernel<P=2, double, MODE_J> (leaf vmult, regular + hanging tiles)",
+                     "algorithmic_bytes": algo, "vmult_us": ms_vmult * 1e3},
+    }
+    out.update(extra)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cb = cpu_baseline()
+        cb.pop("_check", None)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+def leaf_cell_count(spec) -> int:
+    """Leaf cells of the mesh (host mesh builder, no GPU needed)."""
+    import paper_2404_03265_amd.meshinfo as mi
+    return mi.HostMesh(spec.n_base, spec.n_local, spec.degree).leaf_cells()
+
+
+if __name__ == "__main__":
+    main()

@@ -25,6 +25,8 @@ int pff_mesh_free(pff_mesh* m);
 /* n_nodes: leaf nodes; n_levels; level_nodes (n_levels entries, nullable);
  * M: lattice units across the domain (x = -10 + 20 X / M). */
 int pff_mesh_sizes(const pff_mesh* m, int64_t* n_nodes, int32_t* n_levels, int64_t* level_nodes, int64_t* M);
+/* Number of leaf cells. */
+int pff_mesh_leaf_cells(const pff_mesh* m, int64_t* n_cells);
 /* xy: 2 n int32 (all X, then all Y) of the leaf (level = -1) or a level. */
 int pff_mesh_coords(const pff_mesh* m, int32_t level, int32_t* xy);
 /* flags: n bytes, bits as in pff_node_flags (active bits are never set here). */

@@ -268,6 +268,29 @@ class LeafProblem:
         Jc = self.C3.T @ J @ self.C3
         return (Mf @ Jc @ Mf + sp.diags(1.0 - f)).tocsr()
 
+    def masked_rows(self, rows, src, U, phit, active):
+        """Selected rows of J~ src (blocked dof indices), assembling only the
+        cells that touch those rows (directly or through a hanging node whose
+        masters include the row's node). For spot checks on large meshes."""
+        n = self.n
+        mesh = self.mesh
+        rows = np.asarray(rows)
+        nodes = np.unique(rows % n)
+        need = set(int(k) for k in nodes)
+        for h, lst in mesh.hanging_constraints.items():
+            if any(m in need for m, _ in lst):
+                need.add(int(h))
+        need = np.array(sorted(need))
+        sel = np.isin(mesh.cell_nodes, need).any(axis=1)
+        cs = CellSet(self.el, self.cells.H[sel], self.cells.nodes[sel])
+        g = cs.gather
+        Ke = element_jacobian(cs, self.prm, g(U[:n]), g(U[n:2 * n]), g(U[2 * n:]), g(phit))
+        J = assemble_matrix(cs.nodes, n, Ke)
+        f = self.free_mask(active)
+        x = self.C3 @ (src * f)
+        y = (self.C3.T @ (J @ x))[rows]
+        return np.where(f[rows], y, src[rows])
+
     # crack volume (Sec. 4) and its derivative
     def tcv(self, U):
         n = self.n

@@ -74,6 +74,7 @@ _SIGS = {
     "pff_mesh_free": (C.c_int, [VP]),
     "pff_mesh_sizes": (C.c_int, [VP, C.POINTER(C.c_int64), C.POINTER(C.c_int32), VP,
                                  C.POINTER(C.c_int64)]),
+    "pff_mesh_leaf_cells": (C.c_int, [VP, C.POINTER(C.c_int64)]),
     "pff_mesh_coords": (C.c_int, [VP, C.c_int32, VP]),
     "pff_mesh_flags": (C.c_int, [VP, C.c_int32, VP]),
     "pff_mesh_hanging": (C.c_int, [VP, C.POINTER(C.c_int64), VP, VP, VP]),

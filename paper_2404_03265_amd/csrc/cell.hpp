@@ -188,57 +188,63 @@ __device__ __forceinline__ void integrate_g(const Basis<T>& B, const T (&fx)[(P 
 // coarse face's nodes; interpolate them to the fine face positions (forward)
 // or distribute fine-face contributions back to the coarse nodes (transpose).
 // Corner slots are fixed points of both faces' maps, so faces commute.
-template <int P, typename T>
-__device__ __forceinline__ void hang_face(const Basis<T>& B, T (&u)[(P + 1) * (P + 1)], int start,
-                                          int stride, int sub) {
-  constexpr int N = P + 1;
+// FACE: 0 left (a = 0), 1 right (a = P), 2 bottom (b = 0), 3 top (b = P);
+// all slot indices are compile-time so the local arrays stay in registers.
+template <int P, int FACE>
+struct FaceSlots {
+  static constexpr int N = P + 1;
+  static constexpr int start = FACE == 0 ? 0 : FACE == 1 ? P : FACE == 2 ? 0 : P * N;
+  static constexpr int stride = FACE < 2 ? N : 1;
+};
+
+template <int P, int FACE, typename T>
+__device__ __forceinline__ void hang_face(const Basis<T>& B, T (&u)[(P + 1) * (P + 1)], int sub) {
+  constexpr int N = P + 1, S0 = FaceSlots<P, FACE>::start, ST = FaceSlots<P, FACE>::stride;
   T c[N];
 #pragma unroll
-  for (int k = 0; k < N; ++k) c[k] = u[start + k * stride];
+  for (int k = 0; k < N; ++k) c[k] = u[S0 + k * ST];
 #pragma unroll
   for (int t = 0; t < N; ++t) {
     T s = T(0);
 #pragma unroll
-    for (int k = 0; k < N; ++k) s += B.hang[sub][t][k] * c[k];
-    u[start + t * stride] = s;
+    for (int k = 0; k < N; ++k) s += (sub ? B.hang[1][t][k] : B.hang[0][t][k]) * c[k];
+    u[S0 + t * ST] = s;
   }
 }
 
-template <int P, typename T>
-__device__ __forceinline__ void hang_face_T(const Basis<T>& B, T (&u)[(P + 1) * (P + 1)], int start,
-                                            int stride, int sub) {
-  constexpr int N = P + 1;
+template <int P, int FACE, typename T>
+__device__ __forceinline__ void hang_face_T(const Basis<T>& B, T (&u)[(P + 1) * (P + 1)], int sub) {
+  constexpr int N = P + 1, S0 = FaceSlots<P, FACE>::start, ST = FaceSlots<P, FACE>::stride;
   T f[N];
 #pragma unroll
-  for (int t = 0; t < N; ++t) f[t] = u[start + t * stride];
+  for (int t = 0; t < N; ++t) f[t] = u[S0 + t * ST];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     T s = T(0);
 #pragma unroll
-    for (int t = 0; t < N; ++t) s += B.hang[sub][t][k] * f[t];
-    u[start + k * stride] = s;
+    for (int t = 0; t < N; ++t) s += (sub ? B.hang[1][t][k] : B.hang[0][t][k]) * f[t];
+    u[S0 + k * ST] = s;
   }
 }
 
-// info bits: 0..3 hanging faces (L, R, B, T), 4 cx, 5 cy
+// info bits: 0..3 hanging faces (L, R, B, T), 4 cx, 5 cy. Vertical faces
+// are halves of the coarse face selected by cy, horizontal ones by cx.
 template <int P, typename T>
 __device__ __forceinline__ void hang_apply(const Basis<T>& B, T (&u)[(P + 1) * (P + 1)], unsigned info) {
-  constexpr int N = P + 1;
   const int cx = (info >> 4) & 1, cy = (info >> 5) & 1;
-  if (info & 1u) hang_face<P, T>(B, u, 0, N, cy);
-  if (info & 2u) hang_face<P, T>(B, u, P, N, cy);
-  if (info & 4u) hang_face<P, T>(B, u, 0, 1, cx);
-  if (info & 8u) hang_face<P, T>(B, u, P * N, 1, cx);
+  if (info & 1u) hang_face<P, 0, T>(B, u, cy);
+  if (info & 2u) hang_face<P, 1, T>(B, u, cy);
+  if (info & 4u) hang_face<P, 2, T>(B, u, cx);
+  if (info & 8u) hang_face<P, 3, T>(B, u, cx);
 }
 
 template <int P, typename T>
 __device__ __forceinline__ void hang_apply_T(const Basis<T>& B, T (&u)[(P + 1) * (P + 1)], unsigned info) {
-  constexpr int N = P + 1;
   const int cx = (info >> 4) & 1, cy = (info >> 5) & 1;
-  if (info & 1u) hang_face_T<P, T>(B, u, 0, N, cy);
-  if (info & 2u) hang_face_T<P, T>(B, u, P, N, cy);
-  if (info & 4u) hang_face_T<P, T>(B, u, 0, 1, cx);
-  if (info & 8u) hang_face_T<P, T>(B, u, P * N, 1, cx);
+  if (info & 1u) hang_face_T<P, 0, T>(B, u, cy);
+  if (info & 2u) hang_face_T<P, 1, T>(B, u, cy);
+  if (info & 4u) hang_face_T<P, 2, T>(B, u, cx);
+  if (info & 8u) hang_face_T<P, 3, T>(B, u, cx);
 }
 
 }  // namespace pff

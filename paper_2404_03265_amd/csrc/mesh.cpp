@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <numeric>
+#include <stdexcept>
 #include <unordered_map>
 #include <unordered_set>
 
@@ -150,11 +151,29 @@ void build_tiles(int p, int n_tiles, const std::vector<int32_t>& fp,
                                      (uint16_t(col) << CELL_COLOR_SHIFT)));
     }
     ti[TILE_NCOLOR] = ncol;
+    if (ncol > 16) throw std::runtime_error("more than 16 colours in a tile");
     T.max_cells = std::max<int>(T.max_cells, int(cl.size()));
     T.max_owned = std::max<int>(T.max_owned, no);
     T.max_local = std::max<int>(T.max_local, no + int(halo_tmp.size()));
   }
   T.n_cell_records = int64_t(T.cell_info.size());
+  T.order.clear();
+  std::vector<int32_t> hang_tiles;
+  for (int t = 0; t < n_tiles; ++t) {
+    const int32_t* ti = &T.tile_info[size_t(t) * 8];
+    bool h = false;
+    for (int c = 0; c < ti[TILE_NCELL]; ++c)
+      if (T.cell_info[size_t(ti[TILE_CELL0]) + c] & 15u) h = true;
+    (h ? hang_tiles : T.order).push_back(t);
+  }
+  T.n_regular = int(T.order.size());
+  T.order.insert(T.order.end(), hang_tiles.begin(), hang_tiles.end());
+  std::vector<int32_t> counts(n_tiles);
+  for (int t = 0; t < n_tiles; ++t) counts[t] = T.tile_info[size_t(t) * 8 + TILE_NCELL];
+  if (n_tiles > 0) {
+    std::nth_element(counts.begin(), counts.begin() + n_tiles / 2, counts.end());
+    T.typ_cells = counts[n_tiles / 2];
+  }
 }
 
 }  // namespace

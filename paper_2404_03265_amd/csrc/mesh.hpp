@@ -40,6 +40,9 @@ struct TileSet {
   int max_cells = 0;        // largest cell count of a tile
   int max_local = 0;        // largest local node count of a tile
   int max_owned = 0;
+  int typ_cells = 0;        // median cell count of a tile
+  int n_regular = 0;        // tiles without hanging-face cells (listed first in `order`)
+  std::vector<int32_t> order;       // tile ids: regular tiles, then tiles with hanging cells
   std::vector<int32_t> tile_info;   // 8 ints per tile, see TILE_* below
   std::vector<int32_t> halo;        // global node ids of halo nodes, per tile
   std::vector<uint16_t> cell_loc;   // (p+1)^2 local node ids per cell record

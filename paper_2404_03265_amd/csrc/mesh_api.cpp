@@ -60,6 +60,12 @@ int pff_mesh_sizes(const pff_mesh* m, int64_t* n_nodes, int32_t* n_levels, int64
   return PFF_OK;
 }
 
+int pff_mesh_leaf_cells(const pff_mesh* m, int64_t* n_cells) {
+  if (!m || !n_cells) return PFF_E_ARG;
+  *n_cells = m->m.n_leaf_cells;
+  return PFF_OK;
+}
+
 int pff_mesh_coords(const pff_mesh* m, int32_t level, int32_t* xy) {
   if (bad_level(m, level) || !xy) return PFF_E_ARG;
   const auto& X = level < 0 ? m->m.NX : m->m.levels[level].NX;

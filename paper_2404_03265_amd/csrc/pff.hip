@@ -29,11 +29,13 @@ namespace {
   } while (0)
 
 struct DevTiles {
+  int32_t* order = nullptr;
+  int n_regular = 0;
   int32_t* info = nullptr;
   int32_t* halo = nullptr;
   uint16_t* loc = nullptr;
   uint16_t* cinfo = nullptr;
-  int n_tiles = 0, max_local = 0, max_owned = 0, max_cells = 0;
+  int n_tiles = 0, max_local = 0, max_owned = 0, max_cells = 0, typ_cells = 0;
   int64_t n_rec = 0;
 };
 
@@ -122,6 +124,8 @@ T* upload(const std::vector<T>& v) {
 DevTiles upload_tiles(const TileSet& t) {
   DevTiles d;
   d.info = upload(t.tile_info);
+  d.order = upload(t.order);
+  d.n_regular = t.n_regular;
   d.halo = upload(t.halo);
   d.loc = upload(t.cell_loc);
   d.cinfo = upload(t.cell_info);
@@ -129,6 +133,7 @@ DevTiles upload_tiles(const TileSet& t) {
   d.max_local = t.max_local;
   d.max_owned = t.max_owned;
   d.max_cells = t.max_cells;
+  d.typ_cells = t.typ_cells;
   d.n_rec = t.n_cell_records;
   return d;
 }
@@ -189,18 +194,31 @@ struct pff_ctx {
     a.n = nn;
     a.max_local = t.max_local;
     a.max_owned = t.max_owned;
-    for (int l = 0; l < 16; ++l) a.H[l] = T(l < int(mesh.level_H.size()) ? mesh.level_H[l] : 1.0);
+    a.H0 = T(mesh.level_H[0]);
     a.B = make_basis<T>(p);
     a.mat = mat();
     using TR = ModeTraits<MODE>;
     constexpr int NF = TR::n_src + TR::n_state;
     const size_t lds = size_t((NF > 0 ? NF : 1) * t.max_local + 3 * t.max_owned) * sizeof(T);
-    int threads = ((std::min(t.max_cells, 256) + 63) / 64) * 64;
+    // one thread per cell of a typical tile; larger tiles loop over their cells
+    int threads = ((std::min(std::max(t.typ_cells, 1), 256) + 63) / 64) * 64;
     threads = std::max(64, threads);
-    if (p == 1)
-      hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI>), dim3(t.n_tiles), dim3(threads), lds, s, a);
-    else
-      hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI>), dim3(t.n_tiles), dim3(threads), lds, s, a);
+    a.tile_order = t.order;
+    const int nreg = t.n_regular, nhang = t.n_tiles - t.n_regular;
+    if (nreg > 0) {
+      a.tile_base = 0;
+      if (p == 1)
+        hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI, false>), dim3(nreg), dim3(threads), lds, s, a);
+      else
+        hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI, false>), dim3(nreg), dim3(threads), lds, s, a);
+    }
+    if (nhang > 0) {
+      a.tile_base = nreg;
+      if (p == 1)
+        hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI, true>), dim3(nhang), dim3(threads), lds, s, a);
+      else
+        hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI, true>), dim3(nhang), dim3(threads), lds, s, a);
+    }
     HIPCHK(hipGetLastError());
   }
 
@@ -740,7 +758,7 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
 int pff_destroy(pff_ctx* c) {
   if (!c) return PFF_E_ARG;
   auto f = [](void* p) { if (p) hipFree(p); };
-  auto ft = [&](DevTiles& t) { f(t.info); f(t.halo); f(t.loc); f(t.cinfo); };
+  auto ft = [&](DevTiles& t) { f(t.order); f(t.info); f(t.halo); f(t.loc); f(t.cinfo); };
   ft(c->tiles);
   f(c->flags);
   f(c->hang);

@@ -38,6 +38,8 @@ enum Epi : int { EPI_PLAIN = 0, EPI_RESID = 1, EPI_CHEB = 2 };
 
 template <typename T>
 struct TileArgs {
+  const int32_t* tile_order;   // tile ids; this launch handles tile_order[tile_base + blockIdx.x]
+  int tile_base;
   const int32_t* tile_info;
   const int32_t* halo;
   const uint16_t* cell_loc;
@@ -46,7 +48,7 @@ struct TileArgs {
   int64_t n;
   int max_local;
   int max_owned;
-  T H[16];
+  T H0;             // cell edge on level 0; level l has H0 / 2^l
   Basis<T> B;
   Material mat;
   const T* src;      // 3n input (operand / state U)
@@ -75,7 +77,7 @@ struct ModeTraits {
   static constexpr bool mask_src = (MODE == MODE_J || MODE == MODE_JT || MODE == MODE_LEVEL);
 };
 
-template <int P, typename T, int MODE, int EPI>
+template <int P, typename T, int MODE, int EPI, bool HANG>
 __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
   using TR = ModeTraits<MODE>;
@@ -86,7 +88,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   T* acc = lds + (NF > 0 ? NF : 1) * ML;   // [3][max_owned]
   const int MO = a.max_owned;
 
-  const int tile = blockIdx.x;
+  const int tile = a.tile_order[a.tile_base + blockIdx.x];
   const int32_t* ti = a.tile_info + 8 * tile;
   const int o0 = ti[TILE_OWNED0], no = ti[TILE_NOWNED];
   const int h0 = ti[TILE_HALO0], nh = ti[TILE_NHALO];
@@ -140,8 +142,9 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       info = a.cell_info[rec];
       color = int((info >> CELL_COLOR_SHIFT) & 15u);
       const int lev = int((info >> CELL_LEVEL_SHIFT) & 31u);
-      const T H = a.H[lev];
-      const bool hang = TR::leaf && (info & 15u);
+      const T H = T(ldexp(double(a.H0), -lev));
+      // tiles without hanging-face cells run the HANG = false instantiation
+      const bool hang = HANG && TR::leaf && (info & 15u);
       auto gather = [&](int field, T(&u)[NL]) {
 #pragma unroll
         for (int k = 0; k < NL; ++k) u[k] = lds[field * ML + loc[k]];
@@ -154,11 +157,143 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         for (int qx = 0; qx < N1; ++qx) wq[qy * N1 + qx] = a.B.w[qx] * a.B.w[qy];
       const T invH = T(1) / H;
 
-      if constexpr (MODE == MODE_J || MODE == MODE_JT || MODE == MODE_LEVEL || MODE == MODE_DIAG_LEAF ||
-                    MODE == MODE_DIAG_LEVEL) {
+      if constexpr (MODE == MODE_J) {
+        // Jacobian (Sec. 3.1), ordered to keep few arrays live:
+        //   u rows:   g(phit) sigma(du) : grad psi
+        //   phi rows: c1 dphi + B : e(du) (value), Gc l grad dphi (gradient)
+        //   c1 = (1-k) S(u) + 2 p tr e(u) + Gc/l, B = 2(1-k) phi sigma(u) + 2 p phi I
+        T c1[NQ], bxx[NQ], byy[NQ], bxy[NQ];
+        {
+          T u[NL], sx1[NQ], sy1[NQ], sx2[NQ], sy2[NQ];
+          gather(3, u);
+          interp_g<P, T>(a.B, u, sx1, sy1);
+          gather(4, u);
+          interp_g<P, T>(a.B, u, sx2, sy2);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const T exx = sx1[q] * invH, eyy = sy2[q] * invH, exy = T(0.5) * (sy1[q] + sx2[q]) * invH;
+            const T tr = exx + eyy;
+            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+            const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
+            c1[q] = (T(1) - kap) * S + T(2) * pr * tr + Gc / ell;
+            bxx[q] = sxx;
+            byy[q] = syy;
+            bxy[q] = sxy;
+          }
+        }
+        {
+          T u[NL], pq[NQ];
+          gather(5, u);
+          interp_v<P, T>(a.B, u, pq);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const T f = T(2) * (T(1) - kap) * pq[q], t = T(2) * pr * pq[q];
+            bxx[q] = f * bxx[q] + t;
+            byy[q] = f * byy[q] + t;
+            bxy[q] = f * bxy[q];
+          }
+        }
+        T dxx[NQ], dxy[NQ], dyx[NQ], dyy[NQ], be[NQ];
+        {
+          T u[NL];
+          gather(0, u);
+          interp_g<P, T>(a.B, u, dxx, dxy);
+          gather(1, u);
+          interp_g<P, T>(a.B, u, dyx, dyy);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const T exx = dxx[q] * invH, eyy = dyy[q] * invH, exy = T(0.5) * (dxy[q] + dyx[q]) * invH;
+            be[q] = bxx[q] * exx + byy[q] * eyy + T(2) * bxy[q] * exy;
+          }
+        }
+        {
+          T u[NL], tq[NQ];
+          gather(6, u);
+          interp_v<P, T>(a.B, u, tq);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const T wg = H * wq[q] * ((T(1) - kap) * tq[q] * tq[q] + kap);
+            const T exx = dxx[q] * invH, eyy = dyy[q] * invH, exy = T(0.5) * (dxy[q] + dyx[q]) * invH;
+            const T tr = exx + eyy;
+            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+            dxx[q] = wg * sxx;
+            dxy[q] = wg * sxy;
+            dyx[q] = wg * sxy;
+            dyy[q] = wg * syy;
+          }
+        }
+        integrate_g<P, T>(a.B, dxx, dxy, out[0]);
+        integrate_g<P, T>(a.B, dyx, dyy, out[1]);
+        {
+          T u[NL], pv[NQ], px[NQ], py[NQ];
+          gather(2, u);
+          interp_vg<P, T>(a.B, u, pv, px, py);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            pv[q] = H * H * wq[q] * (c1[q] * pv[q] + be[q]);
+            px[q] = wq[q] * Gc * ell * px[q];
+            py[q] = wq[q] * Gc * ell * py[q];
+          }
+          integrate<P, T>(a.B, pv, px, py, out[2]);
+        }
+      } else if constexpr (MODE == MODE_LEVEL) {
+        // level block operator diag(G_uu, G_phiphi) (Sec. 3.2): the J rows
+        // without the coupling B : e(du); state (u_x, u_y, phit) injected
+        T c1[NQ], gq[NQ];
+        {
+          T u[NL], sx1[NQ], sy1[NQ], sx2[NQ], sy2[NQ];
+          gather(3, u);
+          interp_g<P, T>(a.B, u, sx1, sy1);
+          gather(4, u);
+          interp_g<P, T>(a.B, u, sx2, sy2);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const T exx = sx1[q] * invH, eyy = sy2[q] * invH, exy = T(0.5) * (sy1[q] + sx2[q]) * invH;
+            const T tr = exx + eyy;
+            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+            const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
+            c1[q] = (T(1) - kap) * S + T(2) * pr * tr + Gc / ell;
+          }
+          gather(5, u);
+          interp_v<P, T>(a.B, u, gq);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) gq[q] = H * wq[q] * ((T(1) - kap) * gq[q] * gq[q] + kap);
+        }
+        {
+          T u[NL], dxx[NQ], dxy[NQ], dyx[NQ], dyy[NQ];
+          gather(0, u);
+          interp_g<P, T>(a.B, u, dxx, dxy);
+          gather(1, u);
+          interp_g<P, T>(a.B, u, dyx, dyy);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const T exx = dxx[q] * invH, eyy = dyy[q] * invH, exy = T(0.5) * (dxy[q] + dyx[q]) * invH;
+            const T tr = exx + eyy;
+            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+            dxx[q] = gq[q] * sxx;
+            dxy[q] = gq[q] * sxy;
+            dyx[q] = gq[q] * sxy;
+            dyy[q] = gq[q] * syy;
+          }
+          integrate_g<P, T>(a.B, dxx, dxy, out[0]);
+          integrate_g<P, T>(a.B, dyx, dyy, out[1]);
+        }
+        {
+          T u[NL], pv[NQ], px[NQ], py[NQ];
+          gather(2, u);
+          interp_vg<P, T>(a.B, u, pv, px, py);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            pv[q] = H * H * wq[q] * c1[q] * pv[q];
+            px[q] = wq[q] * Gc * ell * px[q];
+            py[q] = wq[q] * Gc * ell * py[q];
+          }
+          integrate<P, T>(a.B, pv, px, py, out[2]);
+        }
+      } else if constexpr (MODE == MODE_JT || MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
         // state-derived coefficients at the Gauss points:
         //   g = (1-k) phit^2 + k, c1 = (1-k) S + 2 p tr e(u) + Gc/l,
-        //   Bt = 2 (1-k) phi sigma(u) + 2 p phi I (coupling, leaf only)
+        //   B = 2 (1-k) phi sigma(u) + 2 p phi I (coupling, leaf only)
         constexpr int SU = TR::n_src;
         T cg[NQ], cc1[NQ], bxx[NQ], byy[NQ], bxy[NQ];
         {
@@ -217,6 +352,8 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
             out[2][k] = dph;
           }
         } else {
+          // transpose of the Jacobian: the coupling moves to the u rows,
+          //   u rows: g sigma(s_u) : grad psi + s_phi B : grad psi
           T gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pv[NQ], px[NQ], py[NQ];
           {
             T u[NL];
@@ -232,24 +369,13 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
             const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
             const T tr = exx + eyy;
             const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
-            const T wg = H * wq[q];       // gradient tests: JxW / H
-            const T wv = H * H * wq[q];   // value tests: JxW
+            const T wg = H * wq[q];
             const T gq = cg[q];
-            T fxu = gq * sxx, fyu = gq * sxy, fxv = gq * sxy, fyv = gq * syy;
-            T val = cc1[q] * pv[q];
-            if constexpr (MODE == MODE_J) {
-              val += bxx[q] * exx + byy[q] * eyy + T(2) * bxy[q] * exy;
-            } else if constexpr (MODE == MODE_JT) {
-              fxu += pv[q] * bxx[q];
-              fyu += pv[q] * bxy[q];
-              fxv += pv[q] * bxy[q];
-              fyv += pv[q] * byy[q];
-            }
-            gx1[q] = wg * fxu;
-            gy1[q] = wg * fyu;
-            gx2[q] = wg * fxv;
-            gy2[q] = wg * fyv;
-            pv[q] = wv * val;
+            gx1[q] = wg * (gq * sxx + pv[q] * bxx[q]);
+            gy1[q] = wg * (gq * sxy + pv[q] * bxy[q]);
+            gx2[q] = wg * (gq * sxy + pv[q] * bxy[q]);
+            gy2[q] = wg * (gq * syy + pv[q] * byy[q]);
+            pv[q] = H * H * wq[q] * cc1[q] * pv[q];
             px[q] = wq[q] * Gc * ell * px[q];
             py[q] = wq[q] * Gc * ell * py[q];
           }

@@ -38,6 +38,11 @@ class HostMesh:
     def _nn(self, level):
         return self.n if level < 0 else self.level_nodes[level]
 
+    def leaf_cells(self):
+        c = C.c_int64()
+        assert self.lib.pff_mesh_leaf_cells(self.h, C.byref(c)) == 0
+        return c.value
+
     def coords(self, level=-1):
         xy = np.zeros(2 * self._nn(level), dtype=np.int32)
         assert self.lib.pff_mesh_coords(self.h, level, _np(xy)) == 0

@@ -1,0 +1,194 @@
+"""GPU parity of the multigrid preconditioner, GMRES and the Newton / active
+set step against the FP64 oracle, plus the FP32 V-cycle error bound."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import inputs
+from oracle.mg import Hierarchy, MGParams, VCycle, cg_eigs
+from oracle.newton import NewtonParams, newton_step
+from tests.gpu_common import Case, rel_err
+
+pytestmark = pytest.mark.gpu
+
+MESHES = {
+    "tiny": dict(n_base=16, n_local=2, coarse=4, band=(3.0, 1.0)),
+    "small": dict(n_base=32, n_local=2, coarse=16, band=(2.0, 0.5)),
+}
+_cases = {}
+
+
+def mg_case(name, p, mask="bernoulli", cheb=3, coarse_its=30):
+    key = (name, p, mask, cheb, coarse_its)
+    if key not in _cases:
+        from paper_2404_03265_amd import SolverParams
+        m = MESHES[name]
+        print(f"[case] {key}", flush=True)
+        sp_ = SolverParams(cheb_degree=cheb, coarse_its=coarse_its)
+        c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask=mask,
+                 u_std=1e-2, solver_params=sp_)
+        c.load_state(setup_mg=True)
+        c.hier = Hierarchy(c.om)
+        mgp = MGParams(cheb_degree=cheb, coarse_its=coarse_its)
+        lam_max, lam_min0 = c.g.get_eigen()
+        c.vc = VCycle(c.hier, c.prm, mgp, c.U_o, c.phit_o, c.active_o,
+                      eigen=([lam_max[l] for l in range(c.g.n_levels)], lam_min0))
+        c.mgp = mgp
+        _cases[key] = c
+    return _cases[key]
+
+
+def level_map(c, l):
+    """library level-l node -> oracle level-l node"""
+    lv = c.hier.levels[l]
+    X, Y = c.g.coords(l)
+    pos = {(int(x), int(y)): i for i, (x, y) in enumerate(zip(lv.NX, lv.NY))}
+    return np.array([pos[(int(x), int(y))] for x, y in zip(X, Y)])
+
+
+CASES = [(n, p) for n in MESHES for p in (1, 2)]
+
+
+@pytest.mark.parametrize("name,p", CASES)
+def test_level_active_sets_and_inverse_diagonals(name, p):
+    c = mg_case(name, p)
+    for l in range(c.g.n_levels):
+        mp = level_map(c, l)
+        f = c.g.flags(l)
+        assert np.array_equal((f & 4) != 0, c.vc.ops[l].extra["active"][mp])
+        nl = c.hier.levels[l].n
+        got = c.g.inverse_diagonal(l).cpu().numpy()
+        ref = c.vc.ops[l].Dinv
+        ref_g = np.concatenate([ref[k * nl:(k + 1) * nl][mp] for k in range(3)])
+        assert rel_err(got, ref_g) <= 1e-12, l
+
+
+@pytest.mark.parametrize("name,p", CASES)
+def test_eigenvalue_estimates(name, p):
+    """CG-Lanczos estimates of D^{-1} A per level and block (Sec. 3.2)."""
+    c = mg_case(name, p)
+    lam_max, lam_min0 = c.g.get_eigen()
+    n = c.hier.levels
+    for l, op in enumerate(c.vc.ops):
+        nl = n[l].n
+        bu = np.zeros(3 * nl, bool)
+        bu[:2 * nl] = True
+        its = c.mgp.coarse_eig_its if l == 0 else c.mgp.eig_cg_its
+        for b, blk in enumerate((bu, ~bu)):
+            lo, hi = cg_eigs(op.A, op.Dinv, op.free & blk, its)
+            assert abs(lam_max[l, b] - hi) <= 1e-9 * hi, (l, b, lam_max[l, b], hi)
+            if l == 0:
+                assert abs(lam_min0[b] - lo) <= 1e-9 * hi
+
+
+@pytest.mark.parametrize("name,p", CASES)
+def test_vcycle_fp64_matches_oracle(name, p):
+    c = mg_case(name, p)
+    src = inputs.random_vector(c.X, c.Y, 3)
+    got = c.g.vcycle(c.dev(src)).cpu().numpy()
+    ref = c.to_g(c.vc.apply(c.to_o(src)))
+    assert rel_err(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("name,p", CASES)
+def test_vcycle_fp32_error_bound(name, p):
+    """Mixed precision: the whole V-cycle in FP32 stays within 1e-5 (relative,
+    largest entry) of the FP64 oracle V-cycle."""
+    c = mg_case(name, p)
+    src = inputs.random_vector(c.X, c.Y, 4)
+    got = c.g.vcycle(c.dev(src), fp32=True).cpu().numpy()
+    ref = c.to_g(c.vc.apply(c.to_o(src)))
+    err = rel_err(got, ref)
+    print(f"fp32 vcycle rel err {err:.2e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("name,p", CASES)
+def test_vcycle_degree4_and_short_coarse(name, p):
+    c = mg_case(name, p, cheb=4, coarse_its=8)
+    src = inputs.random_vector(c.X, c.Y, 5)
+    got = c.g.vcycle(c.dev(src)).cpu().numpy()
+    ref = c.to_g(c.vc.apply(c.to_o(src)))
+    assert rel_err(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("name,p", CASES)
+def test_gmres_matches_direct_solve(name, p):
+    c = mg_case(name, p)
+    J = c.lp.masked_operator(c.U_o, c.phit_o, c.active_o)
+    b = inputs.random_vector(c.X, c.Y, 6) * c.to_g(c.lp.free_mask(c.active_o)).astype(float)
+    x, info, rc = c.g.gmres(c.dev(b), tol=1e-13 * np.linalg.norm(b))
+    assert info["converged"] == 1, info
+    xd = c.to_g(spla.spsolve(J.tocsc(), c.to_o(b)))
+    assert np.linalg.norm(x.cpu().numpy() - xd) <= 1e-9 * np.linalg.norm(xd)
+    # transposed system (adjoint solves)
+    xt, info_t, _ = c.g.gmres(c.dev(b), transpose=True, tol=1e-13 * np.linalg.norm(b))
+    xdt = c.to_g(spla.spsolve(J.T.tocsc(), c.to_o(b)))
+    assert info_t["converged"] == 1
+    assert np.linalg.norm(xt.cpu().numpy() - xdt) <= 1e-9 * np.linalg.norm(xdt)
+
+
+@pytest.mark.parametrize("name,p", CASES)
+def test_newton_step_matches_oracle(name, p):
+    """One Alg. 2 iteration from the load-step start (u = 0, phi = 1 off the
+    crack): same active set, same GMRES iteration count within one, and the
+    same update to the GMRES tolerance."""
+    import torch
+    m = MESHES[name]
+    c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="rule")
+    n = c.n
+    ux, uy, phi = inputs.sneddon_state(c.X, c.Y, c.M, random=False)
+    U0 = np.concatenate([ux, uy, phi])
+    Ud = c.dev(U0)
+    ph = c.dev(phi)
+    act = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    info, rc = c.g.newton_step(Ud, ph, ph, act)
+    lam_max, lam_min0 = c.g.get_eigen()
+    Uo0 = c.lp.distribute(c.to_o(U0))
+    pho = c.to_o(phi)
+    hier = Hierarchy(c.om)
+    Un, act_o, oinfo = newton_step(c.lp, hier, MGParams(), NewtonParams(), Uo0, pho, pho,
+                                   np.zeros(n, bool),
+                                   eigen=([lam_max[l] for l in range(c.g.n_levels)], lam_min0))
+    assert np.array_equal(act.cpu().numpy().astype(bool), act_o[c.g2o])
+    assert abs(info["gmres_iterations"] - oinfo.gmres_iterations) <= 1
+    assert info["ls_trials"] == oinfo.ls_trials
+    assert abs(info["residual_before"] - oinfo.residual_before) <= 1e-12 * oinfo.residual_before
+    Ug = Ud.cpu().numpy()
+    ref = c.to_g(Un)
+    assert np.linalg.norm(Ug - ref) <= 1e-6 * np.linalg.norm(ref)
+    assert abs(info["residual_after"] - oinfo.residual_after) <= 1e-6 * oinfo.residual_before + 1e-12
+
+
+def test_full_size_vmult_sampled_rows():
+    """The benchmark workload (1024 x 1024 base cells + 3 local levels, Q2,
+    20.5 M unknowns) in the benchmark's launch configuration: 600 sampled rows
+    (every class of node included) against the oracle row by row."""
+    import time
+    t0 = time.time()
+    c = Case(1024, 3, 2, mask="bernoulli", u_std=1e-4, build_oracle=False)
+    c.load_state()
+    src = inputs.random_vector(c.X, c.Y, 1)
+    dst = c.g.vmult(c.dev(src)).cpu().numpy()
+    print(f"[full] library side done {time.time() - t0:.1f}s", flush=True)
+    c.build_oracle(1024, 3, 2, 16, (2.0, 0.5))
+    print(f"[full] oracle mesh built {time.time() - t0:.1f}s", flush=True)
+    rng = np.random.default_rng(7)
+    n = c.n
+    f = c.g.flags()
+    pick = []
+    for mask in ((f & 2) != 0, (f & 1) != 0, c.active, (f & 7) == 0):
+        idx = np.flatnonzero(mask)
+        pick.extend(rng.choice(idx, size=min(50, idx.size), replace=False).tolist())
+    # masters of sampled hanging nodes, and random nodes
+    for h in [k for k in pick if f[k] & 2][:50]:
+        pick.extend(int(c.o2g[m]) for m, _ in c.om.hanging_constraints[int(c.g2o[h])])
+    pick.extend(rng.choice(n, size=300, replace=False).tolist())
+    pick = np.unique(np.array(pick))
+    rows_g = np.concatenate([pick + k * n for k in range(3)])
+    rows_o = np.concatenate([c.g2o[pick] + k * n for k in range(3)])
+    ref = c.lp.masked_rows(rows_o, c.to_o(src), c.U_o, c.phit_o, c.active_o)
+    got = dst[rows_g]
+    print(f"[full] oracle rows done {time.time() - t0:.1f}s", flush=True)
+    scale = np.abs(dst).max()
+    assert np.abs(got - ref).max() <= 1e-12 * scale
