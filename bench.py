@@ -124,6 +124,9 @@ def main():
     ap.add_argument("--vmult-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="only a few vmults and one plain device copy of the same vector "
+                         "(for hardware counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -154,6 +157,14 @@ def main():
     g.set_state(U, phi, phi, None, setup_mg=False)
     src = torch.tensor(inputs.random_vector(X, Y, 1), device="cuda")
     dst = torch.empty_like(src)
+    if args.profile_pass:
+        for _ in range(3):
+            g.vmult(src, dst)
+        calib = torch.empty_like(src)
+        calib.copy_(src)      # plain copy of 3n doubles: counter calibration
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_pass": spec.name, "copy_bytes": 2 * src.numel() * 8}), flush=True)
+        return
     ms_vmult = time_calls(lambda: g.vmult(src, dst), args.vmult_reps)
     gdofs = n_dof / (ms_vmult * 1e-3) / 1e9
     n_cells_leaf = leaf_cell_count(spec)

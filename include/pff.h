@@ -211,6 +211,9 @@ int pff_param_grad(pff_ctx* ctx, const double* z, double* out, void* stream);
 /* Set hanging entries of a nodal vector with ncomp blocked components from
  * their masters. */
 int pff_distribute(pff_ctx* ctx, double* v, int32_t ncomp, void* stream);
+/* Zero the constrained rows (Dirichlet u, hanging, active phi with the
+ * loaded active set) of a 3n vector in place. */
+int pff_mask_constrained(pff_ctx* ctx, double* v, void* stream);
 /* Deterministic dot product of two device vectors of length len (host out). */
 int pff_dot(pff_ctx* ctx, const double* a, const double* b, int64_t len, double* out, void* stream);
 

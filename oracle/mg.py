@@ -10,7 +10,8 @@ Kanschat): level l consists of all cells of refinement level l and the smoother
 acts only there, with the refinement edge held fixed, so hanging nodes never
 appear on a level. Boundary constraints go to every level unchanged; a level
 unknown of the phase field is inactive only if all fine unknowns it interacts
-with are inactive (Sec. 3.2, last paragraph).
+with are inactive (Sec. 3.2, last paragraph), except on the home level of a
+free leaf unknown (see Hierarchy.level_active).
 
 The two blocks share their level structure, so a level vector holds all three
 components: [u_x | u_y | phi]; the u block is the first two components.
@@ -167,18 +168,26 @@ class Hierarchy:
             self.copy_index[g] = i
 
     def level_active(self, leaf_active):
-        """Level active sets: the leaf flag on nodes of level leaf cells, or'ed
-        with every fine active node reached through the prolongation stencil."""
+        """Level active sets (Sec. 3.2: a level unknown is inactive only if all
+        fine unknowns it interacts with are inactive). Reading: on every level a
+        node is active if the leaf unknown at its position is active or if any
+        finer-level unknown in its prolongation stencil is active, except on the
+        one level where a free leaf unknown is copied to and from (its home):
+        there it keeps its own flag. Without that exception a free unknown next
+        to an active one is frozen on every level that holds it and the
+        V-cycle maps it to zero for every input (a singular preconditioner)."""
         L = len(self.levels) - 1
         leaf_active = np.asarray(leaf_active, dtype=bool) & ~self.mesh.hanging
         acts = [None] * (L + 1)
         for l in range(L, -1, -1):
             lv = self.levels[l]
-            a = np.zeros(lv.n, dtype=bool)
-            a[lv.leafcell_node] = leaf_active[lv.leaf_index[lv.leafcell_node]]
+            own = leaf_active[lv.leaf_index]
+            a = own.copy()
             if l < L:
                 Pabs = abs(self.P[l + 1])
                 a |= (Pabs.T @ acts[l + 1].astype(float)) > 0
+            home = lv.leafcell_node & ~lv.edge
+            a = np.where(home, own, a)
             acts[l] = a
         return acts
 

@@ -219,6 +219,10 @@ class PhaseFieldSolver:
         self._check(self.lib.pff_distribute(self.h, _ptr(v), ncomp, _stream()))
         return v
 
+    def mask_constrained(self, v):
+        self._check(self.lib.pff_mask_constrained(self.h, _ptr(v), _stream()))
+        return v
+
     def dot(self, a, b):
         v = C.c_double()
         self._check(self.lib.pff_dot(self.h, _ptr(a), _ptr(b), a.numel(), C.byref(v), _stream()))

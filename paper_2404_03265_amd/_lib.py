@@ -67,6 +67,7 @@ _SIGS = {
     "pff_tcv": (C.c_int, [VP, VP, C.POINTER(C.c_double), VP, VP]),
     "pff_param_grad": (C.c_int, [VP, VP, VP, VP]),
     "pff_distribute": (C.c_int, [VP, VP, C.c_int32, VP]),
+    "pff_mask_constrained": (C.c_int, [VP, VP, VP]),
     "pff_dot": (C.c_int, [VP, VP, VP, C.c_int64, C.POINTER(C.c_double), VP]),
     "pff_last_error": (C.c_char_p, [VP]),
     # host-only mesh inspection (pff_mesh.h)

@@ -1,0 +1,70 @@
+"""Differentiation forms on top of the C ABI (argument marshalling only):
+
+* JacobianApply: torch.autograd.Function whose forward is pff_vmult and whose
+  backward is pff_vmult_T, so dst = J~ src can sit inside a torch graph.
+* adjoint_tcv_gradient: gradient of the crack volume TCV (Sec. 4) with respect
+  to (Gc, E, p) at a converged state with frozen active set:
+      J~^T z = dTCV/dU (constrained rows zero),  dTCV/dtheta = -z^T dF~/dtheta.
+* TcvOfParams: torch.autograd.Function theta -> TCV(U(theta)) whose forward runs
+  Newton / active set iterations (Alg. 2) and whose backward is the adjoint.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class JacobianApply(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, src, solver):
+        ctx.solver = solver
+        return solver.vmult(src.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad):
+        return ctx.solver.vmult_T(grad.contiguous()), None
+
+
+def solve_load_step(solver, U, phi_old, phi_tilde, active=None, tol=1e-7, max_steps=30):
+    """Alg. 2 loop until the active set repeats and |R~| <= tol. U is updated
+    in place; returns (active, list of per-step info dicts)."""
+    if active is None:
+        active = torch.zeros(solver.n, dtype=torch.uint8, device=U.device)
+    infos = []
+    for _ in range(max_steps):
+        prev = active.clone()
+        info, rc = solver.newton_step(U, phi_old, phi_tilde, active)
+        infos.append(info)
+        if torch.equal(prev, active) and info["residual_before"] <= tol:
+            break
+    return active, infos
+
+
+def adjoint_tcv_gradient(solver, U, phi_old, phi_tilde, active, tol=0.0):
+    """(TCV, dTCV/d(Gc, E, p)) at U with the active set frozen."""
+    solver.set_state(U, phi_old, phi_tilde, active, setup_mg=True)
+    tcv, g = solver.tcv(U, grad=True)
+    solver.mask_constrained(g)
+    z, info, rc = solver.gmres(g, transpose=True, tol=tol)
+    dF = solver.param_grad(z)
+    return tcv, -torch.as_tensor(dF, dtype=torch.float64), z, info
+
+
+class TcvOfParams(torch.autograd.Function):
+    """theta = (Gc, E, p) -> TCV of the converged load step."""
+
+    @staticmethod
+    def forward(ctx, theta, solver, U0, phi_old, phi_tilde, newton_tol=1e-10):
+        p = solver.params
+        p.Gc, p.E, p.pressure = (float(x) for x in theta.detach().cpu())
+        solver.set_params(p)
+        U = U0.clone()
+        active, _ = solve_load_step(solver, U, phi_old, phi_tilde, tol=newton_tol)
+        tcv, grad, _, _ = adjoint_tcv_gradient(solver, U, phi_old, phi_tilde, active)
+        ctx.save_for_backward(grad.to(theta.device))
+        ctx.U = U
+        return theta.new_tensor(tcv)
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return g * grad, None, None, None, None, None

@@ -199,7 +199,8 @@ struct pff_ctx {
     a.mat = mat();
     using TR = ModeTraits<MODE>;
     constexpr int NF = TR::n_src + TR::n_state;
-    const size_t lds = size_t((NF > 0 ? NF : 1) * t.max_local + 3 * t.max_owned) * sizeof(T);
+    const size_t lds = size_t((NF > 0 ? NF : 1) * t.max_local + 3 * t.max_owned) * sizeof(T) +
+                       size_t(t.max_local);   // node flags
     // one thread per cell of a typical tile; larger tiles loop over their cells
     int threads = ((std::min(std::max(t.typ_cells, 1), 256) + 63) / 64) * 64;
     threads = std::max(64, threads);
@@ -1101,6 +1102,16 @@ int pff_distribute(pff_ctx* c, double* v, int32_t ncomp, void* stream) {
   if (c->n_hang)
     hipLaunchKernelGGL((k_distribute<double>), dim3(grid_for(int64_t(ncomp) * c->n_hang)), dim3(256), 0, c->s, v, c->n,
                        ncomp, c->hang, c->n_hang, c->p + 1);
+  HIPCHK(hipGetLastError());
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_mask_constrained(pff_ctx* c, double* v, void* stream) {
+  if (!c || !v) return PFF_E_ARG;
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_mask_leaf, dim3(grid_for(3 * c->n)), dim3(256), 0, c->s, v, c->flags, c->n);
   HIPCHK(hipGetLastError());
   return PFF_OK;
   GUARD_END(c)

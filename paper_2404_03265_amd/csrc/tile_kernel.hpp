@@ -100,24 +100,64 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   const T kap = T(m.kappa), pr = T(m.pressure), Gc = T(m.Gc), ell = T(m.ell);
   const T mu = T(m.mu), lam = T(m.lam);
 
-  // 1. stage local nodes
-  for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
-    const int64_t g = l < no ? int64_t(o0 + l) : int64_t(a.halo[h0 + l - no]);
-    if constexpr (NF > 0) {
-      const uint8_t f = a.flags[g];
-      if constexpr (TR::n_src > 0) {
+  // cell records of the first round are loaded before staging so that their
+  // latency overlaps with the node loads
+  int loc0[NL];
+  unsigned info0 = 0;
+  if (int(threadIdx.x) < nc) {
+    const int64_t rec = int64_t(c0) + threadIdx.x;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          T v = a.src[c * n + g];
-          if constexpr (TR::mask_src) {
-            const bool fixed = (c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
-            if (fixed) v = T(0);
+    for (int k = 0; k < NL; ++k) loc0[k] = a.cell_loc[rec * NL + k];
+    info0 = a.cell_info[rec];
+  }
+
+  // 1. stage local nodes: all global loads of a batch are issued before any
+  //    LDS store (one dependent round trip for halo ids, one for the values)
+  uint8_t* lflag = reinterpret_cast<uint8_t*>(acc + 3 * MO);   // [max_local]
+  constexpr int SLOTS = P == 1 ? 2 : 6;   // ~ local nodes / threads of a typical tile
+  for (int base = 0; base < nloc; base += SLOTS * int(blockDim.x)) {
+    int64_t gs[SLOTS];
+#pragma unroll
+    for (int k = 0; k < SLOTS; ++k) {
+      const int l = base + k * int(blockDim.x) + int(threadIdx.x);
+      gs[k] = l < no ? int64_t(o0 + l) : (l < nloc ? int64_t(a.halo[h0 + l - no]) : int64_t(-1));
+    }
+    uint8_t fs[SLOTS];
+    T vs[SLOTS][NF > 0 ? NF : 1];
+#pragma unroll
+    for (int k = 0; k < SLOTS; ++k) {
+      const int64_t g = gs[k];
+      fs[k] = g >= 0 ? a.flags[g] : uint8_t(0);
+      if constexpr (NF > 0) {
+        if (g >= 0) {
+          if constexpr (TR::n_src > 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vs[k][c] = a.src[c * n + g];
           }
-          lds[c * ML + l] = v;
+#pragma unroll
+          for (int st = 0; st < TR::n_state; ++st) vs[k][TR::n_src + st] = a.st[st][g];
         }
       }
+    }
 #pragma unroll
-      for (int s = 0; s < TR::n_state; ++s) lds[(TR::n_src + s) * ML + l] = a.st[s][g];
+    for (int k = 0; k < SLOTS; ++k) {
+      const int l = base + k * int(blockDim.x) + int(threadIdx.x);
+      if (l < nloc) {
+        lflag[l] = fs[k];
+        if constexpr (NF > 0) {
+#pragma unroll
+          for (int c = 0; c < NF; ++c) {
+            T v = vs[k][c];
+            if constexpr (TR::mask_src) {
+              if (c < 3) {
+                const bool fixed = (c < 2) ? (fs[k] & NODE_DIRICHLET) : (fs[k] & NODE_ACTIVE);
+                if (fixed) v = T(0);
+              }
+            }
+            lds[c * ML + l] = v;
+          }
+        }
+      }
     }
   }
   for (int l = threadIdx.x; l < 3 * MO; l += blockDim.x) acc[l] = T(0);
@@ -136,10 +176,16 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
 #pragma unroll
       for (int k = 0; k < NL; ++k) out[c][k] = T(0);
     if (live) {
-      const int64_t rec = int64_t(c0) + cell;
+      if (base == 0) {
 #pragma unroll
-      for (int k = 0; k < NL; ++k) loc[k] = a.cell_loc[rec * NL + k];
-      info = a.cell_info[rec];
+        for (int k = 0; k < NL; ++k) loc[k] = loc0[k];
+        info = info0;
+      } else {
+        const int64_t rec = int64_t(c0) + cell;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) loc[k] = a.cell_loc[rec * NL + k];
+        info = a.cell_info[rec];
+      }
       color = int((info >> CELL_COLOR_SHIFT) & 15u);
       const int lev = int((info >> CELL_LEVEL_SHIFT) & 31u);
       const T H = T(ldexp(double(a.H0), -lev));
@@ -485,7 +531,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   // 4. epilogue over owned nodes
   for (int l = threadIdx.x; l < no; l += blockDim.x) {
     const int64_t g = o0 + l;
-    const uint8_t f = a.flags[g];
+    const uint8_t f = lflag[l];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const T v = acc[c * MO + l];

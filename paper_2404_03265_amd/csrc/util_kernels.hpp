@@ -125,14 +125,18 @@ __global__ void k_inject(T* st, int64_t nl, const int32_t* leaf_index, const dou
   }
 }
 
-// Level active set (Sec. 3.2): the leaf flag on nodes of level leaf cells, or
-// any active fine node reached through the prolongation stencil.
+// Level active set (Sec. 3.2: inactive only if every fine unknown it
+// interacts with is inactive): active if the leaf unknown at the same
+// position is active or any finer unknown in the prolongation stencil is;
+// on the home level of a leaf unknown (NODE_COPY) only its own flag counts,
+// so that no free leaf unknown is frozen on every level that holds it.
 __global__ void k_level_active(uint8_t* fl, int64_t nl, const int32_t* leaf_index, const uint8_t* leaf_flags,
                                const int64_t* PT_ptr, const int32_t* PT_col, const uint8_t* fine_flags) {
   GRID_LOOP(i, nl) {
     uint8_t f = fl[i] & uint8_t(~NODE_ACTIVE);
-    bool act = (f & NODE_LEAFCELL) && (leaf_flags[leaf_index[i]] & NODE_ACTIVE);
-    if (PT_ptr && !act)
+    const bool own = (leaf_flags[leaf_index[i]] & NODE_ACTIVE) != 0;
+    bool act = own;
+    if (!(f & NODE_COPY) && PT_ptr && !act)
       for (int64_t e = PT_ptr[i]; e < PT_ptr[i + 1]; ++e)
         if (fine_flags[PT_col[e]] & NODE_ACTIVE) { act = true; break; }
     if (act) f |= NODE_ACTIVE;

@@ -1,0 +1,69 @@
+"""The C ABI library loads on a machine without a GPU and exports every entry
+point declared in include/*.h; host-only calls behave as documented."""
+import ctypes as C
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2404_03265_amd", "libpff.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libpff.so not built")
+
+
+def declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        names.update(re.findall(r"^\s*(?:int|const char\*)\s+(pff_\w+)\s*\(", txt, flags=re.M))
+    return sorted(names)
+
+
+def test_headers_declare_the_boundary():
+    names = declared_symbols()
+    for required in ("pff_create", "pff_set_state", "pff_vmult", "pff_vmult_T", "pff_inverse_diagonal",
+                     "pff_vcycle", "pff_gmres_solve", "pff_newton_step"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(LIB)
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_symbol():
+    from paper_2404_03265_amd import _lib
+    assert set(declared_symbols()) <= set(_lib.exported_symbols())
+
+
+def test_host_only_calls():
+    from paper_2404_03265_amd import _lib
+    lib = _lib.load()
+    p = _lib.Params()
+    assert lib.pff_default_params(C.byref(p)) == 0
+    assert p.cheb_degree == 3 and p.gmres_restart == 30 and abs(p.smooth_range - 0.08) < 1e-15
+    # argument errors are reported without touching a device
+    assert lib.pff_default_params(None) < 0
+    assert lib.pff_vmult(None, None, None, None) < 0
+    spec = _lib.MeshSpec(30, 1, 1, 16, 2.0, 0.5, 0, 0)      # 30 is not 16 * 2^k
+    h = C.c_void_p()
+    assert lib.pff_mesh_build(C.byref(spec), C.byref(h)) < 0
+    spec = _lib.MeshSpec(32, 1, 3, 16, 2.0, 0.5, 0, 0)      # degree 3 is not offered
+    assert lib.pff_mesh_build(C.byref(spec), C.byref(h)) < 0
+    spec = _lib.MeshSpec(32, 1, 2, 16, 2.0, 0.5, 0, 0)
+    assert lib.pff_mesh_build(C.byref(spec), C.byref(h)) == 0
+    n = C.c_int64()
+    assert lib.pff_mesh_sizes(h, C.byref(n), None, None, None) == 0 and n.value > 0
+    assert lib.pff_mesh_coords(h, 99, None) < 0
+    assert lib.pff_mesh_free(h) == 0
+
+
+def test_product_path_has_no_cpu_fallback(monkeypatch):
+    """Without the library the binding raises instead of computing on the CPU."""
+    from paper_2404_03265_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError):
+        _lib.load(os.path.join(ROOT, "does_not_exist.so"))

@@ -486,3 +486,32 @@ def test_adjoint_gradient_matches_finite_differences():
         # ~ eps * TCV / (h theta) from the 1e-14 solves
         noise = 1e-8 * abs(lp.tcv(U)) / base[key]
         assert abs(grad[name] - fd) <= 1e-6 * abs(fd) + noise
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_vcycle_nonsingular_with_scattered_active_set(p, tiny_mesh_factory):
+    """With a scattered active set the level sets grow by dilation; every free
+    leaf unknown must stay free on its home level, otherwise the V-cycle maps
+    it to zero for every input. Checked on the dense matrix of P^{-1} (brute
+    force, tiny mesh) and through GMRES against a direct solve."""
+    mesh = tiny_mesh_factory(p)
+    n = mesh.n_nodes
+    prm = Params(ell=0.35, kappa=1e-10, pressure=1e-3)
+    lp = LeafProblem(mesh, prm)
+    U, phit = _state(mesh, lp, u_std=1e-2)
+    act = inputs.bernoulli_mask(mesh.NX, mesh.NY, 2, 0.1) & ~mesh.hanging
+    hier = Hierarchy(mesh)
+    acts = hier.level_active(act)
+    for l, lv in enumerate(hier.levels):
+        home = lv.leafcell_node & ~lv.edge
+        assert np.array_equal(acts[l][home], act[lv.leaf_index[home]])
+    vc = VCycle(hier, prm, MGParams(), U, phit, act)
+    free = np.flatnonzero(lp.free_mask(act))
+    if free.size <= 1500:
+        Pm = np.column_stack([vc.apply(np.eye(3 * n)[:, i])[free] for i in free])
+        assert np.linalg.svd(Pm, compute_uv=False).min() > 1e-6
+    J = lp.masked_operator(U, phit, act)
+    b = inputs.random_vector(mesh.NX, mesh.NY, 6) * lp.free_mask(act)
+    x, info = gmres(lambda v: J @ v, vc.apply, b, 1e-13 * np.linalg.norm(b))
+    xd = spla.spsolve(J.tocsc(), b)
+    assert info.converged and np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
