@@ -20,10 +20,14 @@ V-cycle sequence (all matrices assembled; x_l, d_l are level vectors):
   copy:   d_m[i] = b[g] for each free leaf unknown g, m = coarsest level of
           the leaf cells that own g (g is never on m's refinement edge)
   down:   x_l = Cheb(d_l, x0 = 0) on the free unknowns of level l
-          t_l = d_l - A_l x_l (every row, the refinement edge included)
+          t_l = d_l - A_l x_l on every row (the refinement edge included) except
+          Dirichlet and level-active rows, which are zero
           d_{l-1} += P_l^T t_l
   coarse: x_0 = coarse solve of d_0
-  up:     x_l += P_l x_{l-1}     (edge values of x_l now hold the coarse correction)
+  up:     x_l += P_l x_{l-1}, then zero on Dirichlet and level-active unknowns
+          (edge values of x_l now hold the coarse correction); with the zeroed
+          residual rows above, restriction and prolongation stay transposes of
+          each other, so the cycle stays symmetric
           x_l = Cheb(d_l, x0 = x_l): residual d_l - A_l x_l over free rows,
           only free entries updated
   back:   out[g] = x_m[i] for free leaf unknowns, out = b on constrained ones.
@@ -291,6 +295,9 @@ class VCycle:
             Dinv = np.where(free, 1.0 / np.where(diag != 0, diag, 1.0), 0.0)
             op = LevelOps(A=A, free=free, Dinv=Dinv)
             op.extra["active"] = acts[l]
+            # unknowns held at zero on this level (the edge is not: it carries
+            # the coarse correction)
+            op.extra["held"] = np.concatenate([lv.dirichlet, lv.dirichlet, acts[l]])
             self.ops.append(op)
         self.set_eigen(eigen)
 
@@ -387,11 +394,12 @@ class VCycle:
         x = [None] * (L + 1)
         for l in range(L, 0, -1):
             x[l] = self.chebyshev(l, d[l], None, k)
-            t = d[l] - self.ops[l].A @ x[l]
+            t = np.where(self.ops[l].extra["held"], 0.0, d[l] - self.ops[l].A @ x[l])
             d[l - 1] = d[l - 1] + h.P3[l].T @ t
         x[0] = self.coarse_solve(d[0])
         for l in range(1, L + 1):
             x[l] = x[l] + h.P3[l] @ x[l - 1]
+            x[l] = np.where(self.ops[l].extra["held"], 0.0, x[l])
             x[l] = self.chebyshev(l, d[l], x[l], k)
         out = np.array(b_leaf, dtype=float, copy=True)
         for c in range(3):

@@ -19,6 +19,8 @@ struct Basis {
   T v[3][3];      // v[q][a] = l_a(g_q)
   T d[3][3];      // d[q][a] = l_a'(g_q)
   T w[3];         // Gauss weights on [0, 1]
+  T vw[3][3];     // vw[q][a] = w_q l_a(g_q): weighted tables for integration
+  T dw[3][3];     // dw[q][a] = w_q l_a'(g_q)
   T hang[2][3][3];  // hang[sub][t][k] = l_k((sub + t/P) / 2)
 };
 
@@ -179,6 +181,67 @@ __device__ __forceinline__ void integrate_g(const Basis<T>& B, const T (&fx)[(P 
       T s = T(0);
 #pragma unroll
       for (int qx = 0; qx < N; ++qx) s += B.v[qx][a] * A[b][qx] + B.d[qx][a] * C[b][qx];
+      out[b * N + a] = s;
+    }
+}
+
+// Weighted variants: the Gauss weights sit in the tables (vw, dw), so the
+// point values passed in carry no weight factor.
+template <int P, typename T>
+__device__ __forceinline__ void integrate_w(const Basis<T>& B, const T (&fv)[(P + 1) * (P + 1)],
+                                            const T (&fx)[(P + 1) * (P + 1)],
+                                            const T (&fy)[(P + 1) * (P + 1)], T (&out)[(P + 1) * (P + 1)]) {
+  constexpr int N = P + 1;
+  T A[N][N], C[N][N];
+#pragma unroll
+  for (int b = 0; b < N; ++b)
+#pragma unroll
+    for (int qx = 0; qx < N; ++qx) {
+      T sa = T(0), sc = T(0);
+#pragma unroll
+      for (int qy = 0; qy < N; ++qy) {
+        sa += B.vw[qy][b] * fv[qy * N + qx] + B.dw[qy][b] * fy[qy * N + qx];
+        sc += B.vw[qy][b] * fx[qy * N + qx];
+      }
+      A[b][qx] = sa;
+      C[b][qx] = sc;
+    }
+#pragma unroll
+  for (int b = 0; b < N; ++b)
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      T s = T(0);
+#pragma unroll
+      for (int qx = 0; qx < N; ++qx) s += B.vw[qx][a] * A[b][qx] + B.dw[qx][a] * C[b][qx];
+      out[b * N + a] = s;
+    }
+}
+
+template <int P, typename T>
+__device__ __forceinline__ void integrate_gw(const Basis<T>& B, const T (&fx)[(P + 1) * (P + 1)],
+                                             const T (&fy)[(P + 1) * (P + 1)], T (&out)[(P + 1) * (P + 1)]) {
+  constexpr int N = P + 1;
+  T A[N][N], C[N][N];
+#pragma unroll
+  for (int b = 0; b < N; ++b)
+#pragma unroll
+    for (int qx = 0; qx < N; ++qx) {
+      T sa = T(0), sc = T(0);
+#pragma unroll
+      for (int qy = 0; qy < N; ++qy) {
+        sa += B.dw[qy][b] * fy[qy * N + qx];
+        sc += B.vw[qy][b] * fx[qy * N + qx];
+      }
+      A[b][qx] = sa;
+      C[b][qx] = sc;
+    }
+#pragma unroll
+  for (int b = 0; b < N; ++b)
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      T s = T(0);
+#pragma unroll
+      for (int qx = 0; qx < N; ++qx) s += B.vw[qx][a] * A[b][qx] + B.dw[qx][a] * C[b][qx];
       out[b * N + a] = s;
     }
 }

@@ -98,6 +98,8 @@ Basis<T> make_basis(int p) {
     for (int a = 0; a < N; ++a) {
       B.v[q][a] = T(lag(a, g[q]));
       B.d[q][a] = T(dlag(a, g[q]));
+      B.vw[q][a] = T(w[q] * lag(a, g[q]));
+      B.dw[q][a] = T(w[q] * dlag(a, g[q]));
     }
   }
   for (int sub = 0; sub < 2; ++sub)
@@ -403,7 +405,7 @@ struct pff_ctx {
       LevelWork<T>& w = work<T>(D);
       LevelWork<T>& wc = work<T>(lv[l - 1]);
       hipLaunchKernelGGL((k_prolong_add<T>), dim3(grid_for(D.n)), dim3(256), 0, s, w.x[xi[l]], wc.x[xi[l - 1]], D.n,
-                         lv[l - 1].n, D.P_ptr, D.P_col, w.Pval);
+                         lv[l - 1].n, D.P_ptr, D.P_col, w.Pval, D.flags);
       xi[l] = chebyshev<T>(l, w.d, xi[l], k);
     }
     for (int l = 0; l <= L; ++l) {

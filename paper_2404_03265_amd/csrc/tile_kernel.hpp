@@ -88,7 +88,13 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   T* acc = lds + (NF > 0 ? NF : 1) * ML;   // [3][max_owned]
   const int MO = a.max_owned;
 
-  const int tile = a.tile_order[a.tile_base + blockIdx.x];
+  // XCD-aware order: workgroups go to the 8 XCDs round-robin, so XCD x
+  // receives a contiguous chunk of the tile list and neighbouring tiles (which
+  // share halo nodes) run on the same XCD and hit the same L2.
+  const int nb = int(gridDim.x), bid = int(blockIdx.x);
+  const int xq = nb >> 3, xr = nb & 7, xcd = bid & 7;
+  const int order_idx = xcd * xq + (xcd < xr ? xcd : xr) + (bid >> 3);
+  const int tile = a.tile_order[a.tile_base + order_idx];
   const int32_t* ti = a.tile_info + 8 * tile;
   const int o0 = ti[TILE_OWNED0], no = ti[TILE_NOWNED];
   const int h0 = ti[TILE_HALO0], nh = ti[TILE_NHALO];
@@ -203,37 +209,45 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         for (int qx = 0; qx < N1; ++qx) wq[qy * N1 + qx] = a.B.w[qx] * a.B.w[qy];
       const T invH = T(1) / H;
 
-      if constexpr (MODE == MODE_J) {
-        // Jacobian (Sec. 3.1), ordered to keep few arrays live:
-        //   u rows:   g(phit) sigma(du) : grad psi
-        //   phi rows: c1 dphi + B : e(du) (value), Gc l grad dphi (gradient)
-        //   c1 = (1-k) S(u) + 2 p tr e(u) + Gc/l, B = 2(1-k) phi sigma(u) + 2 p phi I
+      if constexpr (MODE == MODE_J || MODE == MODE_LEVEL) {
+        // Jacobian (Sec. 3.1) in reference units (gradients of the unit square,
+        // Gauss weights in the integration tables); with e^, sigma^ the
+        // reference strain and stress (e = e^ / H):
+        //   u rows:   g(phit) sigma^(du) : grad^ psi
+        //   phi rows: [H^2 c1 dphi + H B : e(du)] psi + Gc l grad^ dphi . grad^ psi
+        //   H^2 c1 = (1-k) S^ + 2 p H tr e^ + H^2 Gc/l,
+        //   H B    = 2 (1-k) phi sigma^(u) + 2 p H phi I   (coupling; not on levels)
+        // The level block operator diag(G_uu, G_phiphi) (Sec. 3.2) is the same
+        // without the coupling term, with the injected level state (u_x, u_y, phit).
+        constexpr bool CPL = (MODE == MODE_J);
+        constexpr int FUX = 3, FUY = 4, FPHI = 5, FPT = CPL ? 6 : 5;
+        const T twopH = T(2) * pr * H, gcl2 = H * H * Gc / ell, gcell = Gc * ell;
         T c1[NQ], bxx[NQ], byy[NQ], bxy[NQ];
         {
           T u[NL], sx1[NQ], sy1[NQ], sx2[NQ], sy2[NQ];
-          gather(3, u);
+          gather(FUX, u);
           interp_g<P, T>(a.B, u, sx1, sy1);
-          gather(4, u);
+          gather(FUY, u);
           interp_g<P, T>(a.B, u, sx2, sy2);
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            const T exx = sx1[q] * invH, eyy = sy2[q] * invH, exy = T(0.5) * (sy1[q] + sx2[q]) * invH;
+            const T exx = sx1[q], eyy = sy2[q], exy = T(0.5) * (sy1[q] + sx2[q]);
             const T tr = exx + eyy;
             const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
             const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
-            c1[q] = (T(1) - kap) * S + T(2) * pr * tr + Gc / ell;
+            c1[q] = (T(1) - kap) * S + twopH * tr + gcl2;
             bxx[q] = sxx;
             byy[q] = syy;
             bxy[q] = sxy;
           }
         }
-        {
+        if constexpr (CPL) {
           T u[NL], pq[NQ];
-          gather(5, u);
+          gather(FPHI, u);
           interp_v<P, T>(a.B, u, pq);
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            const T f = T(2) * (T(1) - kap) * pq[q], t = T(2) * pr * pq[q];
+            const T f = T(2) * (T(1) - kap) * pq[q], t = twopH * pq[q];
             bxx[q] = f * bxx[q] + t;
             byy[q] = f * byy[q] + t;
             bxy[q] = f * bxy[q];
@@ -246,95 +260,42 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
           interp_g<P, T>(a.B, u, dxx, dxy);
           gather(1, u);
           interp_g<P, T>(a.B, u, dyx, dyy);
+          if constexpr (CPL) {
 #pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            const T exx = dxx[q] * invH, eyy = dyy[q] * invH, exy = T(0.5) * (dxy[q] + dyx[q]) * invH;
-            be[q] = bxx[q] * exx + byy[q] * eyy + T(2) * bxy[q] * exy;
+            for (int q = 0; q < NQ; ++q)
+              be[q] = bxx[q] * dxx[q] + byy[q] * dyy[q] + bxy[q] * (dxy[q] + dyx[q]);
           }
         }
         {
           T u[NL], tq[NQ];
-          gather(6, u);
+          gather(FPT, u);
           interp_v<P, T>(a.B, u, tq);
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            const T wg = H * wq[q] * ((T(1) - kap) * tq[q] * tq[q] + kap);
-            const T exx = dxx[q] * invH, eyy = dyy[q] * invH, exy = T(0.5) * (dxy[q] + dyx[q]) * invH;
+            const T gq = (T(1) - kap) * tq[q] * tq[q] + kap;
+            const T exx = dxx[q], eyy = dyy[q], exy2 = dxy[q] + dyx[q];
             const T tr = exx + eyy;
-            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
-            dxx[q] = wg * sxx;
-            dxy[q] = wg * sxy;
-            dyx[q] = wg * sxy;
-            dyy[q] = wg * syy;
+            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = mu * exy2;
+            dxx[q] = gq * sxx;
+            dxy[q] = gq * sxy;
+            dyx[q] = gq * sxy;
+            dyy[q] = gq * syy;
           }
         }
-        integrate_g<P, T>(a.B, dxx, dxy, out[0]);
-        integrate_g<P, T>(a.B, dyx, dyy, out[1]);
+        integrate_gw<P, T>(a.B, dxx, dxy, out[0]);
+        integrate_gw<P, T>(a.B, dyx, dyy, out[1]);
         {
           T u[NL], pv[NQ], px[NQ], py[NQ];
           gather(2, u);
           interp_vg<P, T>(a.B, u, pv, px, py);
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            pv[q] = H * H * wq[q] * (c1[q] * pv[q] + be[q]);
-            px[q] = wq[q] * Gc * ell * px[q];
-            py[q] = wq[q] * Gc * ell * py[q];
+            if constexpr (CPL) pv[q] = c1[q] * pv[q] + be[q];
+            else pv[q] = c1[q] * pv[q];
+            px[q] = gcell * px[q];
+            py[q] = gcell * py[q];
           }
-          integrate<P, T>(a.B, pv, px, py, out[2]);
-        }
-      } else if constexpr (MODE == MODE_LEVEL) {
-        // level block operator diag(G_uu, G_phiphi) (Sec. 3.2): the J rows
-        // without the coupling B : e(du); state (u_x, u_y, phit) injected
-        T c1[NQ], gq[NQ];
-        {
-          T u[NL], sx1[NQ], sy1[NQ], sx2[NQ], sy2[NQ];
-          gather(3, u);
-          interp_g<P, T>(a.B, u, sx1, sy1);
-          gather(4, u);
-          interp_g<P, T>(a.B, u, sx2, sy2);
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            const T exx = sx1[q] * invH, eyy = sy2[q] * invH, exy = T(0.5) * (sy1[q] + sx2[q]) * invH;
-            const T tr = exx + eyy;
-            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
-            const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
-            c1[q] = (T(1) - kap) * S + T(2) * pr * tr + Gc / ell;
-          }
-          gather(5, u);
-          interp_v<P, T>(a.B, u, gq);
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) gq[q] = H * wq[q] * ((T(1) - kap) * gq[q] * gq[q] + kap);
-        }
-        {
-          T u[NL], dxx[NQ], dxy[NQ], dyx[NQ], dyy[NQ];
-          gather(0, u);
-          interp_g<P, T>(a.B, u, dxx, dxy);
-          gather(1, u);
-          interp_g<P, T>(a.B, u, dyx, dyy);
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            const T exx = dxx[q] * invH, eyy = dyy[q] * invH, exy = T(0.5) * (dxy[q] + dyx[q]) * invH;
-            const T tr = exx + eyy;
-            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
-            dxx[q] = gq[q] * sxx;
-            dxy[q] = gq[q] * sxy;
-            dyx[q] = gq[q] * sxy;
-            dyy[q] = gq[q] * syy;
-          }
-          integrate_g<P, T>(a.B, dxx, dxy, out[0]);
-          integrate_g<P, T>(a.B, dyx, dyy, out[1]);
-        }
-        {
-          T u[NL], pv[NQ], px[NQ], py[NQ];
-          gather(2, u);
-          interp_vg<P, T>(a.B, u, pv, px, py);
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            pv[q] = H * H * wq[q] * c1[q] * pv[q];
-            px[q] = wq[q] * Gc * ell * px[q];
-            py[q] = wq[q] * Gc * ell * py[q];
-          }
-          integrate<P, T>(a.B, pv, px, py, out[2]);
+          integrate_w<P, T>(a.B, pv, px, py, out[2]);
         }
       } else if constexpr (MODE == MODE_JT || MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
         // state-derived coefficients at the Gauss points:
@@ -543,7 +504,9 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         if constexpr (EPI == EPI_PLAIN) {
           a.dst[i] = v;
         } else if constexpr (EPI == EPI_RESID) {
-          a.dst[i] = a.b[i] - v;
+          // residual to restrict: zero on rows held at zero on this level
+          const bool held = (c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
+          a.dst[i] = held ? T(0) : a.b[i] - v;
         } else {
           const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
           const int blk = c < 2 ? 0 : 1;

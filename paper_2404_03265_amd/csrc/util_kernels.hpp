@@ -175,10 +175,11 @@ __global__ void k_copy_from_level(double* out, const T* x, int64_t nl, const uin
   }
 }
 
-// x_f += P x_c (rows of P: fine nodes)
+// x_f += P x_c (rows of P: fine nodes); unknowns held at zero on the fine
+// level (u on the boundary, phi on the level active set) stay zero
 template <typename T>
 __global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, const int64_t* ptr,
-                              const int32_t* col, const T* val) {
+                              const int32_t* col, const T* val, const uint8_t* ff) {
   GRID_LOOP(i, nf) {
     T s0 = T(0), s1 = T(0), s2 = T(0);
     for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
@@ -188,9 +189,12 @@ __global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, const 
       s1 += w * xc[nc + j];
       s2 += w * xc[2 * nc + j];
     }
-    xf[i] += s0;
-    xf[nf + i] += s1;
-    xf[2 * nf + i] += s2;
+    const uint8_t f = ff[i];
+    if (!(f & NODE_DIRICHLET)) {
+      xf[i] += s0;
+      xf[nf + i] += s1;
+    }
+    if (!(f & NODE_ACTIVE)) xf[2 * nf + i] += s2;
   }
 }
 
