@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sneddon_1024x1024_L3_Q2")
     ap.add_argument("--vmult-reps", type=int, default=50)
+    ap.add_argument("--tile", type=int, nargs=2, default=(0, 0),
+                    help="owned cells per tile (x, y); 0 0 = library default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--profile-pass", action="store_true",
@@ -146,7 +148,7 @@ def main():
     sp_ = SolverParams(E=spec.E, nu=spec.nu, Gc=spec.Gc, pressure=spec.pressure, kappa=spec.kappa,
                        ell=spec.ell)
     t0 = time.time()
-    g = PhaseFieldSolver(spec.n_base, spec.n_local, spec.degree, params=sp_)
+    g = PhaseFieldSolver(spec.n_base, spec.n_local, spec.degree, tile=tuple(args.tile), params=sp_)
     n_tiles, n_rec, _ = g.tile_stats()
     log(f"{spec.name}: {3 * g.n} unknowns, {g.n_levels} levels, {n_tiles} tiles, "
         f"built in {time.time() - t0:.1f}s")

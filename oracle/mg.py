@@ -209,7 +209,11 @@ def cg_eigs(A, Dinv, free, its):
     z = d * r
     pvec = z.copy()
     rz = r @ z
+    rz0 = rz
     alphas, betas = [], []
+    # at most `its` steps and never more than the number of unknowns; stop
+    # once the residual has dropped by 1e-12 (later Lanczos steps only add
+    # spurious Ritz values)
     for _ in range(min(its, idx.size)):
         q = Af @ pvec
         pq = pvec @ q
@@ -224,7 +228,7 @@ def cg_eigs(A, Dinv, free, its):
         betas.append(beta)
         pvec = z + beta * pvec
         rz = rz_new
-        if rz == 0:
+        if rz <= 1e-24 * rz0:
             break
     k = len(alphas)
     diag = np.array([1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0)

@@ -7,7 +7,8 @@ Newton iteration (Sec. 3.1, Alg. 2):
  2. Active set (eq. AcInS with the constant c of Sec. 2):
     lambda_i = R_i / B_ii with B the lumped phase-field mass,
     c_i = 2 |lambda_i / (phi_i - phi_old_i)| (c_i * 0 taken as 0),
-    active <=> lambda_i + c_i (phi_i - phi_old_i) > 0; hanging unknowns never.
+    active <=> lambda_i + c_i (phi_i - phi_old_i) > tau (tau = 1e-12 max |lambda|,
+    rounding-level ties count as zero); hanging unknowns never.
  3. Inhomogeneous constraint dphi_i = phi_old_i - phi_i on the active set.
     F is affine in phi at fixed u and dF/dphi does not depend on phi, so
     R~(U_c) with U_c = U + dU_c equals R~(U) - J dU_c exactly.
@@ -61,7 +62,11 @@ def active_set(lp: LeafProblem, R, phi, phi_old):
     nz = diff != 0.0
     c = np.where(nz, 2.0 * np.abs(lam / np.where(nz, diff, 1.0)), 0.0)
     val = lam + c * diff
-    return (val > 0.0) & ~hang
+    # exact ties (lambda = 0 where the state makes the phase-field residual
+    # vanish) arrive as rounding noise; values below 1e-12 max|lambda| count
+    # as zero, so ties stay inactive as the strict inequality intends
+    tau = 1e-12 * np.abs(lam[~hang]).max() if np.any(~hang) else 0.0
+    return (val > tau) & ~hang
 
 
 def masked_residual(lp: LeafProblem, U, phit, active):

@@ -207,6 +207,15 @@ struct pff_ctx {
     int threads = ((std::min(std::max(t.typ_cells, 1), 256) + 63) / 64) * 64;
     threads = std::max(64, threads);
     a.tile_order = t.order;
+    if (lds > size_t(160 * 1024)) throw std::runtime_error("tile needs more LDS than a CU has; use smaller tiles");
+    if (lds > size_t(64 * 1024)) {
+      const void* k0 = p == 1 ? reinterpret_cast<const void*>(&tile_kernel<1, T, MODE, EPI, false>)
+                              : reinterpret_cast<const void*>(&tile_kernel<2, T, MODE, EPI, false>);
+      const void* k1 = p == 1 ? reinterpret_cast<const void*>(&tile_kernel<1, T, MODE, EPI, true>)
+                              : reinterpret_cast<const void*>(&tile_kernel<2, T, MODE, EPI, true>);
+      HIPCHK(hipFuncSetAttribute(k0, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+      HIPCHK(hipFuncSetAttribute(k1, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    }
     const int nreg = t.n_regular, nhang = t.n_tiles - t.n_regular;
     if (nreg > 0) {
       a.tile_base = 0;
@@ -436,9 +445,14 @@ struct pff_ctx {
       hipLaunchKernelGGL(k_free_ones, dim3(grid_for(len)), dim3(256), 0, s, r + off, w.dinv + off, len);
       hipLaunchKernelGGL(k_mul, dim3(grid_for(3 * nl)), dim3(256), 0, s, z, w.dinv, r, 3 * nl);
       HIPCHK(hipMemcpyAsync(pv, z, sizeof(double) * 3 * nl, hipMemcpyDeviceToDevice, s));
+      const double n_free = dot(r + off, r + off, len);
       double rz = dot(r + off, z + off, len);
+      const double rz0 = rz;
       std::vector<double> al, be;
-      for (int it = 0; it < its && rz > 0.0; ++it) {
+      // at most `its` steps and never more than the number of free unknowns;
+      // stop once the residual has dropped by 1e-12
+      const int max_it = int(std::min<double>(its, n_free));
+      for (int it = 0; it < max_it && rz > 0.0; ++it) {
         level_apply<double>(l, pv, q, EPI_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr);
         // only the block's free rows matter: p is zero elsewhere
         const double pq = dot(pv + off, q + off, len);
@@ -452,6 +466,7 @@ struct pff_ctx {
         be.push_back(beta);
         hipLaunchKernelGGL(k_waxpy, dim3(grid_for(len)), dim3(256), 0, s, pv + off, z + off, pv + off, beta, len);
         rz = rz2;
+        if (rz <= 1e-24 * rz0) break;
       }
       const int m = int(al.size());
       double lo = 1.0, hi = 1.0;
@@ -856,8 +871,12 @@ int pff_set_state(pff_ctx* c, const double* U, const double* phi_old, const doub
   } else {
     double* R = c->wv[2];
     c->residual(R, c->U);
+    double* tau = c->red_out + 200;
+    hipLaunchKernelGGL(k_lambda_max_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->s, R, c->mass + 2 * n,
+                       c->flags, n, c->red_part);
+    hipLaunchKernelGGL(k_reduce_max_final, dim3(1), dim3(RED_THREADS), 0, c->s, c->red_part, RED_BLOCKS, 1e-12, tau);
     hipLaunchKernelGGL(k_active_rule, dim3(grid_for(n)), dim3(256), 0, c->s, c->flags, R, c->mass + 2 * n,
-                       c->U + 2 * n, c->phio, n);
+                       c->U + 2 * n, c->phio, n, tau);
   }
   HIPCHK(hipGetLastError());
   c->has_state = true;

@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   // 1. stage local nodes: all global loads of a batch are issued before any
   //    LDS store (one dependent round trip for halo ids, one for the values)
   uint8_t* lflag = reinterpret_cast<uint8_t*>(acc + 3 * MO);   // [max_local]
-  constexpr int SLOTS = P == 1 ? 2 : 6;   // ~ local nodes / threads of a typical tile
+  constexpr int SLOTS = 4;   // local nodes per thread and batch (larger tiles take several batches)
   for (int base = 0; base < nloc; base += SLOTS * int(blockDim.x)) {
     int64_t gs[SLOTS];
 #pragma unroll

@@ -53,9 +53,12 @@ __global__ void k_set_active(uint8_t* flags, const uint8_t* active, int64_t n) {
 }
 
 // Active-set rule of Alg. 2 with c_i = 2 |lambda_i / (phi_i - phi_old_i)|
-// (c_i * 0 := 0), lambda = R_phi / B.
+// (c_i * 0 := 0), lambda = R_phi / B: active <=> lambda + c (phi - phi_old)
+// exceeds tau, tau = 1e-12 max |lambda| (*tau_ptr): exact ties that quadrature
+// turns into rounding noise count as zero, i.e. inactive.
 __global__ void k_active_rule(uint8_t* flags, const double* R, const double* mass, const double* phi,
-                              const double* phio, int64_t n) {
+                              const double* phio, int64_t n, const double* tau_ptr) {
+  const double tau = *tau_ptr;
   GRID_LOOP(i, n) {
     uint8_t f = flags[i] & uint8_t(~NODE_ACTIVE);
     if (!(f & NODE_HANGING)) {
@@ -63,10 +66,43 @@ __global__ void k_active_rule(uint8_t* flags, const double* R, const double* mas
       const double diff = phi[i] - phio[i];
       const double c = diff != 0.0 ? 2.0 * fabs(lam / diff) : 0.0;
       const double val = lam + c * diff;
-      if (val > 0.0) f |= NODE_ACTIVE;
+      if (val > tau) f |= NODE_ACTIVE;
     }
     flags[i] = f;
   }
+}
+
+// per-block maxima of |R_phi / B| over non-hanging nodes
+__global__ void __launch_bounds__(RED_THREADS) k_lambda_max_partial(const double* R, const double* mass,
+                                                                      const uint8_t* flags, int64_t n,
+                                                                      double* part) {
+  __shared__ double sh[RED_THREADS];
+  double m = 0.0;
+  GRID_LOOP(i, n) {
+    if (!(flags[i] & NODE_HANGING)) m = fmax(m, fabs(R[2 * n + i] / mass[i]));
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// out[0] = scale * max of part[0..nb)
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_max_final(const double* part, int nb, double scale,
+                                                                    double* out) {
+  __shared__ double sh[RED_THREADS];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) m = fmax(m, part[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = scale * sh[0];
 }
 
 __global__ void k_get_active(uint8_t* out, const uint8_t* flags, int64_t n) {
