@@ -60,7 +60,7 @@ typedef struct pff_ctx pff_ctx;
  * passes refining every cell whose centre lies strictly inside
  * |x| < band_x, |y| < band_y, then 2:1 face balancing. degree = 1 (Q1) or
  * 2 (Q2). tile_x, tile_y: owned cells per tile along x and y (0 = default:
- * 15 for Q1, 7 for Q2). */
+ * 15 for Q1, 10 for Q2). */
 typedef struct {
   int32_t n_base, n_local, degree, coarse;
   double band_x, band_y;

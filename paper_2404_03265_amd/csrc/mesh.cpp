@@ -192,8 +192,8 @@ bool Mesh::build(const MeshSpec& s) {
   n_levels = lmax + 1;
   M = int64_t(s.coarse) << lmax;
   M *= p;
-  const int TX = s.tile_x > 0 ? s.tile_x : (p == 1 ? 15 : 7);
-  const int TY = s.tile_y > 0 ? s.tile_y : (p == 1 ? 15 : 7);
+  const int TX = s.tile_x > 0 ? s.tile_x : (p == 1 ? 15 : 10);
+  const int TY = s.tile_y > 0 ? s.tile_y : (p == 1 ? 15 : 10);
   auto S = [&](int l) { return int64_t(p) << (lmax - l); };
   auto ncell = [&](int l) { return int64_t(s.coarse) << l; };
   level_H.assign(n_levels, 0.0);

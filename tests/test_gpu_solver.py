@@ -192,3 +192,42 @@ def test_full_size_vmult_sampled_rows():
     print(f"[full] oracle rows done {time.time() - t0:.1f}s", flush=True)
     scale = np.abs(dst).max()
     assert np.abs(got - ref).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("name,p", CASES)
+def test_adjoint_crack_volume_gradient(name, p):
+    """Adjoint gradient of TCV w.r.t. (Gc, E, p) at a converged load step with
+    frozen active set: GPU (transposed GMRES + parameter derivatives) against
+    the oracle's direct adjoint at the same state; the autograd wrapper returns
+    the same gradient; z^T (J~ v) = (J~^T z)^T v."""
+    import torch
+    from oracle.newton import adjoint_gradient
+    from paper_2404_03265_amd import SolverParams
+    from paper_2404_03265_amd.autograd import adjoint_tcv_gradient, solve_load_step, JacobianApply
+    m = MESHES[name]
+    sp_ = SolverParams(gmres_rtol=1e-13, gmres_atol=1e-15)
+    c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="rule",
+             solver_params=sp_)
+    ux, uy, phi = inputs.sneddon_state(c.X, c.Y, c.M, random=False)
+    U = c.dev(np.concatenate([ux, uy, phi]))
+    ph = c.dev(phi)
+    act, infos = solve_load_step(c.g, U, ph, ph, tol=1e-10)
+    assert infos[-1]["residual_before"] <= 1e-10
+    tcv, grad, z, info = adjoint_tcv_gradient(c.g, U, ph, ph, act, tol=0.0)
+    assert info["converged"] == 1
+    Uo = c.to_o(U.cpu().numpy())
+    act_o = act.cpu().numpy().astype(bool)[c.o2g]
+    ref, _ = adjoint_gradient(c.lp, Uo, c.to_o(phi), act_o)
+    assert abs(tcv - c.lp.tcv(Uo)) <= 1e-12 * abs(tcv)
+    for i, k in enumerate(("Gc", "E", "p")):
+        assert abs(grad[i].item() - ref[k]) <= 1e-7 * max(abs(ref[k]), 1e-14 * abs(tcv)), (k, grad[i], ref[k])
+    v = c.dev(inputs.random_vector(c.X, c.Y, 21))
+    w = c.dev(inputs.random_vector(c.X, c.Y, 22))
+    lhs = torch.dot(w, c.g.vmult(v)).item()
+    rhs = torch.dot(c.g.vmult_T(w), v).item()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # autograd: backward of JacobianApply is the transpose
+    vv = v.clone().requires_grad_(True)
+    y = JacobianApply.apply(vv, c.g)
+    y.backward(w)
+    assert torch.allclose(vv.grad, c.g.vmult_T(w), rtol=0, atol=1e-13 * w.abs().max().item())
