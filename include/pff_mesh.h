@@ -39,8 +39,25 @@ int pff_mesh_hanging(const pff_mesh* m, int64_t* count, int32_t* node, int32_t* 
 int pff_mesh_prolongation(const pff_mesh* m, int32_t level, int64_t* nnz, int64_t* ptr, int32_t* col, double* val);
 /* Leaf node at the position of every node of a level (n_level int32). */
 int pff_mesh_leaf_index(const pff_mesh* m, int32_t level, int32_t* idx);
-/* Tile statistics: tiles, cell records (own + halo), largest tile. */
+/* Tile statistics: tiles, cell records (one per cell), largest tile. */
 int pff_mesh_tile_stats(const pff_mesh* m, int32_t level, int64_t* n_tiles, int64_t* n_records, int64_t* max_cells);
+/* Tile tables of the leaf (level = -1) or a level operator, as the device
+ * kernels read them. sizes (10 int64, required): n_tiles, length of the
+ * shared list, n_private, n_shared, n_slots, cell records, regular tiles,
+ * largest local node count, hanging-node records, largest number of
+ * hanging-node colours of a tile. Arrays are optional (NULL skips):
+ * tile_info (12 per tile: private start, private count, shared-list start,
+ * shared count, first cell record, cell count, cell colours, first slot,
+ * first hanging record, hanging records, hanging colours, unused), shared
+ * (global ids), shared_ptr (n_shared + 1), shared_slot (n_slots), cell_loc and
+ * cell_loc_sub ((p+1)^2 per record, local ids: private nodes first, then the
+ * tile's shared list; own nodes, and with hanging faces replaced by the coarse
+ * face's nodes), cell_info (per record), order (n_tiles: tiles without
+ * hanging-face cells first), hang_rec (4 per record: hanging node, masters),
+ * hang_w (3 per record), hang_col (per record). */
+int pff_mesh_tile_tables(const pff_mesh* m, int32_t level, int64_t* sizes, int32_t* tile_info, int32_t* shared,
+                         int32_t* shared_ptr, int32_t* shared_slot, uint16_t* cell_loc, uint16_t* cell_loc_sub,
+                         uint16_t* cell_info, int32_t* order, uint16_t* hang_rec, double* hang_w, uint8_t* hang_col);
 
 #ifdef __cplusplus
 }

@@ -83,6 +83,7 @@ _SIGS = {
     "pff_mesh_leaf_index": (C.c_int, [VP, C.c_int32, VP]),
     "pff_mesh_tile_stats": (C.c_int, [VP, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]),
+    "pff_mesh_tile_tables": (C.c_int, [VP, C.c_int32, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
 }
 
 _lib = None

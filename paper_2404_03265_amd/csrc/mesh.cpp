@@ -1,6 +1,6 @@
 // Quadtree mesh of (-10,10)^2 with band refinement and 2:1 face balance,
 // Q_p nodes on an integer lattice, hanging-node constraints, tile tables for
-// the owner-computes operator kernels and the local-smoothing level hierarchy.
+// the cell-partition operator kernels and the local-smoothing level hierarchy.
 //
 // Geometry (Sec. 4, Fig. 1, Table 1): uniform base mesh reached from a coarse
 // grid by global refinement, then local refinement of cells whose centre is
@@ -13,7 +13,9 @@
 #include "mesh.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <numeric>
 #include <stdexcept>
@@ -60,119 +62,208 @@ struct PosIndex {
   int64_t Y(int64_t n) const { return int64_t(keys[n] / W); }
 };
 
-// Generic tile builder. Cells carry footprints in temporary node ids; nodes
-// carry an owner tile. Produces the node renumbering (owned nodes of a tile
-// contiguous, ordered by (tile, Y, X)) and the tile tables.
-void build_tiles(int p, int n_tiles, const std::vector<int32_t>& fp,
-                 std::vector<uint16_t>& info, const std::vector<int32_t>& node_tile,
+// Generic tile builder. cell_tile partitions the cells into tiles; node_home
+// names the tile of a cell holding each node (used for nodes no footprint
+// touches). fp holds the substituted footprints, fp_raw the cells' own nodes
+// (the same arrays where there are no hanging nodes); hang lists the hanging
+// constraints by temporary node id. Produces the node renumbering and the
+// tile tables (see TileSet).
+void build_tiles(int p, int n_tiles, const std::vector<int32_t>& fp, const std::vector<int32_t>& fp_raw,
+                 const std::unordered_map<int64_t, Hanging>& hang,
+                 const std::vector<uint16_t>& info, const std::vector<int32_t>& cell_tile,
+                 const std::vector<int32_t>& node_home,
                  const std::vector<int32_t>& NXt, const std::vector<int32_t>& NYt,
                  TileSet& T, std::vector<int32_t>& new_id) {
   const int NL = (p + 1) * (p + 1);
-  const int64_t n_nodes = int64_t(node_tile.size());
+  const int64_t n_nodes = int64_t(node_home.size());
   const int64_t n_cells = int64_t(info.size());
   T.p = p;
   T.n_tiles = n_tiles;
-  // node renumbering
+  // first and last tile touching every node (through either footprint: a
+  // tile writes the masters of its hanging nodes)
+  std::vector<int32_t> tmin(n_nodes, INT32_MAX), tmax(n_nodes, -1);
+  for (int64_t c = 0; c < n_cells; ++c) {
+    const int32_t t = cell_tile[c];
+    for (int k = 0; k < 2 * NL; ++k) {
+      const int32_t nd = k < NL ? fp[c * NL + k] : fp_raw[c * NL + k - NL];
+      tmin[nd] = std::min(tmin[nd], t);
+      tmax[nd] = std::max(tmax[nd], t);
+    }
+  }
+  // private nodes by (tile, Y, X), then shared nodes by (first tile, Y, X)
+  std::vector<int32_t> key_tile(n_nodes);
+  std::vector<char> is_shared(n_nodes, 0);
+  for (int64_t nd = 0; nd < n_nodes; ++nd) {
+    if (tmax[nd] < 0) {
+      key_tile[nd] = node_home[nd];
+    } else {
+      key_tile[nd] = tmin[nd];
+      is_shared[nd] = tmin[nd] != tmax[nd];
+    }
+  }
   std::vector<int32_t> order(n_nodes);
   std::iota(order.begin(), order.end(), 0);
   std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    if (node_tile[a] != node_tile[b]) return node_tile[a] < node_tile[b];
+    if (is_shared[a] != is_shared[b]) return is_shared[a] < is_shared[b];
+    if (key_tile[a] != key_tile[b]) return key_tile[a] < key_tile[b];
     if (NYt[a] != NYt[b]) return NYt[a] < NYt[b];
     return NXt[a] < NXt[b];
   });
   new_id.assign(n_nodes, -1);
   std::vector<int32_t> owned0(n_tiles + 1, 0);
+  T.n_private = 0;
   for (int64_t r = 0; r < n_nodes; ++r) {
     new_id[order[r]] = int32_t(r);
-    owned0[node_tile[order[r]] + 1]++;
-  }
-  for (int t = 0; t < n_tiles; ++t) owned0[t + 1] += owned0[t];
-  // contributors: cells whose footprint touches a tile's owned nodes
-  std::vector<std::vector<int32_t>> tcells(n_tiles);
-  for (int64_t c = 0; c < n_cells; ++c) {
-    int last = -1;
-    for (int k = 0; k < NL; ++k) {
-      int t = node_tile[fp[c * NL + k]];
-      if (t != last) tcells[t].push_back(int32_t(c));
-      last = t;
+    if (!is_shared[order[r]]) {
+      owned0[key_tile[order[r]] + 1]++;
+      T.n_private++;
     }
   }
-  T.tile_info.assign(size_t(n_tiles) * 8, 0);
-  T.halo.clear();
+  for (int t = 0; t < n_tiles; ++t) owned0[t + 1] += owned0[t];
+  T.n_shared = n_nodes - T.n_private;
+  // hanging constraints by new id
+  std::unordered_map<int32_t, const Hanging*> hang_new;
+  for (const auto& kv : hang) hang_new[new_id[kv.first]] = &kv.second;
+  // cells of each tile, in cell order
+  std::vector<int32_t> cell0(n_tiles + 1, 0), cells(n_cells);
+  for (int64_t c = 0; c < n_cells; ++c) cell0[cell_tile[c] + 1]++;
+  for (int t = 0; t < n_tiles; ++t) cell0[t + 1] += cell0[t];
+  {
+    std::vector<int32_t> fill(cell0.begin(), cell0.end() - 1);
+    for (int64_t c = 0; c < n_cells; ++c) cells[fill[cell_tile[c]]++] = int32_t(c);
+  }
+  T.tile_info.assign(size_t(n_tiles) * TILE_STRIDE, 0);
+  T.shared.clear();
   T.cell_loc.clear();
+  T.cell_loc_sub.clear();
   T.cell_info.clear();
-  T.max_cells = T.max_local = T.max_owned = 0;
-  std::vector<int32_t> halo_tmp;
+  T.hang_rec.clear();
+  T.hang_w.clear();
+  T.hang_col.clear();
+  T.max_cells = T.max_local = T.max_owned = T.max_hang_colors = 0;
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> slots_of(T.n_shared);  // (tile, slot)
+  std::vector<int32_t> sh, hn;
+  int64_t slot0 = 0;
   for (int t = 0; t < n_tiles; ++t) {
-    auto& cl = tcells[t];
-    std::sort(cl.begin(), cl.end());
-    cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
     const int32_t o0 = owned0[t], no = owned0[t + 1] - owned0[t];
-    halo_tmp.clear();
-    for (int32_t c : cl)
-      for (int k = 0; k < NL; ++k) {
-        int32_t g = new_id[fp[int64_t(c) * NL + k]];
-        if (g < o0 || g >= o0 + no) halo_tmp.push_back(g);
+    sh.clear();
+    hn.clear();
+    for (int32_t r = cell0[t]; r < cell0[t + 1]; ++r)
+      for (int k = 0; k < 2 * NL; ++k) {
+        const int64_t c = cells[r];
+        const int32_t g = new_id[k < NL ? fp[c * NL + k] : fp_raw[c * NL + k - NL]];
+        if (g >= T.n_private) sh.push_back(g);
+        else if (g < o0 || g >= o0 + no) throw std::runtime_error("private node of another tile");
+        if (k >= NL && hang_new.count(g)) hn.push_back(g);
       }
-    std::sort(halo_tmp.begin(), halo_tmp.end());
-    halo_tmp.erase(std::unique(halo_tmp.begin(), halo_tmp.end()), halo_tmp.end());
-    int32_t* ti = &T.tile_info[size_t(t) * 8];
+    std::sort(sh.begin(), sh.end());
+    sh.erase(std::unique(sh.begin(), sh.end()), sh.end());
+    std::sort(hn.begin(), hn.end());
+    hn.erase(std::unique(hn.begin(), hn.end()), hn.end());
+    int32_t* ti = &T.tile_info[size_t(t) * TILE_STRIDE];
     ti[TILE_OWNED0] = o0;
     ti[TILE_NOWNED] = no;
-    ti[TILE_HALO0] = int32_t(T.halo.size());
-    ti[TILE_NHALO] = int32_t(halo_tmp.size());
+    ti[TILE_SHARED0] = int32_t(T.shared.size());
+    ti[TILE_NSHARED] = int32_t(sh.size());
     ti[TILE_CELL0] = int32_t(T.cell_info.size());
-    ti[TILE_NCELL] = int32_t(cl.size());
-    T.halo.insert(T.halo.end(), halo_tmp.begin(), halo_tmp.end());
-    // local ids and greedy colouring over shared owned nodes
-    std::vector<uint32_t> used(no, 0u);
+    ti[TILE_NCELL] = cell0[t + 1] - cell0[t];
+    ti[TILE_SLOT0] = int32_t(slot0);
+    for (size_t r = 0; r < sh.size(); ++r)
+      slots_of[sh[r] - T.n_private].push_back({t, int32_t(slot0 + int64_t(r))});
+    slot0 += int64_t(sh.size());
+    if (slot0 > INT32_MAX) throw std::runtime_error("too many partial-sum slots");
+    T.shared.insert(T.shared.end(), sh.begin(), sh.end());
+    const int nloc = no + int(sh.size());
+    if (nloc > 65535) throw std::runtime_error("tile has more than 65535 local nodes");
+    auto local = [&](int32_t g) -> uint16_t {
+      return uint16_t(g < T.n_private ? g - o0
+                                      : no + int32_t(std::lower_bound(sh.begin(), sh.end(), g) - sh.begin()));
+    };
+    // cells: local ids of both footprints; greedy colouring so that cells of
+    // one colour share no node of either footprint
+    std::vector<uint32_t> used(nloc, 0u);
     int ncol = 0;
-    for (int32_t c : cl) {
-      uint16_t loc[9];
+    for (int32_t r = cell0[t]; r < cell0[t + 1]; ++r) {
+      const int64_t c = cells[r];
+      uint16_t loc[9], lsub[9];
       uint32_t busy = 0;
       for (int k = 0; k < NL; ++k) {
-        int32_t g = new_id[fp[int64_t(c) * NL + k]];
-        int32_t l;
-        if (g >= o0 && g < o0 + no) {
-          l = g - o0;
-          busy |= used[l];
-        } else {
-          l = no + int32_t(std::lower_bound(halo_tmp.begin(), halo_tmp.end(), g) - halo_tmp.begin());
-        }
-        loc[k] = uint16_t(l);
+        loc[k] = local(new_id[fp_raw[c * NL + k]]);
+        lsub[k] = local(new_id[fp[c * NL + k]]);
+        busy |= used[loc[k]] | used[lsub[k]];
       }
       int col = 0;
       while (busy & (1u << col)) ++col;
-      for (int k = 0; k < NL; ++k)
-        if (loc[k] < no) used[loc[k]] |= (1u << col);
+      for (int k = 0; k < NL; ++k) {
+        used[loc[k]] |= (1u << col);
+        used[lsub[k]] |= (1u << col);
+      }
       ncol = std::max(ncol, col + 1);
-      for (int k = 0; k < NL; ++k) T.cell_loc.push_back(loc[k]);
+      for (int k = 0; k < NL; ++k) {
+        T.cell_loc.push_back(loc[k]);
+        T.cell_loc_sub.push_back(lsub[k]);
+      }
       T.cell_info.push_back(uint16_t((info[c] & ~(uint16_t(31) << CELL_COLOR_SHIFT)) |
                                      (uint16_t(col) << CELL_COLOR_SHIFT)));
     }
     ti[TILE_NCOLOR] = ncol;
     if (ncol > 16) throw std::runtime_error("more than 16 colours in a tile");
-    T.max_cells = std::max<int>(T.max_cells, int(cl.size()));
+    // hanging nodes touched by the tile's cells; colours over masters
+    ti[TILE_HANG0] = int32_t(T.hang_col.size());
+    ti[TILE_NHANG] = int32_t(hn.size());
+    std::fill(used.begin(), used.end(), 0u);
+    int nhcol = 0;
+    for (int32_t g : hn) {
+      const Hanging& h = *hang_new[g];
+      uint16_t rec[4];
+      double w[3] = {0.0, 0.0, 0.0};
+      rec[0] = local(g);
+      uint32_t busy = 0;
+      for (int k = 0; k < 3; ++k) {
+        const bool on = k <= p;
+        rec[1 + k] = local(new_id[h.master[on ? k : 0]]);
+        w[k] = on ? h.weight[k] : 0.0;
+        busy |= used[rec[1 + k]];
+      }
+      int col = 0;
+      while (busy & (1u << col)) ++col;
+      if (col > 15) throw std::runtime_error("more than 16 hanging-node colours in a tile");
+      for (int k = 0; k <= p; ++k) used[rec[1 + k]] |= (1u << col);
+      nhcol = std::max(nhcol, col + 1);
+      for (int k = 0; k < 4; ++k) T.hang_rec.push_back(rec[k]);
+      for (int k = 0; k < 3; ++k) T.hang_w.push_back(w[k]);
+      T.hang_col.push_back(uint8_t(col));
+    }
+    ti[TILE_NHCOLOR] = nhcol;
+    T.max_hang_colors = std::max(T.max_hang_colors, nhcol);
+    T.max_cells = std::max<int>(T.max_cells, ti[TILE_NCELL]);
     T.max_owned = std::max<int>(T.max_owned, no);
-    T.max_local = std::max<int>(T.max_local, no + int(halo_tmp.size()));
+    T.max_local = std::max<int>(T.max_local, nloc);
+  }
+  T.n_slots = slot0;
+  T.shared_ptr.assign(size_t(T.n_shared) + 1, 0);
+  T.shared_slot.clear();
+  T.shared_slot.reserve(size_t(slot0));
+  for (int64_t s = 0; s < T.n_shared; ++s) {
+    auto& v = slots_of[s];
+    std::sort(v.begin(), v.end());
+    if (v.size() < 2) throw std::runtime_error("shared node with fewer than two tiles");
+    for (auto& e : v) T.shared_slot.push_back(e.second);
+    T.shared_ptr[s + 1] = int32_t(T.shared_slot.size());
   }
   T.n_cell_records = int64_t(T.cell_info.size());
-  T.order.clear();
-  std::vector<int32_t> hang_tiles;
+  // launch order: tiles in (level, row, column) order, so that a contiguous
+  // chunk of the list covers neighbouring tiles; n_regular counts the tiles
+  // without hanging-face cells
+  T.order.resize(n_tiles);
+  std::iota(T.order.begin(), T.order.end(), 0);
+  T.n_regular = 0;
   for (int t = 0; t < n_tiles; ++t) {
-    const int32_t* ti = &T.tile_info[size_t(t) * 8];
+    const int32_t* ti = &T.tile_info[size_t(t) * TILE_STRIDE];
     bool h = false;
     for (int c = 0; c < ti[TILE_NCELL]; ++c)
       if (T.cell_info[size_t(ti[TILE_CELL0]) + c] & 15u) h = true;
-    (h ? hang_tiles : T.order).push_back(t);
-  }
-  T.n_regular = int(T.order.size());
-  T.order.insert(T.order.end(), hang_tiles.begin(), hang_tiles.end());
-  std::vector<int32_t> counts(n_tiles);
-  for (int t = 0; t < n_tiles; ++t) counts[t] = T.tile_info[size_t(t) * 8 + TILE_NCELL];
-  if (n_tiles > 0) {
-    std::nth_element(counts.begin(), counts.begin() + n_tiles / 2, counts.end());
-    T.typ_cells = counts[n_tiles / 2];
+    if (!h) T.n_regular++;
   }
 }
 
@@ -192,8 +283,9 @@ bool Mesh::build(const MeshSpec& s) {
   n_levels = lmax + 1;
   M = int64_t(s.coarse) << lmax;
   M *= p;
-  const int TX = s.tile_x > 0 ? s.tile_x : (p == 1 ? 15 : 10);
-  const int TY = s.tile_y > 0 ? s.tile_y : (p == 1 ? 15 : 10);
+  const int TX = s.tile_x > 0 ? s.tile_x : (p == 1 ? 16 : 8);
+  const int TY = s.tile_y > 0 ? s.tile_y : (p == 1 ? 16 : 8);
+  if (TX * TY > 256) { error = "a tile holds at most 256 cells"; return false; }
   auto S = [&](int l) { return int64_t(p) << (lmax - l); };
   auto ncell = [&](int l) { return int64_t(s.coarse) << l; };
   level_H.assign(n_levels, 0.0);
@@ -283,7 +375,7 @@ bool Mesh::build(const MeshSpec& s) {
   for (int64_t n = 0; n < nn; ++n) { NXt[n] = int32_t(pos.X(n)); NYt[n] = int32_t(pos.Y(n)); }
 
   // footprints with hanging substitution
-  std::vector<int32_t> fp(cells.size() * NL);
+  std::vector<int32_t> fp(cells.size() * NL), fp_raw(cells.size() * NL);
   std::vector<uint16_t> info(cells.size());
   std::unordered_map<int64_t, Hanging> hang_tmp;
   for (size_t c = 0; c < cells.size(); ++c) {
@@ -294,6 +386,7 @@ bool Mesh::build(const MeshSpec& s) {
     if (C.j & 1) inf |= CELL_CY;
     for (int bb = 0; bb <= p; ++bb)
       for (int a = 0; a <= p; ++a) fp[c * NL + bb * (p + 1) + a] = int32_t(pos.find(C.i * Sl + a * h, C.j * Sl + bb * h));
+    for (int k = 0; k < NL; ++k) fp_raw[c * NL + k] = fp[c * NL + k];
     for (int d = 0; d < 4; ++d) {
       int64_t ni = C.i + DI[d], nj = C.j + DJ[d];
       if (ni < 0 || nj < 0 || ni >= ncell(C.l) || nj >= ncell(C.l)) continue;
@@ -371,7 +464,7 @@ bool Mesh::build(const MeshSpec& s) {
     if (node_tile[n] < 0) { error = "node without owner cell"; return false; }
   }
   std::vector<int32_t> new_id;
-  build_tiles(p, n_leaf_tiles, fp, info, node_tile, NXt, NYt, tiles, new_id);
+  build_tiles(p, n_leaf_tiles, fp, fp_raw, hang_tmp, info, cell_tile, node_tile, NXt, NYt, tiles, new_id);
   n_nodes = nn;
   NX.assign(nn, 0);
   NY.assign(nn, 0);
@@ -475,7 +568,7 @@ bool Mesh::build(const MeshSpec& s) {
     for (size_t c = 0; c < lc.size(); ++c)
       if (is_leaf(l, lc[c].i, lc[c].j))
         for (int k = 0; k < NL; ++k) fl[lfp[c * NL + k]] |= NODE_LEAFCELL;
-    build_tiles(p, int(ltile.size()), lfp, linfo, ntile, NXl, NYl, L.tiles, lev_new[l]);
+    build_tiles(p, int(ltile.size()), lfp, lfp, {}, linfo, lcell_tile, ntile, NXl, NYl, L.tiles, lev_new[l]);
     L.n = n;
     L.NX.assign(n, 0);
     L.NY.assign(n, 0);

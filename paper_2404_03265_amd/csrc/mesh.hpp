@@ -32,24 +32,51 @@ enum : uint8_t {
   NODE_COPY = 1u << 5,       // level node receives/returns a leaf value
 };
 
-// One set of cells processed by tiles: each tile owns a contiguous range of
-// nodes and lists every cell contributing to them (own and halo cells).
+// One set of cells processed by tiles. The tiles partition the cells; the
+// local nodes of a tile are the nodes its cells touch. A node touched by the
+// cells of one tile only (or by none, like a hanging node, which then belongs
+// to the tile of the cell holding it) is private to that tile; a node touched
+// by several tiles is shared. Numbering: private nodes grouped by tile, then
+// shared nodes. Every tile writes a partial sum per shared local node into a
+// slot of its own; a fix-up pass adds the slots of each shared node in
+// ascending tile order, so results do not depend on scheduling.
 struct TileSet {
   int p = 1;
   int n_tiles = 0;
   int max_cells = 0;        // largest cell count of a tile
   int max_local = 0;        // largest local node count of a tile
-  int max_owned = 0;
-  int typ_cells = 0;        // median cell count of a tile
+  int max_owned = 0;        // largest private node count of a tile
   int n_regular = 0;        // tiles without hanging-face cells (listed first in `order`)
-  std::vector<int32_t> order;       // tile ids: regular tiles, then tiles with hanging cells
-  std::vector<int32_t> tile_info;   // 8 ints per tile, see TILE_* below
-  std::vector<int32_t> halo;        // global node ids of halo nodes, per tile
-  std::vector<uint16_t> cell_loc;   // (p+1)^2 local node ids per cell record
-  std::vector<uint16_t> cell_info;  // info word per cell record
+  int64_t n_private = 0;    // nodes [0, n_private) are private
+  int64_t n_shared = 0;     // nodes [n_private, n_private + n_shared) are shared
+  int64_t n_slots = 0;      // partial-sum slots
+  std::vector<int32_t> order;        // tile ids: regular tiles, then tiles with hanging cells
+  std::vector<int32_t> tile_info;    // TILE_STRIDE ints per tile, see TILE_* below
+  std::vector<int32_t> shared;       // global ids of each tile's shared local nodes
+  std::vector<int32_t> shared_ptr;   // n_shared + 1 offsets into shared_slot
+  std::vector<int32_t> shared_slot;  // slots of a shared node, ascending tile order
+  // cell footprints in local ids, (p+1)^2 per cell record: the cell's own
+  // nodes (hanging nodes included), and the same with the slots of a hanging
+  // face replaced by the nodes of the coarse face (per-cell constraint form)
+  std::vector<uint16_t> cell_loc;
+  std::vector<uint16_t> cell_loc_sub;
+  std::vector<uint16_t> cell_info;   // info word per cell record
   int64_t n_cell_records = 0;
+  // hanging nodes of a tile, one record each: local id of the hanging node
+  // and of its p+1 masters (unused slots repeat master 0 with weight 0),
+  // weights, and a colour such that records of one colour share no master
+  std::vector<uint16_t> hang_rec;    // 4 per record
+  std::vector<double> hang_w;        // 3 per record
+  std::vector<uint8_t> hang_col;     // 1 per record
+  int max_hang_colors = 0;
 };
-enum { TILE_OWNED0 = 0, TILE_NOWNED, TILE_HALO0, TILE_NHALO, TILE_CELL0, TILE_NCELL, TILE_NCOLOR, TILE_PAD };
+// Per tile: private node range, shared local node list, cell records, number
+// of cell colours, first partial-sum slot (slots are consecutive per tile),
+// hanging-node records and their number of colours.
+enum {
+  TILE_OWNED0 = 0, TILE_NOWNED, TILE_SHARED0, TILE_NSHARED, TILE_CELL0, TILE_NCELL, TILE_NCOLOR, TILE_SLOT0,
+  TILE_HANG0, TILE_NHANG, TILE_NHCOLOR, TILE_PAD, TILE_STRIDE
+};
 
 // A CSR matrix with double weights (exact dyadic values).
 struct Csr {
@@ -84,7 +111,7 @@ struct MeshSpec {
   int coarse = 16;
   double band_x = 2.0;
   double band_y = 0.5;
-  int tile_x = 0;  // owned cells per tile (0 = default for the degree)
+  int tile_x = 0;  // cells per tile in x (0 = default for the degree)
   int tile_y = 0;
 };
 

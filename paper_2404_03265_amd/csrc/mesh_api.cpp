@@ -122,4 +122,36 @@ int pff_mesh_tile_stats(const pff_mesh* m, int32_t level, int64_t* n_tiles, int6
   return PFF_OK;
 }
 
+int pff_mesh_tile_tables(const pff_mesh* m, int32_t level, int64_t* sizes, int32_t* tile_info, int32_t* shared,
+                         int32_t* shared_ptr, int32_t* shared_slot, uint16_t* cell_loc, uint16_t* cell_loc_sub,
+                         uint16_t* cell_info, int32_t* order, uint16_t* hang_rec, double* hang_w, uint8_t* hang_col) {
+  if (bad_level(m, level) || !sizes) return PFF_E_ARG;
+  const pff::TileSet& t = level < 0 ? m->m.tiles : m->m.levels[level].tiles;
+  sizes[0] = t.n_tiles;
+  sizes[1] = int64_t(t.shared.size());
+  sizes[2] = t.n_private;
+  sizes[3] = t.n_shared;
+  sizes[4] = t.n_slots;
+  sizes[5] = t.n_cell_records;
+  sizes[6] = t.n_regular;
+  sizes[7] = t.max_local;
+  sizes[8] = int64_t(t.hang_col.size());
+  sizes[9] = t.max_hang_colors;
+  auto put = [](auto* dst, const auto& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+  };
+  put(tile_info, t.tile_info);
+  put(shared, t.shared);
+  put(shared_ptr, t.shared_ptr);
+  put(shared_slot, t.shared_slot);
+  put(cell_loc, t.cell_loc);
+  put(cell_loc_sub, t.cell_loc_sub);
+  put(cell_info, t.cell_info);
+  put(order, t.order);
+  put(hang_rec, t.hang_rec);
+  put(hang_w, t.hang_w);
+  put(hang_col, t.hang_col);
+  return PFF_OK;
+}
+
 }  // extern "C"

@@ -32,11 +32,17 @@ struct DevTiles {
   int32_t* order = nullptr;
   int n_regular = 0;
   int32_t* info = nullptr;
-  int32_t* halo = nullptr;
+  int32_t* shared = nullptr;
+  int32_t* sh_ptr = nullptr;
+  int32_t* sh_slot = nullptr;
   uint16_t* loc = nullptr;
+  uint16_t* loc_sub = nullptr;
   uint16_t* cinfo = nullptr;
-  int n_tiles = 0, max_local = 0, max_owned = 0, max_cells = 0, typ_cells = 0;
-  int64_t n_rec = 0;
+  uint16_t* hang_rec = nullptr;
+  double* hang_w = nullptr;
+  uint8_t* hang_col = nullptr;
+  int n_tiles = 0, max_local = 0, max_cells = 0;
+  int64_t n_rec = 0, n_private = 0, n_shared = 0, n_slots = 0;
 };
 
 template <typename T>
@@ -128,15 +134,22 @@ DevTiles upload_tiles(const TileSet& t) {
   d.info = upload(t.tile_info);
   d.order = upload(t.order);
   d.n_regular = t.n_regular;
-  d.halo = upload(t.halo);
+  d.shared = upload(t.shared);
+  d.sh_ptr = upload(t.shared_ptr);
+  d.sh_slot = upload(t.shared_slot);
   d.loc = upload(t.cell_loc);
+  d.loc_sub = upload(t.cell_loc_sub);
   d.cinfo = upload(t.cell_info);
+  d.hang_rec = upload(t.hang_rec);
+  d.hang_w = upload(t.hang_w);
+  d.hang_col = upload(t.hang_col);
   d.n_tiles = t.n_tiles;
   d.max_local = t.max_local;
-  d.max_owned = t.max_owned;
   d.max_cells = t.max_cells;
-  d.typ_cells = t.typ_cells;
   d.n_rec = t.n_cell_records;
+  d.n_private = t.n_private;
+  d.n_shared = t.n_shared;
+  d.n_slots = t.n_slots;
   return d;
 }
 
@@ -166,6 +179,8 @@ struct pff_ctx {
   double* red_out = nullptr;
   double* host_red = nullptr;   // pinned
   double* V = nullptr;          // GMRES basis
+  void* part = nullptr;         // partial sums of shared nodes (largest tile set)
+  size_t part_bytes = 0;
   int V_cap = 0;
   bool has_state = false;
   bool mg_ready = false;
@@ -189,48 +204,51 @@ struct pff_ctx {
   template <typename T, int MODE, int EPI>
   void launch_tile(const DevTiles& t, const uint8_t* fl, int64_t nn, TileArgs<T>& a) {
     a.tile_info = t.info;
-    a.halo = t.halo;
+    a.shared = t.shared;
     a.cell_loc = t.loc;
+    a.cell_loc_sub = t.loc_sub;
     a.cell_info = t.cinfo;
+    a.hang_rec = t.hang_rec;
+    a.hang_w = t.hang_w;
+    a.hang_col = t.hang_col;
     a.flags = fl;
     a.n = nn;
     a.max_local = t.max_local;
-    a.max_owned = t.max_owned;
+    a.part = reinterpret_cast<T*>(part);
+    a.n_slots = t.n_slots;
+    a.n_private = t.n_private;
+    a.n_shared = t.n_shared;
+    a.sh_ptr = t.sh_ptr;
+    a.sh_slot = t.sh_slot;
     a.H0 = T(mesh.level_H[0]);
     a.B = make_basis<T>(p);
     a.mat = mat();
     using TR = ModeTraits<MODE>;
     constexpr int NF = TR::n_src + TR::n_state;
-    const size_t lds = size_t((NF > 0 ? NF : 1) * t.max_local + 3 * t.max_owned) * sizeof(T) +
-                       size_t(t.max_local);   // node flags
-    // one thread per cell of a typical tile; larger tiles loop over their cells
-    int threads = ((std::min(std::max(t.typ_cells, 1), 256) + 63) / 64) * 64;
-    threads = std::max(64, threads);
+    // staged fields, three accumulators, node flags
+    const size_t lds = size_t(((NF > 0 ? NF : 1) + 3) * t.max_local) * sizeof(T) + size_t(t.max_local);
+    // one thread per cell of the largest tile
+    const int threads = std::max(64, ((t.max_cells + 63) / 64) * 64);
+    if (threads > 256) throw std::runtime_error("a tile holds at most 256 cells");
+    if (size_t(3 * t.n_slots) * sizeof(T) > part_bytes) throw std::runtime_error("partial-sum buffer too small");
     a.tile_order = t.order;
     if (lds > size_t(160 * 1024)) throw std::runtime_error("tile needs more LDS than a CU has; use smaller tiles");
-    if (lds > size_t(64 * 1024)) {
-      const void* k0 = p == 1 ? reinterpret_cast<const void*>(&tile_kernel<1, T, MODE, EPI, false>)
-                              : reinterpret_cast<const void*>(&tile_kernel<2, T, MODE, EPI, false>);
-      const void* k1 = p == 1 ? reinterpret_cast<const void*>(&tile_kernel<1, T, MODE, EPI, true>)
-                              : reinterpret_cast<const void*>(&tile_kernel<2, T, MODE, EPI, true>);
-      HIPCHK(hipFuncSetAttribute(k0, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-      HIPCHK(hipFuncSetAttribute(k1, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-    }
-    const int nreg = t.n_regular, nhang = t.n_tiles - t.n_regular;
-    if (nreg > 0) {
-      a.tile_base = 0;
+    // hanging nodes are handled on the tile's nodes; only the inverse
+    // diagonal runs the per-cell constraint form
+    constexpr bool HANG = (MODE == MODE_DIAG_LEAF);
+    const void* kfn = p == 1 ? reinterpret_cast<const void*>(&tile_kernel<1, T, MODE, EPI, HANG>)
+                             : reinterpret_cast<const void*>(&tile_kernel<2, T, MODE, EPI, HANG>);
+    if (lds > size_t(64 * 1024))
+      HIPCHK(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    a.tile_base = 0;
+    if (t.n_tiles > 0) {
       if (p == 1)
-        hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI, false>), dim3(nreg), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI, HANG>), dim3(t.n_tiles), dim3(threads), lds, s, a);
       else
-        hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI, false>), dim3(nreg), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI, HANG>), dim3(t.n_tiles), dim3(threads), lds, s, a);
     }
-    if (nhang > 0) {
-      a.tile_base = nreg;
-      if (p == 1)
-        hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI, true>), dim3(nhang), dim3(threads), lds, s, a);
-      else
-        hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI, true>), dim3(nhang), dim3(threads), lds, s, a);
-    }
+    if (t.n_shared > 0)
+      hipLaunchKernelGGL((shared_fixup<T, MODE, EPI>), dim3(grid_for(t.n_shared)), dim3(256), 0, s, a);
     HIPCHK(hipGetLastError());
   }
 
@@ -721,7 +739,13 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
       params->gmres_restart > 60 || params->coarse_mode != 0)
     return PFF_E_ARG;
   try {
-    if (!c->mesh.build(ms)) {
+    bool built = false;
+    try {
+      built = c->mesh.build(ms);
+    } catch (const std::runtime_error& e) {
+      c->mesh.error = e.what();
+    }
+    if (!built) {
       static thread_local std::string msg;
       msg = c->mesh.error;
       return PFF_E_MESH;
@@ -758,6 +782,10 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
     c->phit = dalloc<double>(n);
     c->mass = dalloc<double>(3 * n);
     for (int i = 0; i < 8; ++i) c->wv[i] = dalloc<double>(3 * n);
+    int64_t slots = c->mesh.tiles.n_slots;
+    for (const Level& L : c->mesh.levels) slots = std::max(slots, L.tiles.n_slots);
+    c->part_bytes = size_t(3 * std::max<int64_t>(slots, 1)) * sizeof(double);
+    c->part = dalloc<double>(3 * std::max<int64_t>(slots, 1));
     c->red_part = dalloc<double>(RED_BLOCKS * 64);
     c->red_out = dalloc<double>(256);
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->host_red), 256 * sizeof(double), hipHostMallocDefault));
@@ -776,7 +804,10 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
 int pff_destroy(pff_ctx* c) {
   if (!c) return PFF_E_ARG;
   auto f = [](void* p) { if (p) hipFree(p); };
-  auto ft = [&](DevTiles& t) { f(t.order); f(t.info); f(t.halo); f(t.loc); f(t.cinfo); };
+  auto ft = [&](DevTiles& t) {
+    f(t.order); f(t.info); f(t.shared); f(t.sh_ptr); f(t.sh_slot); f(t.loc); f(t.loc_sub); f(t.cinfo);
+    f(t.hang_rec); f(t.hang_w); f(t.hang_col);
+  };
   ft(c->tiles);
   f(c->flags);
   f(c->hang);
@@ -791,7 +822,7 @@ int pff_destroy(pff_ctx* c) {
   }
   f(c->U); f(c->phio); f(c->phit); f(c->mass);
   for (int i = 0; i < 8; ++i) f(c->wv[i]);
-  f(c->red_part); f(c->red_out); f(c->V);
+  f(c->red_part); f(c->red_out); f(c->V); f(c->part);
   if (c->host_red) hipHostFree(c->host_red);
   delete c;
   return PFF_OK;

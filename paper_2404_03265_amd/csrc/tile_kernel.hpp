@@ -1,18 +1,18 @@
-// Owner-computes tile kernel for every cell-based operator of the solver.
+// Cell-partition tile kernel for every cell-based operator of the solver.
 //
-// A tile owns a contiguous range of nodes and lists every cell whose
-// footprint touches them (its own cells plus a ring of halo cells). One
-// workgroup per tile:
-//   1. stage the tile's local nodes (owned range, then halo list) into LDS,
-//      masking constrained columns;
-//   2. one thread per cell: gather the cell's nodal values from LDS, apply
-//      hanging-node interpolation, run the sum-factorised pointwise law,
-//      integrate, apply the transposed hanging-node map;
-//   3. colour-phased accumulation into LDS accumulators of the owned nodes
-//      (cells of one colour share no owned node: deterministic, no atomics);
-//   4. one coalesced write of the owned nodes through the mode's epilogue.
-// Contributions of halo cells to nodes owned by other tiles are recomputed
-// there and dropped here, so every output is written exactly once.
+// The tiles partition the cells (one block of cells of one refinement level
+// per tile). One workgroup per tile, one thread per cell:
+//   1. stage the tile's local nodes (private range, then shared list) into
+//      LDS, masking constrained columns;
+//   2. each thread gathers its cell's nodal values from LDS, applies the
+//      hanging-node interpolation, runs the sum-factorised pointwise law,
+//      integrates and applies the transposed hanging-node map;
+//   3. colour-phased accumulation into LDS accumulators over all local nodes
+//      (cells of one colour share no node: deterministic, no atomics);
+//   4. private nodes are complete and go through the mode's epilogue in one
+//      coalesced write; shared nodes leave a partial sum in the tile's slots,
+//      which shared_fixup adds in ascending tile order before the epilogue.
+// Every cell is evaluated exactly once and every output written once.
 #pragma once
 
 #include "cell.hpp"
@@ -41,13 +41,25 @@ struct TileArgs {
   const int32_t* tile_order;   // tile ids; this launch handles tile_order[tile_base + blockIdx.x]
   int tile_base;
   const int32_t* tile_info;
-  const int32_t* halo;
-  const uint16_t* cell_loc;
+  const int32_t* shared;       // global ids of the tiles' shared local nodes
+  const uint16_t* cell_loc;       // own nodes per cell (hanging nodes included)
+  const uint16_t* cell_loc_sub;   // hanging faces replaced by the coarse face's nodes
   const uint16_t* cell_info;
+  // hanging nodes per tile: (node, masters) local ids, weights, colour
+  const uint16_t* hang_rec;
+  const double* hang_w;
+  const uint8_t* hang_col;
   const uint8_t* flags;
   int64_t n;
   int max_local;
-  int max_owned;
+  // shared nodes: partial sums, [3][n_slots]; slots of shared node s are
+  // sh_slot[sh_ptr[s] .. sh_ptr[s + 1]) in ascending tile order
+  T* part;
+  int64_t n_slots;
+  int64_t n_private;
+  int64_t n_shared;
+  const int32_t* sh_ptr;
+  const int32_t* sh_slot;
   T H0;             // cell edge on level 0; level l has H0 / 2^l
   Basis<T> B;
   Material mat;
@@ -77,56 +89,108 @@ struct ModeTraits {
   static constexpr bool mask_src = (MODE == MODE_J || MODE == MODE_JT || MODE == MODE_LEVEL);
 };
 
+// Output of one node component: private nodes in the tile kernel, shared
+// nodes in shared_fixup. v is the accumulated cell sum of row i = c n + g.
+template <int MODE, int EPI, typename T>
+__device__ __forceinline__ void node_epilogue(const TileArgs<T>& a, int c, int64_t g, uint8_t f, T v) {
+  const int64_t i = c * a.n + g;
+  if constexpr (MODE == MODE_J || MODE == MODE_JT) {
+    const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
+    a.dst[i] = cons ? a.src[i] : v;
+  } else if constexpr (MODE == MODE_LEVEL) {
+    if constexpr (EPI == EPI_PLAIN) {
+      a.dst[i] = v;
+    } else if constexpr (EPI == EPI_RESID) {
+      // residual to restrict: zero on rows held at zero on this level
+      const bool held = (c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
+      a.dst[i] = held ? T(0) : a.b[i] - v;
+    } else {
+      const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
+      const int blk = c < 2 ? 0 : 1;
+      const T x = a.src[i];
+      if (fixed) {
+        a.dst[i] = T(0);
+        a.xnew[i] = x;
+      } else {
+        const T r = a.b[i] - v;
+        const T dp = a.dold ? a.dold[i] : T(0);
+        const T dn = a.c1[blk] * dp + a.c2[blk] * a.dinv[i] * r;
+        a.dst[i] = dn;
+        a.xnew[i] = x + dn;
+      }
+    }
+  } else if constexpr (MODE == MODE_RESID) {
+    a.dst[i] = (f & NODE_HANGING) ? T(0) : -v;
+  } else if constexpr (MODE == MODE_DIAG_LEAF) {
+    const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
+    a.dst[i] = cons ? T(1) : T(1) / v;
+  } else if constexpr (MODE == MODE_DIAG_LEVEL) {
+    const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
+    a.dst[i] = fixed ? T(0) : T(1) / v;
+  } else {
+    a.dst[i] = (f & NODE_HANGING) ? T(0) : v;
+  }
+}
+
 template <int P, typename T, int MODE, int EPI, bool HANG>
 __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
   using TR = ModeTraits<MODE>;
   constexpr int NF = TR::n_src + TR::n_state;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lds = reinterpret_cast<T*>(smem_raw);
   const int ML = a.max_local;
-  T* acc = lds + (NF > 0 ? NF : 1) * ML;   // [3][max_owned]
-  const int MO = a.max_owned;
+  T* lds = reinterpret_cast<T*>(smem_raw);   // staged fields [NF][max_local]
+  T* acc = lds + (NF > 0 ? NF : 1) * ML;     // accumulators [3][max_local]
+  uint8_t* lflag = reinterpret_cast<uint8_t*>(acc + 3 * ML);   // [max_local]
 
   // XCD-aware order: workgroups go to the 8 XCDs round-robin, so XCD x
   // receives a contiguous chunk of the tile list and neighbouring tiles (which
-  // share halo nodes) run on the same XCD and hit the same L2.
+  // share nodes) run on the same XCD and hit the same L2.
   const int nb = int(gridDim.x), bid = int(blockIdx.x);
   const int xq = nb >> 3, xr = nb & 7, xcd = bid & 7;
   const int order_idx = xcd * xq + (xcd < xr ? xcd : xr) + (bid >> 3);
   const int tile = a.tile_order[a.tile_base + order_idx];
-  const int32_t* ti = a.tile_info + 8 * tile;
+  const int32_t* ti = a.tile_info + TILE_STRIDE * tile;
   const int o0 = ti[TILE_OWNED0], no = ti[TILE_NOWNED];
-  const int h0 = ti[TILE_HALO0], nh = ti[TILE_NHALO];
+  const int s0 = ti[TILE_SHARED0], ns = ti[TILE_NSHARED];
   const int c0 = ti[TILE_CELL0], nc = ti[TILE_NCELL];
   const int ncol = ti[TILE_NCOLOR];
-  const int nloc = no + nh;
+  const int slot0 = ti[TILE_SLOT0];
+  // Hanging nodes: every mode but the inverse diagonal applies the
+  // constraints on the tile's nodes (interpolate after staging, distribute
+  // after accumulation); the inverse diagonal needs the per-cell form.
+  constexpr bool NODE_HANG = TR::leaf && MODE != MODE_DIAG_LEAF;
+  const int hr0 = NODE_HANG ? ti[TILE_HANG0] : 0, nhang = NODE_HANG ? ti[TILE_NHANG] : 0;
+  const int nhcol = NODE_HANG ? ti[TILE_NHCOLOR] : 0;
+  const int nloc = no + ns;
   const int64_t n = a.n;
   const Material& m = a.mat;
   const T kap = T(m.kappa), pr = T(m.pressure), Gc = T(m.Gc), ell = T(m.ell);
   const T mu = T(m.mu), lam = T(m.lam);
 
-  // cell records of the first round are loaded before staging so that their
-  // latency overlaps with the node loads
-  int loc0[NL];
-  unsigned info0 = 0;
-  if (int(threadIdx.x) < nc) {
-    const int64_t rec = int64_t(c0) + threadIdx.x;
+  // the cell record is loaded before staging so that its latency overlaps
+  // with the node loads
+  const int cell = int(threadIdx.x);
+  const bool live = cell < nc;
+  int loc[NL];
+  unsigned info = 0;
+  if (live) {
+    const int64_t rec = int64_t(c0) + cell;
+    const uint16_t* cl = (MODE == MODE_DIAG_LEAF) ? a.cell_loc_sub : a.cell_loc;
 #pragma unroll
-    for (int k = 0; k < NL; ++k) loc0[k] = a.cell_loc[rec * NL + k];
-    info0 = a.cell_info[rec];
+    for (int k = 0; k < NL; ++k) loc[k] = cl[rec * NL + k];
+    info = a.cell_info[rec];
   }
 
   // 1. stage local nodes: all global loads of a batch are issued before any
-  //    LDS store (one dependent round trip for halo ids, one for the values)
-  uint8_t* lflag = reinterpret_cast<uint8_t*>(acc + 3 * MO);   // [max_local]
-  constexpr int SLOTS = 4;   // local nodes per thread and batch (larger tiles take several batches)
+  //    LDS store (one dependent round trip for shared ids, one for the values)
+  constexpr int SLOTS = 4;   // local nodes per thread and batch
   for (int base = 0; base < nloc; base += SLOTS * int(blockDim.x)) {
     int64_t gs[SLOTS];
 #pragma unroll
     for (int k = 0; k < SLOTS; ++k) {
       const int l = base + k * int(blockDim.x) + int(threadIdx.x);
-      gs[k] = l < no ? int64_t(o0 + l) : (l < nloc ? int64_t(a.halo[h0 + l - no]) : int64_t(-1));
+      gs[k] = l < no ? int64_t(o0 + l) : (l < nloc ? int64_t(a.shared[s0 + l - no]) : int64_t(-1));
     }
     uint8_t fs[SLOTS];
     T vs[SLOTS][NF > 0 ? NF : 1];
@@ -166,37 +230,42 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       }
     }
   }
-  for (int l = threadIdx.x; l < 3 * MO; l += blockDim.x) acc[l] = T(0);
+  for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
+    acc[l] = T(0);
+    acc[ML + l] = T(0);
+    acc[2 * ML + l] = T(0);
+  }
   __syncthreads();
+  if constexpr (NODE_HANG && NF > 0) {
+    if (nhang > 0) {
+      // values at hanging nodes from their masters (masters are never hanging)
+      for (int r = threadIdx.x; r < nhang; r += blockDim.x) {
+        const uint16_t* hr = a.hang_rec + 4 * int64_t(hr0 + r);
+        const double* hw = a.hang_w + 3 * int64_t(hr0 + r);
+        const int h = hr[0], m0 = hr[1], m1 = hr[2], m2 = hr[3];
+        const T w0 = T(hw[0]), w1 = T(hw[1]), w2 = T(hw[2]);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          lds[f * ML + h] = w0 * lds[f * ML + m0] + w1 * lds[f * ML + m1] + w2 * lds[f * ML + m2];
+      }
+      __syncthreads();
+    }
+  }
 
-  // 2./3. cells, colour-phased accumulation
-  for (int base = 0; base < nc; base += blockDim.x) {
-    const int cell = base + threadIdx.x;
-    const bool live = cell < nc;
+  // 2./3. one cell per thread, colour-phased accumulation
+  {
     T out[3][NL];
-    int loc[NL];
-    unsigned info = 0;
     int color = -1;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int k = 0; k < NL; ++k) out[c][k] = T(0);
     if (live) {
-      if (base == 0) {
-#pragma unroll
-        for (int k = 0; k < NL; ++k) loc[k] = loc0[k];
-        info = info0;
-      } else {
-        const int64_t rec = int64_t(c0) + cell;
-#pragma unroll
-        for (int k = 0; k < NL; ++k) loc[k] = a.cell_loc[rec * NL + k];
-        info = a.cell_info[rec];
-      }
       color = int((info >> CELL_COLOR_SHIFT) & 15u);
       const int lev = int((info >> CELL_LEVEL_SHIFT) & 31u);
       const T H = T(ldexp(double(a.H0), -lev));
-      // tiles without hanging-face cells run the HANG = false instantiation
-      const bool hang = HANG && TR::leaf && (info & 15u);
+      // per-cell constraint form (inverse diagonal only)
+      const bool hang = HANG && MODE == MODE_DIAG_LEAF && (info & 15u);
       auto gather = [&](int field, T(&u)[NL]) {
 #pragma unroll
         for (int k = 0; k < NL; ++k) u[k] = lds[field * ML + loc[k]];
@@ -468,72 +537,74 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         }
         integrate<P, T>(a.B, f, zero, zero, out[2]);
       }
-      if (hang && MODE != MODE_DIAG_LEAF) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) hang_apply_T<P, T>(a.B, out[c], info);
-      }
     }
+    // LDS atomic adds without return: no read-modify-write round trip per
+    // entry. Within a phase no two lanes address the same node, and one
+    // lane's adds execute in program order, so the summation order is fixed.
     for (int col = 0; col < ncol; ++col) {
-      __syncthreads();
       if (live && color == col) {
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
           const int l = loc[k];
-          if (l < no) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc[c * MO + l] += out[c][k];
-          }
+          for (int c = 0; c < 3; ++c)
+            __hip_atomic_fetch_add(&acc[c * ML + l], out[c][k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
+      __syncthreads();
     }
   }
-  __syncthreads();
+  if constexpr (NODE_HANG) {
+    // contributions at hanging nodes go to their masters; records of one
+    // colour share no master
+    for (int col = 0; col < nhcol; ++col) {
+      for (int r = threadIdx.x; r < nhang; r += blockDim.x) {
+        if (a.hang_col[hr0 + r] != col) continue;
+        const uint16_t* hr = a.hang_rec + 4 * int64_t(hr0 + r);
+        const double* hw = a.hang_w + 3 * int64_t(hr0 + r);
+        const int h = hr[0];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T v = acc[c * ML + h];
+#pragma unroll
+          for (int k = 0; k <= P; ++k)
+            __hip_atomic_fetch_add(&acc[c * ML + hr[1 + k]], T(hw[k]) * v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+      __syncthreads();
+    }
+  }
 
-  // 4. epilogue over owned nodes
+  // 4. private nodes through the epilogue, shared nodes into the tile's slots
   for (int l = threadIdx.x; l < no; l += blockDim.x) {
-    const int64_t g = o0 + l;
     const uint8_t f = lflag[l];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T v = acc[c * MO + l];
-      const int64_t i = c * n + g;
-      if constexpr (MODE == MODE_J || MODE == MODE_JT) {
-        const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
-        a.dst[i] = cons ? a.src[i] : v;
-      } else if constexpr (MODE == MODE_LEVEL) {
-        if constexpr (EPI == EPI_PLAIN) {
-          a.dst[i] = v;
-        } else if constexpr (EPI == EPI_RESID) {
-          // residual to restrict: zero on rows held at zero on this level
-          const bool held = (c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
-          a.dst[i] = held ? T(0) : a.b[i] - v;
-        } else {
-          const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
-          const int blk = c < 2 ? 0 : 1;
-          const T x = a.src[i];
-          if (fixed) {
-            a.dst[i] = T(0);
-            a.xnew[i] = x;
-          } else {
-            const T r = a.b[i] - v;
-            const T dp = a.dold ? a.dold[i] : T(0);
-            const T dn = a.c1[blk] * dp + a.c2[blk] * a.dinv[i] * r;
-            a.dst[i] = dn;
-            a.xnew[i] = x + dn;
-          }
-        }
-      } else if constexpr (MODE == MODE_RESID) {
-        a.dst[i] = (f & NODE_HANGING) ? T(0) : -v;
-      } else if constexpr (MODE == MODE_DIAG_LEAF) {
-        const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
-        a.dst[i] = cons ? T(1) : T(1) / v;
-      } else if constexpr (MODE == MODE_DIAG_LEVEL) {
-        const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
-        a.dst[i] = fixed ? T(0) : T(1) / v;
-      } else {
-        a.dst[i] = (f & NODE_HANGING) ? T(0) : v;
-      }
+    for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, T>(a, c, int64_t(o0) + l, f, acc[c * ML + l]);
+  }
+  for (int r = threadIdx.x; r < ns; r += blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.part[c * a.n_slots + slot0 + r] = acc[c * ML + no + r];
+  }
+}
+
+// Shared nodes: add the partial sums of every tile touching the node in
+// ascending tile order, then apply the mode's epilogue.
+template <typename T, int MODE, int EPI>
+__global__ void __launch_bounds__(256) shared_fixup(const TileArgs<T> a) {
+  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < a.n_shared;
+       s += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t g = a.n_private + s;
+    const int j0 = a.sh_ptr[s], j1 = a.sh_ptr[s + 1];
+    const uint8_t f = a.flags[g];
+    T v[3] = {T(0), T(0), T(0)};
+    for (int j = j0; j < j1; ++j) {
+      const int64_t slot = a.sh_slot[j];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c] += a.part[c * a.n_slots + slot];
     }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, T>(a, c, g, f, v[c]);
   }
 }
 

@@ -80,3 +80,27 @@ class HostMesh:
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
         self.lib.pff_mesh_tile_stats(self.h, level, C.byref(a), C.byref(b), C.byref(c))
         return a.value, b.value, c.value
+
+    def tile_tables(self, level=-1):
+        """Tile tables as the device kernels read them (see pff_mesh_tile_tables)."""
+        sz = np.zeros(10, dtype=np.int64)
+        assert self.lib.pff_mesh_tile_tables(self.h, level, _np(sz), *([None] * 12)) == 0
+        n_tiles, n_sh_list, n_priv, n_sh, n_slots, n_rec, n_reg, max_local, n_hang, max_hcol = (int(v) for v in sz)
+        nl = (self.degree + 1) ** 2
+        t = dict(n_tiles=n_tiles, n_private=n_priv, n_shared=n_sh, n_slots=n_slots, n_regular=n_reg,
+                 max_local=max_local, max_hang_colors=max_hcol,
+                 tile_info=np.zeros((n_tiles, 12), dtype=np.int32),
+                 shared=np.zeros(n_sh_list, dtype=np.int32),
+                 shared_ptr=np.zeros(n_sh + 1, dtype=np.int32),
+                 shared_slot=np.zeros(n_slots, dtype=np.int32),
+                 cell_loc=np.zeros((n_rec, nl), dtype=np.uint16),
+                 cell_loc_sub=np.zeros((n_rec, nl), dtype=np.uint16),
+                 cell_info=np.zeros(n_rec, dtype=np.uint16),
+                 order=np.zeros(n_tiles, dtype=np.int32),
+                 hang_rec=np.zeros((n_hang, 4), dtype=np.uint16),
+                 hang_w=np.zeros((n_hang, 3)),
+                 hang_col=np.zeros(n_hang, dtype=np.uint8))
+        keys = ("tile_info", "shared", "shared_ptr", "shared_slot", "cell_loc", "cell_loc_sub", "cell_info",
+                "order", "hang_rec", "hang_w", "hang_col")
+        assert self.lib.pff_mesh_tile_tables(self.h, level, _np(sz), *[_np(t[k]) for k in keys]) == 0
+        return t
