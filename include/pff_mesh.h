@@ -49,7 +49,8 @@ int pff_mesh_tile_stats(const pff_mesh* m, int32_t level, int64_t* n_tiles, int6
  * tile_info (12 per tile: private start, private count, shared-list start,
  * shared count, first cell record, cell count, cell colours, first slot,
  * first hanging record, hanging records, hanging colours, unused), shared
- * (global ids), shared_ptr (n_shared + 1), shared_slot (n_slots), cell_loc and
+ * (global ids), shared_ptr (n_shared + 1), shared_slot (n_slots: slots of each
+ * shared node in ascending tile order; slots are tile-major), cell_loc and
  * cell_loc_sub ((p+1)^2 per record, local ids: private nodes first, then the
  * tile's shared list; own nodes, and with hanging faces replaced by the coarse
  * face's nodes), cell_info (per record), order (n_tiles: tiles without

@@ -240,6 +240,9 @@ void build_tiles(int p, int n_tiles, const std::vector<int32_t>& fp, const std::
     T.max_owned = std::max<int>(T.max_owned, no);
     T.max_local = std::max<int>(T.max_local, nloc);
   }
+  // slots are tile-major (a tile writes its partial sums contiguously); the
+  // fix-up reads the slots of shared node s from shared_slot in ascending
+  // tile order
   T.n_slots = slot0;
   T.shared_ptr.assign(size_t(T.n_shared) + 1, 0);
   T.shared_slot.clear();

@@ -71,8 +71,9 @@ struct TileSet {
   int max_hang_colors = 0;
 };
 // Per tile: private node range, shared local node list, cell records, number
-// of cell colours, first partial-sum slot (slots are consecutive per tile),
-// hanging-node records and their number of colours.
+// of cell colours, first partial-sum slot (slots are consecutive per tile:
+// entry r of the tile's shared list writes slot TILE_SLOT0 + r), hanging-node
+// records and their number of colours.
 enum {
   TILE_OWNED0 = 0, TILE_NOWNED, TILE_SHARED0, TILE_NSHARED, TILE_CELL0, TILE_NCELL, TILE_NCOLOR, TILE_SLOT0,
   TILE_HANG0, TILE_NHANG, TILE_NHCOLOR, TILE_PAD, TILE_STRIDE

@@ -29,7 +29,6 @@ namespace {
   } while (0)
 
 struct DevTiles {
-  int32_t* order = nullptr;
   int n_regular = 0;
   int32_t* info = nullptr;
   int32_t* shared = nullptr;
@@ -132,7 +131,6 @@ T* upload(const std::vector<T>& v) {
 DevTiles upload_tiles(const TileSet& t) {
   DevTiles d;
   d.info = upload(t.tile_info);
-  d.order = upload(t.order);
   d.n_regular = t.n_regular;
   d.shared = upload(t.shared);
   d.sh_ptr = upload(t.shared_ptr);
@@ -231,7 +229,6 @@ struct pff_ctx {
     const int threads = std::max(64, ((t.max_cells + 63) / 64) * 64);
     if (threads > 256) throw std::runtime_error("a tile holds at most 256 cells");
     if (size_t(3 * t.n_slots) * sizeof(T) > part_bytes) throw std::runtime_error("partial-sum buffer too small");
-    a.tile_order = t.order;
     if (lds > size_t(160 * 1024)) throw std::runtime_error("tile needs more LDS than a CU has; use smaller tiles");
     // hanging nodes are handled on the tile's nodes; only the inverse
     // diagonal runs the per-cell constraint form
@@ -805,7 +802,7 @@ int pff_destroy(pff_ctx* c) {
   if (!c) return PFF_E_ARG;
   auto f = [](void* p) { if (p) hipFree(p); };
   auto ft = [&](DevTiles& t) {
-    f(t.order); f(t.info); f(t.shared); f(t.sh_ptr); f(t.sh_slot); f(t.loc); f(t.loc_sub); f(t.cinfo);
+    f(t.info); f(t.shared); f(t.sh_ptr); f(t.sh_slot); f(t.loc); f(t.loc_sub); f(t.cinfo);
     f(t.hang_rec); f(t.hang_w); f(t.hang_col);
   };
   ft(c->tiles);

@@ -38,8 +38,7 @@ enum Epi : int { EPI_PLAIN = 0, EPI_RESID = 1, EPI_CHEB = 2 };
 
 template <typename T>
 struct TileArgs {
-  const int32_t* tile_order;   // tile ids; this launch handles tile_order[tile_base + blockIdx.x]
-  int tile_base;
+  int tile_base;               // this launch handles tiles tile_base + [0, gridDim.x)
   const int32_t* tile_info;
   const int32_t* shared;       // global ids of the tiles' shared local nodes
   const uint16_t* cell_loc;       // own nodes per cell (hanging nodes included)
@@ -52,8 +51,8 @@ struct TileArgs {
   const uint8_t* flags;
   int64_t n;
   int max_local;
-  // shared nodes: partial sums, [3][n_slots]; slots of shared node s are
-  // sh_slot[sh_ptr[s] .. sh_ptr[s + 1]) in ascending tile order
+  // shared nodes: partial sums, [3][n_slots], tile-major; the slots of
+  // shared node s are sh_slot[sh_ptr[s] .. sh_ptr[s + 1]) in ascending tile order
   T* part;
   int64_t n_slots;
   int64_t n_private;
@@ -91,12 +90,18 @@ struct ModeTraits {
 
 // Output of one node component: private nodes in the tile kernel, shared
 // nodes in shared_fixup. v is the accumulated cell sum of row i = c n + g.
-template <int MODE, int EPI, typename T>
+// With EARLY (private nodes of the tile kernel), the identity rows of the
+// Jacobian modes were already written while staging and are skipped here.
+template <int MODE, int EPI, bool EARLY, typename T>
 __device__ __forceinline__ void node_epilogue(const TileArgs<T>& a, int c, int64_t g, uint8_t f, T v) {
   const int64_t i = c * a.n + g;
   if constexpr (MODE == MODE_J || MODE == MODE_JT) {
     const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
-    a.dst[i] = cons ? a.src[i] : v;
+    if (EARLY) {
+      if (!cons) a.dst[i] = v;
+    } else {
+      a.dst[i] = cons ? a.src[i] : v;
+    }
   } else if constexpr (MODE == MODE_LEVEL) {
     if constexpr (EPI == EPI_PLAIN) {
       a.dst[i] = v;
@@ -141,7 +146,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   const int ML = a.max_local;
   T* lds = reinterpret_cast<T*>(smem_raw);   // staged fields [NF][max_local]
   T* acc = lds + (NF > 0 ? NF : 1) * ML;     // accumulators [3][max_local]
-  uint8_t* lflag = reinterpret_cast<uint8_t*>(acc + 3 * ML);   // [max_local]
+  uint8_t* lflag = reinterpret_cast<uint8_t*>(acc + 3 * ML);     // [max_local]
 
   // XCD-aware order: workgroups go to the 8 XCDs round-robin, so XCD x
   // receives a contiguous chunk of the tile list and neighbouring tiles (which
@@ -149,7 +154,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   const int nb = int(gridDim.x), bid = int(blockIdx.x);
   const int xq = nb >> 3, xr = nb & 7, xcd = bid & 7;
   const int order_idx = xcd * xq + (xcd < xr ? xcd : xr) + (bid >> 3);
-  const int tile = a.tile_order[a.tile_base + order_idx];
+  const int tile = a.tile_base + order_idx;
   const int32_t* ti = a.tile_info + TILE_STRIDE * tile;
   const int o0 = ti[TILE_OWNED0], no = ti[TILE_NOWNED];
   const int s0 = ti[TILE_SHARED0], ns = ti[TILE_NSHARED];
@@ -182,52 +187,90 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
     info = a.cell_info[rec];
   }
 
-  // 1. stage local nodes: all global loads of a batch are issued before any
-  //    LDS store (one dependent round trip for shared ids, one for the values)
-  constexpr int SLOTS = 4;   // local nodes per thread and batch
-  for (int base = 0; base < nloc; base += SLOTS * int(blockDim.x)) {
-    int64_t gs[SLOTS];
+  // 1. stage local nodes. Per round, the shared ids are requested first;
+  //    the private range needs no lookup, so its loads go out while the ids
+  //    are in flight, then the shared values; one LDS store pass at the end.
+  //    The Jacobian modes write their identity rows (constrained private
+  //    nodes) here, from the raw values.
+  constexpr bool JMODE = (MODE == MODE_J || MODE == MODE_JT);
+  constexpr int SP = 4, SS = 2;   // private / shared nodes per thread and round
+  const int bs = int(blockDim.x), tid = int(threadIdx.x);
+  for (int rp = 0, rs = 0; rp < no || rs < ns; rp += SP * bs, rs += SS * bs) {
+    int64_t gsh[SS];
 #pragma unroll
-    for (int k = 0; k < SLOTS; ++k) {
-      const int l = base + k * int(blockDim.x) + int(threadIdx.x);
-      gs[k] = l < no ? int64_t(o0 + l) : (l < nloc ? int64_t(a.shared[s0 + l - no]) : int64_t(-1));
+    for (int k = 0; k < SS; ++k) {
+      const int r = rs + k * bs + tid;
+      gsh[k] = r < ns ? int64_t(a.shared[s0 + r]) : int64_t(-1);
     }
-    uint8_t fs[SLOTS];
-    T vs[SLOTS][NF > 0 ? NF : 1];
+    uint8_t fp_[SP], fsh[SS];
+    T vp[SP][NF > 0 ? NF : 1], vsh[SS][NF > 0 ? NF : 1];
 #pragma unroll
-    for (int k = 0; k < SLOTS; ++k) {
-      const int64_t g = gs[k];
-      fs[k] = g >= 0 ? a.flags[g] : uint8_t(0);
+    for (int k = 0; k < SP; ++k) {
+      const int l = rp + k * bs + tid;
+      const int64_t g = int64_t(o0) + l;
+      fp_[k] = l < no ? a.flags[g] : uint8_t(0);
+      if constexpr (NF > 0) {
+        if (l < no) {
+          if constexpr (TR::n_src > 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vp[k][c] = a.src[c * n + g];
+          }
+#pragma unroll
+          for (int st = 0; st < TR::n_state; ++st) vp[k][TR::n_src + st] = a.st[st][g];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < SS; ++k) {
+      const int64_t g = gsh[k];
+      fsh[k] = g >= 0 ? a.flags[g] : uint8_t(0);
       if constexpr (NF > 0) {
         if (g >= 0) {
           if constexpr (TR::n_src > 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) vs[k][c] = a.src[c * n + g];
+            for (int c = 0; c < 3; ++c) vsh[k][c] = a.src[c * n + g];
           }
 #pragma unroll
-          for (int st = 0; st < TR::n_state; ++st) vs[k][TR::n_src + st] = a.st[st][g];
+          for (int st = 0; st < TR::n_state; ++st) vsh[k][TR::n_src + st] = a.st[st][g];
+        }
+      }
+    }
+    auto put = [&](int l, uint8_t f, const T* v) {
+      lflag[l] = f;
+      if constexpr (NF > 0) {
+#pragma unroll
+        for (int c = 0; c < NF; ++c) {
+          T x = v[c];
+          if constexpr (TR::mask_src) {
+            if (c < 3) {
+              const bool fixed = (c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
+              if (fixed) x = T(0);
+            }
+          }
+          lds[c * ML + l] = x;
+        }
+      }
+    };
+#pragma unroll
+    for (int k = 0; k < SP; ++k) {
+      const int l = rp + k * bs + tid;
+      if (l < no) {
+        put(l, fp_[k], vp[k]);
+        if constexpr (JMODE) {
+          const uint8_t f = fp_[k];
+          const int64_t g = int64_t(o0) + l;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
+            if (cons) a.dst[c * n + g] = vp[k][c];
+          }
         }
       }
     }
 #pragma unroll
-    for (int k = 0; k < SLOTS; ++k) {
-      const int l = base + k * int(blockDim.x) + int(threadIdx.x);
-      if (l < nloc) {
-        lflag[l] = fs[k];
-        if constexpr (NF > 0) {
-#pragma unroll
-          for (int c = 0; c < NF; ++c) {
-            T v = vs[k][c];
-            if constexpr (TR::mask_src) {
-              if (c < 3) {
-                const bool fixed = (c < 2) ? (fs[k] & NODE_DIRICHLET) : (fs[k] & NODE_ACTIVE);
-                if (fixed) v = T(0);
-              }
-            }
-            lds[c * ML + l] = v;
-          }
-        }
-      }
+    for (int k = 0; k < SS; ++k) {
+      const int r = rs + k * bs + tid;
+      if (r < ns) put(no + r, fsh[k], vsh[k]);
     }
   }
   for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
@@ -580,7 +623,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   for (int l = threadIdx.x; l < no; l += blockDim.x) {
     const uint8_t f = lflag[l];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, T>(a, c, int64_t(o0) + l, f, acc[c * ML + l]);
+    for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, true, T>(a, c, int64_t(o0) + l, f, acc[c * ML + l]);
   }
   for (int r = threadIdx.x; r < ns; r += blockDim.x) {
 #pragma unroll
@@ -604,7 +647,7 @@ __global__ void __launch_bounds__(256) shared_fixup(const TileArgs<T> a) {
       for (int c = 0; c < 3; ++c) v[c] += a.part[c * a.n_slots + slot];
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, T>(a, c, g, f, v[c]);
+    for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, false, T>(a, c, g, f, v[c]);
   }
 }
 

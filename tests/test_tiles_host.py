@@ -73,9 +73,8 @@ def _replay(t, n, A, x, sub):
         y[o0:o0 + no] = acc[:no]
         part[slot0:slot0 + ns] = acc[no:]
     for s in range(t["n_shared"]):
-        sl = t["shared_slot"][t["shared_ptr"][s]:t["shared_ptr"][s + 1]]
         v = 0.0
-        for j in sl:
+        for j in t["shared_slot"][t["shared_ptr"][s]:t["shared_ptr"][s + 1]]:
             v += part[j]
         y[t["n_private"] + s] = v
     return y
@@ -106,9 +105,10 @@ def test_tile_tables(case, p, tile):
         assert t["n_private"] + t["n_shared"] == n
         assert np.array_equal(ti[:, 0], np.concatenate([[0], np.cumsum(ti[:-1, 1])]))
         assert int(ti[:, 1].sum()) == t["n_private"]
-        # slots: consecutive per tile, each slot listed by exactly one shared node
+        # slots: tile-major, one per entry of the tiles' shared lists, each
+        # listed by exactly one shared node
         assert np.array_equal(ti[:, 7], np.concatenate([[0], np.cumsum(ti[:-1, 3])]))
-        assert int(ti[:, 3].sum()) == t["n_slots"]
+        assert int(ti[:, 3].sum()) == t["n_slots"] == t["shared_ptr"][-1]
         assert np.array_equal(np.sort(t["shared_slot"]), np.arange(t["n_slots"]))
         assert np.all(np.diff(t["shared_ptr"]) >= 2)
         # hanging records: consecutive per tile
@@ -116,6 +116,7 @@ def test_tile_tables(case, p, tile):
         if level >= 0:
             assert t["hang_rec"].shape[0] == 0
         slot_tile = np.repeat(np.arange(t["n_tiles"]), ti[:, 3])
+        slot_node = t["shared"].astype(np.int64)
         touched = [set() for _ in range(n)]
         for tile_id in range(t["n_tiles"]):
             o0, no, s0, ns, c0, nc, ncol, slot0, h0, nh, nhcol, _ = (int(v) for v in ti[tile_id])
@@ -163,6 +164,7 @@ def test_tile_tables(case, p, tile):
             assert len(touched[gi]) <= 1
         for s in range(t["n_shared"]):
             sl = t["shared_slot"][t["shared_ptr"][s]:t["shared_ptr"][s + 1]]
+            assert np.all(slot_node[sl] == t["n_private"] + s)
             tiles_s = slot_tile[sl]
             assert np.all(np.diff(tiles_s) > 0)           # ascending tile order
             assert set(tiles_s.tolist()) == touched[t["n_private"] + s]
