@@ -59,8 +59,8 @@ typedef struct pff_ctx pff_ctx;
  * reached from a coarse x coarse grid by global refinement, then n_local
  * passes refining every cell whose centre lies strictly inside
  * |x| < band_x, |y| < band_y, then 2:1 face balancing. degree = 1 (Q1) or
- * 2 (Q2). tile_x, tile_y: owned cells per tile along x and y (0 = default:
- * 15 for Q1, 10 for Q2). */
+ * 2 (Q2). tile_x, tile_y: cells per tile along x and y, at most 256 cells
+ * per tile (0 = default: 16 x 16 for Q1, 8 x 8 for Q2). */
 typedef struct {
   int32_t n_base, n_local, degree, coarse;
   double band_x, band_y;
@@ -75,8 +75,10 @@ typedef struct {
  *  upper_factor (1.2): smoothing interval [smooth_range, upper_factor] *
  *  lambda_max (Sec. 3.2); eig_cg_its: CG steps of the eigenvalue estimate;
  *  coarse_mode 0: Chebyshev over [lambda_min, upper_factor * lambda_max] on
- *  level 0 with coarse_its updates (Sec. 3.2); coarse_eig_its: CG steps for
- *  the level-0 estimate.
+ *  level 0 with coarse_its updates (Sec. 3.2); coarse_mode 1: coarse_its
+ *  Jacobi-preconditioned CG steps from zero on level 0, each block with its
+ *  own scalars (a fixed number of steps, so the cycle is reproducible; it is
+ *  not a linear operator); coarse_eig_its: CG steps for the level-0 estimate.
  *  gmres_restart, gmres_max_its, gmres_rtol, gmres_atol: GMRES(m) stops when
  *  the preconditioned residual is below max(atol, rtol * |rhs|) (Table 1).
  *  ls_omega, ls_max: line-search damping omega and l_max (Alg. 2).

@@ -177,6 +177,7 @@ struct pff_ctx {
   double* red_out = nullptr;
   double* host_red = nullptr;   // pinned
   double* V = nullptr;          // GMRES basis
+  double* ccg_s = nullptr;      // coarse CG scalars
   void* part = nullptr;         // partial sums of shared nodes (largest tile set)
   size_t part_bytes = 0;
   int V_cap = 0;
@@ -397,6 +398,25 @@ struct pff_ctx {
     return xi;
   }
 
+  // Coarse solve by a fixed number of Jacobi-preconditioned CG steps from
+  // x = 0 (both blocks, each with its own scalars) on level 0's right-hand
+  // side; the result is left in w.x[0].
+  template <typename T>
+  int coarse_cg() {
+    DevLevel& L = lv[0];
+    LevelWork<T>& w = work<T>(L);
+    T* x = w.x[0];
+    T* r = w.x[1];
+    T* pv = w.dir[0];
+    T* q = w.dir[1];
+    hipLaunchKernelGGL((k_ccg_init<T>), dim3(1), dim3(CCG_THREADS), 0, s, x, r, pv, w.d, w.dinv, L.n, ccg_s);
+    for (int it = 0; it < prm.coarse_its; ++it) {
+      level_apply<T>(0, pv, q, EPI_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr);
+      hipLaunchKernelGGL((k_ccg_step<T>), dim3(1), dim3(CCG_THREADS), 0, s, x, r, pv, q, w.dinv, L.n, ccg_s);
+    }
+    return 0;
+  }
+
   template <typename T>
   void vcycle_impl(double* dst, const double* src) {
     const int L = int(lv.size()) - 1;
@@ -422,7 +442,7 @@ struct pff_ctx {
     }
     {
       LevelWork<T>& w0 = work<T>(lv[0]);
-      xi[0] = chebyshev<T>(0, w0.d, -1, prm.coarse_its);
+      xi[0] = prm.coarse_mode == 1 ? coarse_cg<T>() : chebyshev<T>(0, w0.d, -1, prm.coarse_its);
     }
     for (int l = 1; l <= L; ++l) {
       DevLevel& D = lv[l];
@@ -733,7 +753,7 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
   ms.tile_x = spec->tile_x;
   ms.tile_y = spec->tile_y;
   if (params->cheb_degree < 1 || params->coarse_its < 1 || params->gmres_restart < 1 ||
-      params->gmres_restart > 60 || params->coarse_mode != 0)
+      params->gmres_restart > 60 || params->coarse_mode < 0 || params->coarse_mode > 1)
     return PFF_E_ARG;
   try {
     bool built = false;
@@ -785,6 +805,7 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
     c->part = dalloc<double>(3 * std::max<int64_t>(slots, 1));
     c->red_part = dalloc<double>(RED_BLOCKS * 64);
     c->red_out = dalloc<double>(256);
+    c->ccg_s = dalloc<double>(8);
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->host_red), 256 * sizeof(double), hipHostMallocDefault));
     // lumped phase-field mass (the B of Alg. 2)
     c->leaf_op<MODE_MASS>(c->mass, nullptr, nullptr);
@@ -819,7 +840,7 @@ int pff_destroy(pff_ctx* c) {
   }
   f(c->U); f(c->phio); f(c->phit); f(c->mass);
   for (int i = 0; i < 8; ++i) f(c->wv[i]);
-  f(c->red_part); f(c->red_out); f(c->V); f(c->part);
+  f(c->red_part); f(c->red_out); f(c->V); f(c->part); f(c->ccg_s);
   if (c->host_red) hipHostFree(c->host_red);
   delete c;
   return PFF_OK;
@@ -828,7 +849,7 @@ int pff_destroy(pff_ctx* c) {
 int pff_set_params(pff_ctx* c, const pff_params* p) {
   if (!c || !p) return PFF_E_ARG;
   if (p->cheb_degree < 1 || p->coarse_its < 1 || p->gmres_restart < 1 || p->gmres_restart > 60 ||
-      p->coarse_mode != 0)
+      p->coarse_mode < 0 || p->coarse_mode > 1)
     return PFF_E_ARG;
   c->prm = *p;
   c->mg_ready = false;

@@ -366,4 +366,81 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double* part
   }
 }
 
+// ---- coarse-level CG (one workgroup; the coarse level is small) ----------
+// Jacobi-preconditioned CG from x = 0 on both blocks at once: block 0 is the
+// displacement rows [0, 2n), block 1 the phase-field rows [2n, 3n); each has
+// its own scalars. Free unknowns are those with dinv != 0. s[0..1] holds
+// r.z per block between the kernels. An exactly zero r.z stops a block (its
+// further steps change nothing).
+constexpr int CCG_THREADS = 256;
+
+__device__ __forceinline__ void ccg_reduce2(double& a0, double& a1, double* sh) {
+  sh[threadIdx.x] = a0;
+  sh[CCG_THREADS + threadIdx.x] = a1;
+  __syncthreads();
+  for (int w = CCG_THREADS / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+      sh[threadIdx.x] += sh[threadIdx.x + w];
+      sh[CCG_THREADS + threadIdx.x] += sh[CCG_THREADS + threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  a0 = sh[0];
+  a1 = sh[CCG_THREADS];
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CCG_THREADS) k_ccg_init(T* x, T* r, T* p, const T* b, const T* dinv, int64_t n,
+                                                           double* s) {
+  __shared__ double sh[2 * CCG_THREADS];
+  double rz0 = 0.0, rz1 = 0.0;
+  for (int64_t i = threadIdx.x; i < 3 * n; i += blockDim.x) {
+    const T di = dinv[i];
+    const T ri = di != T(0) ? b[i] : T(0);
+    x[i] = T(0);
+    r[i] = ri;
+    p[i] = di * ri;
+    const double c = double(ri) * double(di * ri);
+    if (i < 2 * n) rz0 += c; else rz1 += c;
+  }
+  ccg_reduce2(rz0, rz1, sh);
+  if (threadIdx.x == 0) { s[0] = rz0; s[1] = rz1; }
+}
+
+// one CG step after q = A p: mask q, alpha = r.z / p.q, x += alpha p,
+// r -= alpha q, z = dinv r, beta = r.z_new / r.z, p = z + beta p
+template <typename T>
+__global__ void __launch_bounds__(CCG_THREADS) k_ccg_step(T* x, T* r, T* p, const T* q, const T* dinv, int64_t n,
+                                                           double* s) {
+  __shared__ double sh[2 * CCG_THREADS];
+  const double rz[2] = {s[0], s[1]};
+  double pq0 = 0.0, pq1 = 0.0;
+  for (int64_t i = threadIdx.x; i < 3 * n; i += blockDim.x) {
+    const double c = dinv[i] != T(0) ? double(p[i]) * double(q[i]) : 0.0;
+    if (i < 2 * n) pq0 += c; else pq1 += c;
+  }
+  ccg_reduce2(pq0, pq1, sh);
+  const double alpha[2] = {rz[0] == 0.0 ? 0.0 : rz[0] / pq0, rz[1] == 0.0 ? 0.0 : rz[1] / pq1};
+  double rn0 = 0.0, rn1 = 0.0;
+  for (int64_t i = threadIdx.x; i < 3 * n; i += blockDim.x) {
+    const int blk = i < 2 * n ? 0 : 1;
+    const T di = dinv[i];
+    const T qi = di != T(0) ? q[i] : T(0);
+    const T al = T(alpha[blk]);
+    x[i] += al * p[i];
+    const T ri = r[i] - al * qi;
+    r[i] = ri;
+    const double c = double(ri) * double(di * ri);
+    if (blk == 0) rn0 += c; else rn1 += c;
+  }
+  ccg_reduce2(rn0, rn1, sh);
+  const double beta[2] = {rz[0] == 0.0 ? 0.0 : rn0 / rz[0], rz[1] == 0.0 ? 0.0 : rn1 / rz[1]};
+  for (int64_t i = threadIdx.x; i < 3 * n; i += blockDim.x) {
+    const int blk = i < 2 * n ? 0 : 1;
+    p[i] = dinv[i] * r[i] + T(beta[blk]) * p[i];
+  }
+  if (threadIdx.x == 0) { s[0] = rn0; s[1] = rn1; }
+}
+
 }  // namespace pff

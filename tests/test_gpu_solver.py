@@ -18,18 +18,18 @@ MESHES = {
 _cases = {}
 
 
-def mg_case(name, p, mask="bernoulli", cheb=3, coarse_its=30):
-    key = (name, p, mask, cheb, coarse_its)
+def mg_case(name, p, mask="bernoulli", cheb=3, coarse_its=30, coarse="cheb"):
+    key = (name, p, mask, cheb, coarse_its, coarse)
     if key not in _cases:
         from paper_2404_03265_amd import SolverParams
         m = MESHES[name]
         print(f"[case] {key}", flush=True)
-        sp_ = SolverParams(cheb_degree=cheb, coarse_its=coarse_its)
+        sp_ = SolverParams(cheb_degree=cheb, coarse_its=coarse_its, coarse_mode={"cheb": 0, "cg": 1}[coarse])
         c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask=mask,
                  u_std=1e-2, solver_params=sp_)
         c.load_state(setup_mg=True)
         c.hier = Hierarchy(c.om)
-        mgp = MGParams(cheb_degree=cheb, coarse_its=coarse_its)
+        mgp = MGParams(cheb_degree=cheb, coarse_its=coarse_its, coarse_mode=coarse)
         lam_max, lam_min0 = c.g.get_eigen()
         c.vc = VCycle(c.hier, c.prm, mgp, c.U_o, c.phit_o, c.active_o,
                       eigen=([lam_max[l] for l in range(c.g.n_levels)], lam_min0))
@@ -110,6 +110,20 @@ def test_vcycle_degree4_and_short_coarse(name, p):
     got = c.g.vcycle(c.dev(src)).cpu().numpy()
     ref = c.to_g(c.vc.apply(c.to_o(src)))
     assert rel_err(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("name,p", CASES)
+def test_vcycle_coarse_cg(name, p):
+    """Coarse solve by fixed-step Jacobi-CG (Chebyshev degree 4 smoothing, the
+    mixed-precision configuration): FP64 cycle to 1e-12, FP32 cycle to 1e-5,
+    both against the oracle cycle with the same coarse CG."""
+    c = mg_case(name, p, cheb=4, coarse_its=20, coarse="cg")
+    src = inputs.random_vector(c.X, c.Y, 8)
+    ref = c.to_g(c.vc.apply(c.to_o(src)))
+    got = c.g.vcycle(c.dev(src)).cpu().numpy()
+    assert rel_err(got, ref) <= 1e-12
+    got32 = c.g.vcycle(c.dev(src), fp32=True).cpu().numpy()
+    assert rel_err(got32, ref) <= 1e-5
 
 
 @pytest.mark.parametrize("name,p", CASES)

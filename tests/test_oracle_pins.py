@@ -515,3 +515,38 @@ def test_vcycle_nonsingular_with_scattered_active_set(p, tiny_mesh_factory):
     x, info = gmres(lambda v: J @ v, vc.apply, b, 1e-13 * np.linalg.norm(b))
     xd = spla.spsolve(J.tocsc(), b)
     assert info.converged and np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+
+
+def test_coarse_cg_closed_forms():
+    """Coarse-level CG (fixed steps from zero, Jacobi preconditioner, blocks
+    separate): one step is the preconditioned steepest-descent step
+    x = (r.z / z.Az) z with z = D^{-1} r; with as many steps as free unknowns
+    it reproduces the exact solve of each block on its free unknowns."""
+    import scipy.sparse.linalg as spla
+    from oracle.mg import Hierarchy, MGParams, VCycle, block_masks
+    mesh = Mesh(16, 1, 1, coarse=4, band=(3.0, 1.0))
+    prm = Params(ell=0.4, kappa=1e-3, pressure=0.2)
+    lp = LeafProblem(mesh, prm)
+    U, phit = _state(mesh, lp, u_std=0.01)
+    rng = np.random.default_rng(3)
+    act = inputs.bernoulli_mask(mesh.NX, mesh.NY, 2, 0.1) & ~mesh.hanging
+    h = Hierarchy(mesh)
+    n0 = h.levels[0].n
+    b = rng.standard_normal(3 * n0)
+    vc1 = VCycle(h, prm, MGParams(coarse_mode="cg", coarse_its=1), U, phit, act)
+    op = vc1.ops[0]
+    x1 = vc1.coarse_solve(b)
+    for blk in block_masks(n0):
+        m = op.free & blk
+        r = b * m
+        z = op.Dinv * r
+        alpha = (r @ z) / (z @ (op.A @ z))
+        assert np.allclose(x1[blk], (alpha * z)[blk], rtol=1e-13, atol=1e-15)
+    nfree = int(op.free.sum())
+    vcn = VCycle(h, prm, MGParams(coarse_mode="cg", coarse_its=nfree + 5), U, phit, act)
+    xn = vcn.coarse_solve(b)
+    for blk in block_masks(n0):
+        idx = np.flatnonzero(op.free & blk)
+        xe = spla.spsolve(op.A[idx][:, idx].tocsc(), b[idx])
+        assert np.linalg.norm(xn[idx] - xe) <= 1e-8 * np.linalg.norm(xe)
+        assert np.all(xn[blk & ~op.free] == 0.0)
