@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vmult_traffic.json")
 KERNEL_SOURCES = ["paper_2404_03265_amd/csrc/tile_kernel.hpp", "paper_2404_03265_amd/csrc/cell.hpp",
-                  "paper_2404_03265_amd/csrc/mesh.cpp"]
+                  "paper_2404_03265_amd/csrc/mesh.cpp", "paper_2404_03265_amd/csrc/mesh.hpp"]
 
 
 def kernel_hash():
@@ -190,8 +190,11 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == spec.name:
-            traffic = tr.get("bytes_per_launch")
+        # HBM bytes per vmult from the committed counter summary, valid only
+        # while the kernel sources are the ones profiled
+        w = tr.get("workloads", {}).get(spec.name)
+        if tr.get("kernel_hash") == kernel_hash() and w is not None:
+            traffic = w.get("bytes_per_launch")
 
     # ---- load-step solves (Alg. 2 loop), FP64 and mixed precision ----------
     extra = {}
