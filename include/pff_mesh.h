@@ -46,9 +46,11 @@ int pff_mesh_tile_stats(const pff_mesh* m, int32_t level, int64_t* n_tiles, int6
  * shared list, n_private, n_shared, n_slots, cell records, regular tiles,
  * largest local node count, hanging-node records, largest number of
  * hanging-node colours of a tile. Arrays are optional (NULL skips):
- * tile_info (12 per tile: private start, private count, shared-list start,
+ * tile_info (32 per tile: private start, private count, shared-list start,
  * shared count, first cell record, cell count, cell colours, first slot,
- * first hanging record, hanging records, hanging colours, unused), shared
+ * first hanging record, hanging records, hanging colours, number of runs of
+ * consecutive ids in the shared list (0 = more than 8), 4 unused, 8 run start
+ * ids, 8 run offsets into the shared list), shared
  * (global ids), shared_ptr (n_shared + 1), shared_slot (n_slots: slots of each
  * shared node in ascending tile order; slots are tile-major), cell_loc and
  * cell_loc_sub ((p+1)^2 per record, local ids: private nodes first, then the

@@ -45,22 +45,25 @@ def normal(seed: int, stream: int, X, Y) -> np.ndarray:
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
 
 
-def crack_mask(X, Y, M: int, half_length: float = 1.0) -> np.ndarray:
-    """Lattice points on the prescribed crack: y = 0 and |x| <= half_length.
+def crack_mask(X, Y, M: int, edge: int, half_length: float = 1.0) -> np.ndarray:
+    """Lattice points of the prescribed crack (Sec. 4: half length l0, a width
+    set by the smallest cell): |x| <= half_length and |y| <= h, with h the
+    diagonal of the finest cell, whose edge is `edge` lattice units.
 
-    Exact in integers: y = 0 <=> 2Y = M and |x| <= a <=> |20X - 10M| <= a M
-    (a is taken as a rational with denominator 1000).
+    Exact in integers: |y| <= h <=> (2Y - M)^2 <= 8 edge^2, and |x| <= a <=>
+    |20X - 10M| <= a M (a is taken as a rational with denominator 1000).
     """
     X = np.asarray(X, dtype=np.int64)
     Y = np.asarray(Y, dtype=np.int64)
     a_num = int(round(half_length * 1000))
-    return (2 * Y == M) & (1000 * np.abs(20 * X - 10 * M) <= a_num * M)
+    return ((2 * Y - M) ** 2 <= 8 * int(edge) ** 2) & (1000 * np.abs(20 * X - 10 * M) <= a_num * M)
 
 
-def sneddon_state(X, Y, M: int, seed: int = 0, u_std: float = 1e-4,
+def sneddon_state(X, Y, M: int, edge: int, seed: int = 0, u_std: float = 1e-4,
                   phi_low: float = 0.5, random: bool = True):
     """Raw nodal state (u_x, u_y, phi) before any constraint is applied.
 
+    edge: finest cell edge in lattice units (the degree p on a Q_p lattice).
     random=True: u ~ N(0, u_std) per component, phi ~ U[phi_low, 1] off the
     crack and 0 on it. random=False: u = 0, phi = 1 off the crack, 0 on it
     (the initial state of a load step). Dirichlet zeroing and hanging-node
@@ -68,7 +71,7 @@ def sneddon_state(X, Y, M: int, seed: int = 0, u_std: float = 1e-4,
     """
     X = np.asarray(X, dtype=np.int64)
     Y = np.asarray(Y, dtype=np.int64)
-    crack = crack_mask(X, Y, M)
+    crack = crack_mask(X, Y, M, edge)
     if random:
         ux = u_std * normal(seed, 0, X, Y)
         uy = u_std * normal(seed, 1, X, Y)

@@ -173,6 +173,18 @@ void build_tiles(int p, int n_tiles, const std::vector<int32_t>& fp, const std::
     slot0 += int64_t(sh.size());
     if (slot0 > INT32_MAX) throw std::runtime_error("too many partial-sum slots");
     T.shared.insert(T.shared.end(), sh.begin(), sh.end());
+    {
+      int nrun = 0;
+      bool fits = true;
+      for (size_t r = 0; r < sh.size() && fits; ++r) {
+        if (r > 0 && sh[r] == sh[r - 1] + 1) continue;
+        if (nrun == TILE_MAX_RUNS) { fits = false; break; }
+        ti[TILE_RUN_START + nrun] = sh[r];
+        ti[TILE_RUN_OFF + nrun] = int32_t(r);
+        ++nrun;
+      }
+      ti[TILE_NRUN] = fits ? nrun : 0;
+    }
     const int nloc = no + int(sh.size());
     if (nloc > 65535) throw std::runtime_error("tile has more than 65535 local nodes");
     auto local = [&](int32_t g) -> uint16_t {

@@ -73,10 +73,16 @@ struct TileSet {
 // Per tile: private node range, shared local node list, cell records, number
 // of cell colours, first partial-sum slot (slots are consecutive per tile:
 // entry r of the tile's shared list writes slot TILE_SLOT0 + r), hanging-node
-// records and their number of colours.
+// records and their number of colours, and the shared list as at most
+// TILE_MAX_RUNS runs of consecutive node ids (TILE_NRUN = 0: read the list):
+// entry r lies in the last run k with TILE_RUN_OFF + k <= r and has id
+// TILE_RUN_START + k's value + (r - offset).
+constexpr int TILE_MAX_RUNS = 8;
 enum {
   TILE_OWNED0 = 0, TILE_NOWNED, TILE_SHARED0, TILE_NSHARED, TILE_CELL0, TILE_NCELL, TILE_NCOLOR, TILE_SLOT0,
-  TILE_HANG0, TILE_NHANG, TILE_NHCOLOR, TILE_PAD, TILE_STRIDE
+  TILE_HANG0, TILE_NHANG, TILE_NHCOLOR, TILE_NRUN,
+  TILE_RUN_START = 16, TILE_RUN_OFF = TILE_RUN_START + TILE_MAX_RUNS,
+  TILE_STRIDE = TILE_RUN_OFF + TILE_MAX_RUNS
 };
 
 // A CSR matrix with double weights (exact dyadic values).

@@ -161,6 +161,17 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   const int c0 = ti[TILE_CELL0], nc = ti[TILE_NCELL];
   const int ncol = ti[TILE_NCOLOR];
   const int slot0 = ti[TILE_SLOT0];
+  const int nrun = ti[TILE_NRUN];
+  // global id of shared entry r: from the runs in the tile header, so the
+  // shared values load without a dependent lookup; the list otherwise
+  auto shared_id = [&](int r) -> int64_t {
+    if (nrun == 0) return a.shared[s0 + r];
+    int id = ti[TILE_RUN_START] + r;
+#pragma unroll
+    for (int k = 1; k < TILE_MAX_RUNS; ++k)
+      if (k < nrun && r >= ti[TILE_RUN_OFF + k]) id = ti[TILE_RUN_START + k] + (r - ti[TILE_RUN_OFF + k]);
+    return id;
+  };
   // Hanging nodes: every mode but the inverse diagonal applies the
   // constraints on the tile's nodes (interpolate after staging, distribute
   // after accumulation); the inverse diagonal needs the per-cell form.
@@ -200,7 +211,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < SS; ++k) {
       const int r = rs + k * bs + tid;
-      gsh[k] = r < ns ? int64_t(a.shared[s0 + r]) : int64_t(-1);
+      gsh[k] = r < ns ? shared_id(r) : int64_t(-1);
     }
     uint8_t fp_[SP], fsh[SS];
     T vp[SP][NF > 0 ? NF : 1], vsh[SS][NF > 0 ? NF : 1];

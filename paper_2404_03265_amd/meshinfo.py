@@ -89,7 +89,7 @@ class HostMesh:
         nl = (self.degree + 1) ** 2
         t = dict(n_tiles=n_tiles, n_private=n_priv, n_shared=n_sh, n_slots=n_slots, n_regular=n_reg,
                  max_local=max_local, max_hang_colors=max_hcol,
-                 tile_info=np.zeros((n_tiles, 12), dtype=np.int32),
+                 tile_info=np.zeros((n_tiles, 32), dtype=np.int32),
                  shared=np.zeros(n_sh_list, dtype=np.int32),
                  shared_ptr=np.zeros(n_sh + 1, dtype=np.int32),
                  shared_slot=np.zeros(n_slots, dtype=np.int32),

@@ -37,7 +37,7 @@ class Case:
         n = self.n
         flags = self.g.flags()
         dirichlet = (flags & 1) != 0
-        ux, uy, phi = inputs.sneddon_state(X, Y, self.M, seed=seed, u_std=u_std)
+        ux, uy, phi = inputs.sneddon_state(X, Y, self.M, p, seed=seed, u_std=u_std)
         ux = np.where(dirichlet, 0.0, ux)
         uy = np.where(dirichlet, 0.0, uy)
         self.U_raw = np.concatenate([ux, uy, phi])

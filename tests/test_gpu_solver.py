@@ -151,7 +151,7 @@ def test_newton_step_matches_oracle(name, p):
     m = MESHES[name]
     c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="rule")
     n = c.n
-    ux, uy, phi = inputs.sneddon_state(c.X, c.Y, c.M, random=False)
+    ux, uy, phi = inputs.sneddon_state(c.X, c.Y, c.M, p, random=False)
     U0 = np.concatenate([ux, uy, phi])
     Ud = c.dev(U0)
     ph = c.dev(phi)
@@ -222,7 +222,7 @@ def test_adjoint_crack_volume_gradient(name, p):
     sp_ = SolverParams(gmres_rtol=1e-13, gmres_atol=1e-15)
     c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="rule",
              solver_params=sp_)
-    ux, uy, phi = inputs.sneddon_state(c.X, c.Y, c.M, random=False)
+    ux, uy, phi = inputs.sneddon_state(c.X, c.Y, c.M, p, random=False)
     U = c.dev(np.concatenate([ux, uy, phi]))
     ph = c.dev(phi)
     act, infos = solve_load_step(c.g, U, ph, ph, tol=1e-10)

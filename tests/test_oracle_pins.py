@@ -22,7 +22,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
 
 def _state(mesh, lp, seed=0, u_std=0.05):
     n = mesh.n_nodes
-    ux, uy, phi = inputs.sneddon_state(mesh.NX, mesh.NY, mesh.M, seed=seed, u_std=u_std)
+    ux, uy, phi = inputs.sneddon_state(mesh.NX, mesh.NY, mesh.M, mesh.p, seed=seed, u_std=u_std)
     U = np.concatenate([ux, uy, phi])
     U[:2 * n][np.concatenate([mesh.dirichlet] * 2)] = 0.0
     U = lp.distribute(U)
@@ -400,7 +400,7 @@ def _sneddon(mesh, prm_kw):
     prm = Params(**prm_kw)
     lp = LeafProblem(mesh, prm)
     n = mesh.n_nodes
-    ux, uy, phi = inputs.sneddon_state(mesh.NX, mesh.NY, mesh.M, random=False)
+    ux, uy, phi = inputs.sneddon_state(mesh.NX, mesh.NY, mesh.M, mesh.p, random=False)
     U = lp.distribute(np.concatenate([ux, uy, phi]))
     return lp, U, U[2 * n:].copy()
 
@@ -418,7 +418,7 @@ def test_newton_u_block_scales_with_p_over_E():
         Rn = lp.residual(Un, phi_old) * lp.free_mask(act)
         assert np.abs(Rn[:2 * n]).max() < 1e-12
         sols.append(Un[:2 * n] * E / pr)
-        crack = inputs.crack_mask(mesh.NX, mesh.NY, mesh.M)
+        crack = inputs.crack_mask(mesh.NX, mesh.NY, mesh.M, mesh.p)
         assert np.all(act[crack])                           # active set contains the crack
     assert np.abs(sols[0] - sols[1]).max() <= 1e-10 * np.abs(sols[0]).max()
 

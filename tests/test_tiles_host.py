@@ -50,7 +50,7 @@ def _replay(t, n, A, x, sub):
     part = np.full(t["n_slots"], np.nan)
     loc_all = t["cell_loc_sub"] if sub else t["cell_loc"]
     for tile in range(t["n_tiles"]):
-        o0, no, s0, ns, c0, nc, ncol, slot0, h0, nh, nhcol, _ = (int(v) for v in t["tile_info"][tile])
+        o0, no, s0, ns, c0, nc, ncol, slot0, h0, nh, nhcol = (int(v) for v in t["tile_info"][tile, :11])
         g = _global_ids(t, tile)
         xl = x[g].copy()
         recs = t["hang_rec"][h0:h0 + nh].astype(np.int64)
@@ -119,9 +119,19 @@ def test_tile_tables(case, p, tile):
         slot_node = t["shared"].astype(np.int64)
         touched = [set() for _ in range(n)]
         for tile_id in range(t["n_tiles"]):
-            o0, no, s0, ns, c0, nc, ncol, slot0, h0, nh, nhcol, _ = (int(v) for v in ti[tile_id])
+            o0, no, s0, ns, c0, nc, ncol, slot0, h0, nh, nhcol = (int(v) for v in ti[tile_id, :11])
             sh = t["shared"][s0:s0 + ns]
             assert np.all(sh >= t["n_private"]) and np.all(np.diff(sh) > 0)
+            # runs of consecutive ids in the header reproduce the list
+            nrun = int(ti[tile_id, 11])
+            if ns and nrun:
+                starts, offs = ti[tile_id, 16:16 + nrun], ti[tile_id, 24:24 + nrun]
+                assert offs[0] == 0 and np.all(np.diff(offs) > 0)
+                r = np.arange(ns)
+                k = np.searchsorted(offs, r, side="right") - 1
+                assert np.array_equal(starts[k] + (r - offs[k]), sh)
+            elif ns:
+                assert 1 + np.sum(np.diff(sh) != 1) > 8
             g = _global_ids(t, tile_id)
             assert no + ns <= t["max_local"]
             locs = t["cell_loc"][c0:c0 + nc].astype(np.int64)
