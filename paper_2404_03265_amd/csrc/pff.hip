@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -52,8 +53,6 @@ struct LevelWork {
   T* x[2] = {nullptr, nullptr};
   T* dir[2] = {nullptr, nullptr};
   T* dinv = nullptr;
-  T* Pval = nullptr;   // prolongation weights in this precision
-  T* PTval = nullptr;
 };
 
 struct DevLevel {
@@ -61,10 +60,16 @@ struct DevLevel {
   DevTiles tiles;
   uint8_t* flags = nullptr;
   int32_t* leaf_index = nullptr;
-  int64_t* P_ptr = nullptr;
-  int32_t* P_col = nullptr;
-  int64_t* PT_ptr = nullptr;
+  int64_t* PT_ptr = nullptr;   // restriction stencils (CSR), for the level active sets
   int32_t* PT_col = nullptr;
+  // transfers in ELL form: P over all nodes of this level, P^T over the
+  // coarse rows that receive contributions
+  TransferEntry* P_ell = nullptr;
+  int P_width = 0;
+  TransferEntry* PT_ell = nullptr;
+  int32_t* PT_rows = nullptr;
+  int64_t PT_nrows = 0;
+  int PT_width = 0;
   LevelWork<double> w64;
   LevelWork<float> w32;
   double lam_max[2] = {1, 1}, lam_min[2] = {1, 1};
@@ -149,6 +154,39 @@ DevTiles upload_tiles(const TileSet& t) {
   d.n_shared = t.n_shared;
   d.n_slots = t.n_slots;
   return d;
+}
+
+// Column-major ELL copies of P (all fine rows) and P^T (the coarse rows with
+// entries); weights must be exact in float (dyadic values).
+void ell_from_csr(const Csr& A, const std::vector<int64_t>& rows, std::vector<TransferEntry>& E, int& width) {
+  width = 0;
+  for (int64_t r : rows) width = std::max<int>(width, int(A.ptr[r + 1] - A.ptr[r]));
+  const int64_t nr = int64_t(rows.size());
+  E.assign(size_t(std::max(width, 1)) * size_t(std::max<int64_t>(nr, 1)), TransferEntry{0, 0.0f});
+  for (int64_t k = 0; k < nr; ++k) {
+    const int64_t r = rows[k];
+    for (int64_t e = A.ptr[r]; e < A.ptr[r + 1]; ++e) {
+      const float w = float(A.val[e]);
+      if (double(w) != A.val[e]) throw std::runtime_error("transfer weight not exact in float");
+      E[size_t(e - A.ptr[r]) * size_t(nr) + size_t(k)] = TransferEntry{A.col[e], w};
+    }
+  }
+}
+
+void upload_transfers(const Level& HL, DevLevel& D) {
+  std::vector<TransferEntry> E;
+  std::vector<int64_t> rows(size_t(HL.P.rows));
+  std::iota(rows.begin(), rows.end(), 0);
+  ell_from_csr(HL.P, rows, E, D.P_width);
+  D.P_ell = upload(E);
+  rows.clear();
+  for (int64_t r = 0; r < HL.PT.rows; ++r)
+    if (HL.PT.ptr[r + 1] > HL.PT.ptr[r]) rows.push_back(r);
+  ell_from_csr(HL.PT, rows, E, D.PT_width);
+  D.PT_ell = upload(E);
+  std::vector<int32_t> r32(rows.begin(), rows.end());
+  D.PT_rows = upload(r32);
+  D.PT_nrows = int64_t(rows.size());
 }
 
 inline int grid_for(int64_t n, int threads = 256) {
@@ -280,11 +318,43 @@ struct pff_ctx {
     hipLaunchKernelGGL((k_dot_partial<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, a, b, len, red_part);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, 1, out_dev);
   }
-  void mdot(const double* Vb, int k, const double* w, int64_t len, double* host_out) {
-    hipLaunchKernelGGL(k_mdot_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, Vb, w, k, len, red_part);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, k, red_out);
+  // the k <= 64 running sums of the orthogonalisation kernels are held in
+  // registers: instantiate for the smallest bound that covers k
+  template <template <int> class F, typename... A>
+  void launch_k(int k, A... args) {
+    if (k <= 8)
+      F<8>::run(s, args...);
+    else if (k <= 16)
+      F<16>::run(s, args...);
+    else if (k <= 32)
+      F<32>::run(s, args...);
+    else if (k <= 64)
+      F<64>::run(s, args...);
+    else
+      throw std::runtime_error("more than 64 Krylov vectors");
+  }
+  template <int K>
+  struct MdotL {
+    static void run(hipStream_t st, const double* V, const double* w, int k, int64_t len, double* part) {
+      hipLaunchKernelGGL(k_mdot_partial<K>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, w, k, len, part);
+    }
+  };
+  template <int K>
+  struct McombMdotL {
+    static void run(hipStream_t st, const double* V, double* w, const double* h, int k, int64_t len, double* part) {
+      hipLaunchKernelGGL(k_mcombine_mdot_partial<K>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, w, h, k, len,
+                         part);
+    }
+  };
+  // out = sums of the k partial columns left in red_part, copied to the host
+  void reduce_to_host(int k, double* host_out) {
+    hipLaunchKernelGGL(k_reduce_final, dim3(k), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, k, red_out);
     HIPCHK(hipMemcpyAsync(host_out, red_out, sizeof(double) * k, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+  }
+  void mdot(const double* Vb, int k, const double* w, int64_t len, double* host_out) {
+    launch_k<MdotL>(k, Vb, w, k, len, red_part);
+    reduce_to_host(k, host_out);
   }
   double norm(const double* a, int64_t len) { return std::sqrt(dot(a, a, len)); }
 
@@ -301,11 +371,7 @@ struct pff_ctx {
     w.d = dalloc<T>(3 * nl);
     for (int i = 0; i < 2; ++i) { w.x[i] = dalloc<T>(3 * nl); w.dir[i] = dalloc<T>(3 * nl); }
     w.dinv = dalloc<T>(3 * nl);
-    if (!HL.P.val.empty()) {
-      std::vector<T> pv(HL.P.val.begin(), HL.P.val.end()), ptv(HL.PT.val.begin(), HL.PT.val.end());
-      w.Pval = upload(pv);
-      w.PTval = upload(ptv);
-    }
+    (void)HL;
     w.ready = true;
   }
 
@@ -437,8 +503,9 @@ struct pff_ctx {
       level_apply<T>(l, w.x[xi[l]], t, EPI_RESID, w.d, nullptr, nullptr, nullptr, nullptr);
       DevLevel& C = lv[l - 1];
       LevelWork<T>& wc = work<T>(C);
-      hipLaunchKernelGGL((k_restrict_add<T>), dim3(grid_for(C.n)), dim3(256), 0, s, wc.d, t, C.n, D.n, D.PT_ptr,
-                         D.PT_col, w.PTval);
+      if (D.PT_nrows > 0)
+        hipLaunchKernelGGL((k_restrict_add<T>), dim3(grid_for(D.PT_nrows)), dim3(256), 0, s, wc.d, t, C.n, D.n,
+                           D.PT_nrows, D.PT_rows, D.PT_width, D.PT_ell);
     }
     {
       LevelWork<T>& w0 = work<T>(lv[0]);
@@ -449,7 +516,7 @@ struct pff_ctx {
       LevelWork<T>& w = work<T>(D);
       LevelWork<T>& wc = work<T>(lv[l - 1]);
       hipLaunchKernelGGL((k_prolong_add<T>), dim3(grid_for(D.n)), dim3(256), 0, s, w.x[xi[l]], wc.x[xi[l - 1]], D.n,
-                         lv[l - 1].n, D.P_ptr, D.P_col, w.Pval, D.flags);
+                         lv[l - 1].n, D.P_width, D.P_ell, D.flags);
       xi[l] = chebyshev<T>(l, w.d, xi[l], k);
     }
     for (int l = 0; l <= L; ++l) {
@@ -638,14 +705,19 @@ struct pff_ctx {
         double* vn = V + int64_t(j + 1) * N;
         apply_A(t, vj, transpose);
         apply_Minv(vn, t, fp32);
-        // classical Gram-Schmidt, twice
-        for (int pass = 0; pass < 2; ++pass) {
-          std::vector<double>& h = pass == 0 ? h1 : h2;
-          mdot(V, j + 1, vn, N, h.data());
-          HIPCHK(hipMemcpyAsync(hdev, h.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, s));
-          hipLaunchKernelGGL(k_mcombine, dim3(grid_for(N)), dim3(256), 0, s, vn, V, hdev, j + 1, N, -1.0);
-        }
-        double hn = norm(vn, N);
+        // classical Gram-Schmidt, twice: h1 = V^T vn; vn -= V h1 fused with
+        // h2 = V^T vn; vn -= V h2 fused with |vn|^2
+        const int k = j + 1;
+        mdot(V, k, vn, N, h1.data());
+        HIPCHK(hipMemcpyAsync(hdev, h1.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+        launch_k<McombMdotL>(k, (const double*)V, vn, (const double*)hdev, k, N, red_part);
+        reduce_to_host(k, h2.data());
+        HIPCHK(hipMemcpyAsync(hdev, h2.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_mcombine_sq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, vn, hdev, k, N,
+                           red_part);
+        double hn2 = 0.0;
+        reduce_to_host(1, &hn2);
+        double hn = std::sqrt(hn2);
         std::vector<double> h(j + 2);
         for (int i = 0; i <= j; ++i) h[i] = h1[i] + h2[i];
         for (int i = 0; i < j; ++i) {
@@ -788,10 +860,9 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
       D.flags = upload(HL.flags);
       D.leaf_index = upload(HL.leaf_index);
       if (l > 0) {
-        D.P_ptr = upload(HL.P.ptr);
-        D.P_col = upload(HL.P.col);
         D.PT_ptr = upload(HL.PT.ptr);
         D.PT_col = upload(HL.PT.col);
+        upload_transfers(HL, D);
       }
     }
     c->U = dalloc<double>(3 * n);
@@ -831,12 +902,12 @@ int pff_destroy(pff_ctx* c) {
   f(c->hang);
   for (DevLevel& D : c->lv) {
     ft(D.tiles);
-    f(D.flags); f(D.leaf_index); f(D.P_ptr); f(D.P_col); f(D.PT_ptr); f(D.PT_col);
+    f(D.flags); f(D.leaf_index); f(D.PT_ptr); f(D.PT_col); f(D.P_ell); f(D.PT_ell); f(D.PT_rows);
     for (auto* w : {&D.w64}) {
-      f(w->state); f(w->d); f(w->x[0]); f(w->x[1]); f(w->dir[0]); f(w->dir[1]); f(w->dinv); f(w->Pval); f(w->PTval);
+      f(w->state); f(w->d); f(w->x[0]); f(w->x[1]); f(w->dir[0]); f(w->dir[1]); f(w->dinv);
     }
     LevelWork<float>& w = D.w32;
-    f(w.state); f(w.d); f(w.x[0]); f(w.x[1]); f(w.dir[0]); f(w.dir[1]); f(w.dinv); f(w.Pval); f(w.PTval);
+    f(w.state); f(w.d); f(w.x[0]); f(w.x[1]); f(w.dir[0]); f(w.dir[1]); f(w.dinv);
   }
   f(c->U); f(c->phio); f(c->phit); f(c->mass);
   for (int i = 0; i < 8; ++i) f(c->wv[i]);

@@ -10,7 +10,7 @@
 
 namespace pff {
 
-constexpr int RED_BLOCKS = 512;
+constexpr int RED_BLOCKS = 2048;
 constexpr int RED_THREADS = 256;
 
 __device__ __forceinline__ bool leaf_constrained(uint8_t f, int c) {
@@ -213,17 +213,28 @@ __global__ void k_copy_from_level(double* out, const T* x, int64_t nl, const uin
 
 // x_f += P x_c (rows of P: fine nodes); unknowns held at zero on the fine
 // level (u on the boundary, phi on the level active set) stay zero
+// Grid transfers in a column-major ELL layout: entry e of row r at
+// E[e * rows + r], so the entries of one step are read with unit stride
+// across the lanes; padding entries have weight 0. The prolongation weights
+// are exact dyadic values, stored as float for both precisions.
+struct TransferEntry {
+  int32_t col;
+  float w;
+};
+
+// x_f += P x_c on unknowns the fine level does not hold at zero
+// (Dirichlet for u, active for phi)
 template <typename T>
-__global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, const int64_t* ptr,
-                              const int32_t* col, const T* val, const uint8_t* ff) {
+__global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, int width, const TransferEntry* E,
+                              const uint8_t* ff) {
   GRID_LOOP(i, nf) {
     T s0 = T(0), s1 = T(0), s2 = T(0);
-    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
-      const T w = val[e];
-      const int64_t j = col[e];
-      s0 += w * xc[j];
-      s1 += w * xc[nc + j];
-      s2 += w * xc[2 * nc + j];
+    for (int e = 0; e < width; ++e) {
+      const TransferEntry t = E[int64_t(e) * nf + i];
+      const T w = T(t.w);
+      s0 += w * xc[t.col];
+      s1 += w * xc[nc + t.col];
+      s2 += w * xc[2 * nc + t.col];
     }
     const uint8_t f = ff[i];
     if (!(f & NODE_DIRICHLET)) {
@@ -234,19 +245,20 @@ __global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, const 
   }
 }
 
-// d_c += P^T t_f (rows of P^T: coarse nodes)
+// d_c += P^T t_f over the coarse rows that receive fine contributions
 template <typename T>
-__global__ void k_restrict_add(T* dc, const T* tf, int64_t nc, int64_t nf, const int64_t* ptr,
-                               const int32_t* col, const T* val) {
-  GRID_LOOP(i, nc) {
+__global__ void k_restrict_add(T* dc, const T* tf, int64_t nc, int64_t nf, int64_t nrows, const int32_t* rows,
+                               int width, const TransferEntry* E) {
+  GRID_LOOP(r, nrows) {
     T s0 = T(0), s1 = T(0), s2 = T(0);
-    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
-      const T w = val[e];
-      const int64_t j = col[e];
-      s0 += w * tf[j];
-      s1 += w * tf[nf + j];
-      s2 += w * tf[2 * nf + j];
+    for (int e = 0; e < width; ++e) {
+      const TransferEntry t = E[int64_t(e) * nrows + r];
+      const T w = T(t.w);
+      s0 += w * tf[t.col];
+      s1 += w * tf[nf + t.col];
+      s2 += w * tf[2 * nf + t.col];
     }
+    const int64_t i = rows[r];
     dc[i] += s0;
     dc[nc + i] += s1;
     dc[2 * nc + i] += s2;
@@ -329,39 +341,99 @@ __global__ void __launch_bounds__(RED_THREADS) k_dot_partial(const T* a, const T
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// multi-dot: part[blk * k + j] = partial of V_j . w
-__global__ void __launch_bounds__(RED_THREADS) k_mdot_partial(const double* V, const double* w, int k,
-                                                                int64_t len, double* part) {
-  __shared__ double sh[RED_THREADS];
-  for (int j = 0; j < k; ++j) {
-    double s = 0.0;
-    const double* v = V + int64_t(j) * len;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x)
-      s += v[i] * w[i];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int ww = blockDim.x / 2; ww > 0; ww >>= 1) {
-      if (threadIdx.x < ww) sh[threadIdx.x] += sh[threadIdx.x + ww];
-      __syncthreads();
+// Orthogonalisation kernels for GMRES (classical Gram-Schmidt, twice).
+// V holds k vectors of length len back to back, k <= K (a compile-time
+// bound, so the k running sums stay in registers). Each kernel streams w and
+// the V[j] once and leaves one partial sum per block and product in
+// part[block * k + j], reduced in fixed order by k_reduce_final.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int K>
+__device__ __forceinline__ void block_partials(const double (&s)[K], int k, double* part) {
+  __shared__ double sh[RED_THREADS / 64][K];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    if (j < k) {
+      const double t = wave_sum(s[j]);
+      if (lane == 0) sh[wave][j] = t;
     }
-    if (threadIdx.x == 0) part[blockIdx.x * k + j] = sh[0];
-    __syncthreads();
+  __syncthreads();
+  if (threadIdx.x < k) {
+    double t = 0.0;
+    for (int q = 0; q < RED_THREADS / 64; ++q) t += sh[q][threadIdx.x];
+    part[int64_t(blockIdx.x) * k + threadIdx.x] = t;
   }
 }
 
+// partials of V[j] . w
+template <int K>
+__global__ void __launch_bounds__(RED_THREADS) k_mdot_partial(const double* V, const double* w, int k,
+                                                                int64_t len, double* part) {
+  double s[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) s[j] = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x) {
+    const double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (j < k) s[j] += V[int64_t(j) * len + i] * wi;
+  }
+  block_partials<K>(s, k, part);
+}
+
+// w -= sum_j h[j] V[j], then partials of V[j] . w for the updated w (the
+// second pass's products, taken from the vector the first pass leaves)
+template <int K>
+__global__ void __launch_bounds__(RED_THREADS) k_mcombine_mdot_partial(const double* V, double* w, const double* h,
+                                                                         int k, int64_t len, double* part) {
+  double s[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) s[j] = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x) {
+    double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (j < k) wi -= h[j] * V[int64_t(j) * len + i];
+    w[i] = wi;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (j < k) s[j] += V[int64_t(j) * len + i] * wi;
+  }
+  block_partials<K>(s, k, part);
+}
+
+// w -= sum_j h[j] V[j], then the partial of w . w
+__global__ void __launch_bounds__(RED_THREADS) k_mcombine_sq_partial(const double* V, double* w, const double* h,
+                                                                       int k, int64_t len, double* part) {
+  double s[1] = {0.0};
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x) {
+    double wi = w[i];
+    for (int j = 0; j < k; ++j) wi -= h[j] * V[int64_t(j) * len + i];
+    w[i] = wi;
+    s[0] += wi * wi;
+  }
+  block_partials<1>(s, 1, part);
+}
+
 // stage 2: out[j] = sum over nb blocks of part[blk * k + j]
+// (one block per column when launched with k blocks)
 __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double* part, int nb, int k, double* out) {
-  __shared__ double sh[RED_THREADS];
-  for (int j = 0; j < k; ++j) {
+  __shared__ double sh[RED_THREADS / 64];
+  for (int j = blockIdx.x; j < k; j += gridDim.x) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i * k + j];
-    sh[threadIdx.x] = s;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[int64_t(i) * k + j];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-      __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int q = 0; q < RED_THREADS / 64; ++q) t += sh[q];
+      out[j] = t;
     }
-    if (threadIdx.x == 0) out[j] = sh[0];
     __syncthreads();
   }
 }
