@@ -7,8 +7,12 @@
 //   2. each thread gathers its cell's nodal values from LDS, applies the
 //      hanging-node interpolation, runs the sum-factorised pointwise law,
 //      integrates and applies the transposed hanging-node map;
-//   3. colour-phased accumulation into LDS accumulators over all local nodes
-//      (cells of one colour share no node: deterministic, no atomics);
+//   3. accumulation into LDS accumulators over all local nodes with
+//      no-return LDS atomic adds, in colour phases (cells of one colour share
+//      no node) when the tile spans several waves or uses substituted
+//      footprints, in one phase for one-wave tiles (one lane's k-th node is
+//      never another lane's k-th node, and a wave's LDS operations execute in
+//      program order): the summation order is fixed either way;
 //   4. private nodes are complete and go through the mode's epilogue in one
 //      coalesced write; shared nodes leave a partial sum in the tile's slots,
 //      which shared_fixup adds in ascending tile order before the epilogue.
@@ -145,8 +149,11 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ML = a.max_local;
   T* lds = reinterpret_cast<T*>(smem_raw);   // staged fields [NF][max_local]
-  T* acc = lds + (NF > 0 ? NF : 1) * ML;     // accumulators [3][max_local]
-  uint8_t* lflag = reinterpret_cast<uint8_t*>(acc + 3 * ML);     // [max_local]
+  // the accumulators [3][max_local] reuse the first three field arrays once
+  // every cell has gathered its values (one LDS region of max(NF, 3) arrays
+  // keeps the footprint per tile, and so the tiles per CU, at its minimum)
+  T* acc = lds;
+  uint8_t* lflag = reinterpret_cast<uint8_t*>(lds + (NF > 3 ? NF : 3) * ML);     // [max_local]
 
   // XCD-aware order: workgroups go to the 8 XCDs round-robin, so XCD x
   // receives a contiguous chunk of the tile list and neighbouring tiles (which
@@ -155,17 +162,24 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   const int xq = nb >> 3, xr = nb & 7, xcd = bid & 7;
   const int order_idx = xcd * xq + (xcd < xr ? xcd : xr) + (bid >> 3);
   const int tile = a.tile_base + order_idx;
-  const int32_t* ti = a.tile_info + TILE_STRIDE * tile;
+  // the whole tile header goes into scalar registers in one batch of loads;
+  // reading it field by field under the branches below would serialise a
+  // scalar-load round trip per run
+  int ti[TILE_STRIDE];
+  {
+    const int32_t* tp = a.tile_info + TILE_STRIDE * tile;
+#pragma unroll
+    for (int k = 0; k < TILE_STRIDE; ++k) ti[k] = tp[k];
+  }
   const int o0 = ti[TILE_OWNED0], no = ti[TILE_NOWNED];
   const int s0 = ti[TILE_SHARED0], ns = ti[TILE_NSHARED];
   const int c0 = ti[TILE_CELL0], nc = ti[TILE_NCELL];
   const int ncol = ti[TILE_NCOLOR];
   const int slot0 = ti[TILE_SLOT0];
   const int nrun = ti[TILE_NRUN];
-  // global id of shared entry r: from the runs in the tile header, so the
-  // shared values load without a dependent lookup; the list otherwise
-  auto shared_id = [&](int r) -> int64_t {
-    if (nrun == 0) return a.shared[s0 + r];
+  // global id of shared entry r from the runs of consecutive ids in the tile
+  // header (no dependent lookup); tiles with more runs use the shared list
+  auto run_id = [&](int r) -> int64_t {
     int id = ti[TILE_RUN_START] + r;
 #pragma unroll
     for (int k = 1; k < TILE_MAX_RUNS; ++k)
@@ -184,68 +198,85 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   const T kap = T(m.kappa), pr = T(m.pressure), Gc = T(m.Gc), ell = T(m.ell);
   const T mu = T(m.mu), lam = T(m.lam);
 
-  // the cell record is loaded before staging so that its latency overlaps
-  // with the node loads
   const int cell = int(threadIdx.x);
   const bool live = cell < nc;
   int loc[NL];
   unsigned info = 0;
-  if (live) {
-    const int64_t rec = int64_t(c0) + cell;
-    const uint16_t* cl = (MODE == MODE_DIAG_LEAF) ? a.cell_loc_sub : a.cell_loc;
+  // the cell record is requested after the first round's node loads (see
+  // below): its latency overlaps theirs instead of preceding them
+  auto load_cell_record = [&]() {
+    if (live) {
+      const int64_t rec = int64_t(c0) + cell;
+      const uint16_t* cl = (MODE == MODE_DIAG_LEAF) ? a.cell_loc_sub : a.cell_loc;
 #pragma unroll
-    for (int k = 0; k < NL; ++k) loc[k] = cl[rec * NL + k];
-    info = a.cell_info[rec];
-  }
-
-  // 1. stage local nodes. Per round, the shared ids are requested first;
-  //    the private range needs no lookup, so its loads go out while the ids
-  //    are in flight, then the shared values; one LDS store pass at the end.
-  //    The Jacobian modes write their identity rows (constrained private
-  //    nodes) here, from the raw values.
-  constexpr bool JMODE = (MODE == MODE_J || MODE == MODE_JT);
-  constexpr int SP = 4, SS = 2;   // private / shared nodes per thread and round
-  const int bs = int(blockDim.x), tid = int(threadIdx.x);
-  for (int rp = 0, rs = 0; rp < no || rs < ns; rp += SP * bs, rs += SS * bs) {
-    int64_t gsh[SS];
-#pragma unroll
-    for (int k = 0; k < SS; ++k) {
-      const int r = rs + k * bs + tid;
-      gsh[k] = r < ns ? shared_id(r) : int64_t(-1);
+      for (int k = 0; k < NL; ++k) loc[k] = cl[rec * NL + k];
+      info = a.cell_info[rec];
     }
+  };
+
+  // 1. stage local nodes. Per round: the shared ids (from the header runs,
+  //    else the list), then every node load of the round as one batch, the
+  //    cell record in the first round, and one LDS store pass at the end, so
+  //    that a tile waits for memory about once. The Jacobian modes write
+  //    their identity rows (constrained private nodes) here, from the raw
+  //    values.
+  constexpr bool JMODE = (MODE == MODE_J || MODE == MODE_JT);
+  // private / shared nodes per thread and round, sized for the default tiles
+  // (Q1: 16 x 16 cells on four waves, Q2: 8 x 8 cells on one wave) so that
+  // one round covers a tile without many idle lanes
+  constexpr int SP = P == 1 ? 1 : 4, SS = P == 1 ? 1 : 2;
+  const int bs = int(blockDim.x), tid = int(threadIdx.x);
+  bool first = true;
+  for (int rp = 0, rs = 0; rp < no || rs < ns; rp += SP * bs, rs += SS * bs) {
+    // shared ids before any load is in flight: with the list, the wait for
+    // the ids then holds nothing else up
+    int64_t gsh[SS];
+    if (nrun > 0) {
+#pragma unroll
+      for (int k = 0; k < SS; ++k) {
+        const int r = rs + k * bs + tid;
+        gsh[k] = r < ns ? run_id(r) : int64_t(-1);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < SS; ++k) {
+        const int r = rs + k * bs + tid;
+        gsh[k] = r < ns ? int64_t(a.shared[s0 + r]) : int64_t(-1);
+      }
+    }
+    // loads without branches (out-of-range lanes read an in-range node and
+    // discard it), so that they issue as one batch
     uint8_t fp_[SP], fsh[SS];
     T vp[SP][NF > 0 ? NF : 1], vsh[SS][NF > 0 ? NF : 1];
 #pragma unroll
     for (int k = 0; k < SP; ++k) {
       const int l = rp + k * bs + tid;
-      const int64_t g = int64_t(o0) + l;
-      fp_[k] = l < no ? a.flags[g] : uint8_t(0);
+      const int64_t g = min(int64_t(o0) + min(l, max(no - 1, 0)), n - 1);
+      fp_[k] = a.flags[g];
       if constexpr (NF > 0) {
-        if (l < no) {
-          if constexpr (TR::n_src > 0) {
+        if constexpr (TR::n_src > 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) vp[k][c] = a.src[c * n + g];
-          }
-#pragma unroll
-          for (int st = 0; st < TR::n_state; ++st) vp[k][TR::n_src + st] = a.st[st][g];
+          for (int c = 0; c < 3; ++c) vp[k][c] = a.src[c * n + g];
         }
+#pragma unroll
+        for (int st = 0; st < TR::n_state; ++st) vp[k][TR::n_src + st] = a.st[st][g];
       }
     }
 #pragma unroll
     for (int k = 0; k < SS; ++k) {
-      const int64_t g = gsh[k];
-      fsh[k] = g >= 0 ? a.flags[g] : uint8_t(0);
+      const int64_t g = gsh[k] >= 0 ? gsh[k] : int64_t(0);
+      fsh[k] = a.flags[g];
       if constexpr (NF > 0) {
-        if (g >= 0) {
-          if constexpr (TR::n_src > 0) {
+        if constexpr (TR::n_src > 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) vsh[k][c] = a.src[c * n + g];
-          }
-#pragma unroll
-          for (int st = 0; st < TR::n_state; ++st) vsh[k][TR::n_src + st] = a.st[st][g];
+          for (int c = 0; c < 3; ++c) vsh[k][c] = a.src[c * n + g];
         }
+#pragma unroll
+        for (int st = 0; st < TR::n_state; ++st) vsh[k][TR::n_src + st] = a.st[st][g];
       }
     }
+    if (first) load_cell_record();
+    first = false;
     auto put = [&](int l, uint8_t f, const T* v) {
       lflag[l] = f;
       if constexpr (NF > 0) {
@@ -284,11 +315,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       if (r < ns) put(no + r, fsh[k], vsh[k]);
     }
   }
-  for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
-    acc[l] = T(0);
-    acc[ML + l] = T(0);
-    acc[2 * ML + l] = T(0);
-  }
+  if (first) load_cell_record();
   __syncthreads();
   if constexpr (NODE_HANG && NF > 0) {
     if (nhang > 0) {
@@ -592,11 +619,24 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         integrate<P, T>(a.B, f, zero, zero, out[2]);
       }
     }
+    // every gather is done: the accumulators take over the field arrays
+    __syncthreads();
+    for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
+      acc[l] = T(0);
+      acc[ML + l] = T(0);
+      acc[2 * ML + l] = T(0);
+    }
+    __syncthreads();
     // LDS atomic adds without return: no read-modify-write round trip per
-    // entry. Within a phase no two lanes address the same node, and one
-    // lane's adds execute in program order, so the summation order is fixed.
-    for (int col = 0; col < ncol; ++col) {
-      if (live && color == col) {
+    // entry. Within a phase no two lanes address the same node in one
+    // instruction, and a wave's adds execute in program order, so the
+    // summation order is fixed. A one-wave tile over the cells' own nodes
+    // needs no colour phases: two distinct cells never have the same node at
+    // the same local position.
+    const bool one_phase = !HANG && blockDim.x <= 64;
+    const int nphase = one_phase ? 1 : ncol;
+    for (int col = 0; col < nphase; ++col) {
+      if (live && (one_phase || color == col)) {
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
           const int l = loc[k];
