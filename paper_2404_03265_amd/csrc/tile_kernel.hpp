@@ -226,6 +226,12 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   // one round covers a tile without many idle lanes
   constexpr int SP = P == 1 ? 1 : 4, SS = P == 1 ? 1 : 2;
   const int bs = int(blockDim.x), tid = int(threadIdx.x);
+  // Jacobian modes: when one round covers the private range, each thread
+  // keeps the raw source values of its private nodes in registers and the
+  // epilogue writes every private row once (identity or product) with full
+  // lanes; otherwise the identity rows are written here.
+  const bool keep_raw = JMODE && no <= SP * bs;
+  T raw[JMODE ? SP : 1][3];
   bool first = true;
   for (int rp = 0, rs = 0; rp < no || rs < ns; rp += SP * bs, rs += SS * bs) {
     // shared ids before any load is in flight: with the list, the wait for
@@ -303,8 +309,9 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
           const int64_t g = int64_t(o0) + l;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
+            raw[k][c] = vp[k][c];
             const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
-            if (cons) a.dst[c * n + g] = vp[k][c];
+            if (cons && !keep_raw) a.dst[c * n + g] = vp[k][c];
           }
         }
       }
@@ -671,10 +678,28 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   }
 
   // 4. private nodes through the epilogue, shared nodes into the tile's slots
-  for (int l = threadIdx.x; l < no; l += blockDim.x) {
-    const uint8_t f = lflag[l];
+  if (keep_raw) {
+    if constexpr (JMODE) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, true, T>(a, c, int64_t(o0) + l, f, acc[c * ML + l]);
+      for (int k = 0; k < SP; ++k) {
+        const int l = k * int(blockDim.x) + int(threadIdx.x);
+        if (l < no) {
+          const uint8_t f = lflag[l];
+          const int64_t g = int64_t(o0) + l;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
+            a.dst[c * n + g] = cons ? raw[k][c] : acc[c * ML + l];
+          }
+        }
+      }
+    }
+  } else {
+    for (int l = threadIdx.x; l < no; l += blockDim.x) {
+      const uint8_t f = lflag[l];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, true, T>(a, c, int64_t(o0) + l, f, acc[c * ML + l]);
+    }
   }
   for (int r = threadIdx.x; r < ns; r += blockDim.x) {
 #pragma unroll
