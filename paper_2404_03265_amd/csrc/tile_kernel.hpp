@@ -226,12 +226,31 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   // one round covers a tile without many idle lanes
   constexpr int SP = P == 1 ? 1 : 4, SS = P == 1 ? 1 : 2;
   const int bs = int(blockDim.x), tid = int(threadIdx.x);
-  // Jacobian modes: when one round covers the private range, each thread
-  // keeps the raw source values of its private nodes in registers and the
-  // epilogue writes every private row once (identity or product) with full
-  // lanes; otherwise the identity rows are written here.
-  const bool keep_raw = JMODE && no <= SP * bs;
-  T raw[JMODE ? SP : 1][3];
+  // When one round covers the private range, each thread keeps what the
+  // epilogue of its private rows needs in registers: the raw source values
+  // (Jacobian identity rows, smoother iterate) and, for the level smoother
+  // and residual, b, D^-1 and the previous update, requested here with the
+  // node loads so that the epilogue issues no dependent load. The Jacobian
+  // modes otherwise write their identity rows while staging.
+  constexpr bool LPRE = MODE == MODE_LEVEL && (EPI == EPI_CHEB || EPI == EPI_RESID);
+  constexpr bool CHEB = MODE == MODE_LEVEL && EPI == EPI_CHEB;
+  constexpr int NPRE = (JMODE || LPRE) ? SP : 1;
+  const bool keep_raw = (JMODE || LPRE) && no <= SP * bs;
+  T raw[NPRE][3], pb[LPRE ? SP : 1][3], pdi[CHEB ? SP : 1][3], pdo[CHEB ? SP : 1][3];
+  if constexpr (LPRE) {
+#pragma unroll
+    for (int k = 0; k < SP; ++k) {
+      const int64_t g = min(int64_t(o0) + min(k * bs + tid, max(no - 1, 0)), n - 1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        pb[k][c] = a.b[c * n + g];
+        if constexpr (CHEB) {
+          pdi[k][c] = a.dinv[c * n + g];
+          pdo[k][c] = a.dold ? a.dold[c * n + g] : T(0);
+        }
+      }
+    }
+  }
   bool first = true;
   for (int rp = 0, rs = 0; rp < no || rs < ns; rp += SP * bs, rs += SS * bs) {
     // shared ids before any load is in flight: with the list, the wait for
@@ -304,6 +323,10 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       const int l = rp + k * bs + tid;
       if (l < no) {
         put(l, fp_[k], vp[k]);
+        if constexpr (LPRE) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) raw[k][c] = vp[k][c];
+        }
         if constexpr (JMODE) {
           const uint8_t f = fp_[k];
           const int64_t g = int64_t(o0) + l;
@@ -679,17 +702,30 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
 
   // 4. private nodes through the epilogue, shared nodes into the tile's slots
   if (keep_raw) {
-    if constexpr (JMODE) {
 #pragma unroll
-      for (int k = 0; k < SP; ++k) {
-        const int l = k * int(blockDim.x) + int(threadIdx.x);
-        if (l < no) {
-          const uint8_t f = lflag[l];
-          const int64_t g = int64_t(o0) + l;
+    for (int k = 0; k < NPRE; ++k) {
+      const int l = k * int(blockDim.x) + int(threadIdx.x);
+      if (l < no) {
+        const uint8_t f = lflag[l];
+        const int64_t g = int64_t(o0) + l;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < 3; ++c) {
+          const int64_t i = c * n + g;
+          const T v = acc[c * ML + l];
+          if constexpr (JMODE) {
             const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
-            a.dst[c * n + g] = cons ? raw[k][c] : acc[c * ML + l];
+            a.dst[i] = cons ? raw[k][c] : v;
+          } else if constexpr (CHEB) {
+            // the level smoother step, as in node_epilogue
+            const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
+            const int blk = c < 2 ? 0 : 1;
+            const T x = raw[k][c];
+            const T dn = a.c1[blk] * pdo[k][c] + a.c2[blk] * pdi[k][c] * (pb[k][c] - v);
+            a.dst[i] = fixed ? T(0) : dn;
+            a.xnew[i] = fixed ? x : x + dn;
+          } else if constexpr (LPRE) {
+            const bool held = (c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
+            a.dst[i] = held ? T(0) : pb[k][c] - v;
           }
         }
       }
