@@ -395,13 +395,27 @@ __global__ void __launch_bounds__(RED_THREADS) k_mcombine_mdot_partial(const dou
   for (int j = 0; j < K; ++j) s[j] = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x) {
     double wi = w[i];
+    if constexpr (K <= 32) {
+      // the K values of element i stay in registers for both passes (a second
+      // read would miss the caches: a wave touches K lines per element)
+      double v[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j)
-      if (j < k) wi -= h[j] * V[int64_t(j) * len + i];
-    w[i] = wi;
+      for (int j = 0; j < K; ++j) {
+        v[j] = j < k ? V[int64_t(j) * len + i] : 0.0;
+        wi -= h[j < k ? j : 0] * v[j];
+      }
+      w[i] = wi;
 #pragma unroll
-    for (int j = 0; j < K; ++j)
-      if (j < k) s[j] += V[int64_t(j) * len + i] * wi;
+      for (int j = 0; j < K; ++j) s[j] += v[j] * wi;
+    } else {
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (j < k) wi -= h[j] * V[int64_t(j) * len + i];
+      w[i] = wi;
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (j < k) s[j] += V[int64_t(j) * len + i] * wi;
+    }
   }
   block_partials<K>(s, k, part);
 }
