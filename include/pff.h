@@ -73,12 +73,14 @@ typedef struct {
  *  ell: phase-field length scale l (Sec. 2, Table 1).
  *  cheb_degree: Chebyshev updates per smoothing step; smooth_range (0.08) and
  *  upper_factor (1.2): smoothing interval [smooth_range, upper_factor] *
- *  lambda_max (Sec. 3.2); eig_cg_its: CG steps of the eigenvalue estimate;
+ *  lambda_max (Sec. 3.2); eig_cg_its: CG steps of the eigenvalue estimate
+ *  (1..200, else PFF_E_ARG);
  *  coarse_mode 0: Chebyshev over [lambda_min, upper_factor * lambda_max] on
  *  level 0 with coarse_its updates (Sec. 3.2); coarse_mode 1: coarse_its
  *  Jacobi-preconditioned CG steps from zero on level 0, each block with its
  *  own scalars (a fixed number of steps, so the cycle is reproducible; it is
- *  not a linear operator); coarse_eig_its: CG steps for the level-0 estimate.
+ *  not a linear operator); coarse_eig_its: CG steps for the level-0 estimate
+ *  (1..200).
  *  gmres_restart, gmres_max_its, gmres_rtol, gmres_atol: GMRES(m) stops when
  *  the preconditioned residual is below max(atol, rtol * |rhs|) (Table 1).
  *  ls_omega, ls_max: line-search damping omega and l_max (Alg. 2).

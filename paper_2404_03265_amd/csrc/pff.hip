@@ -213,6 +213,10 @@ struct pff_ctx {
   double* wv[8] = {};
   double* red_part = nullptr;
   double* red_out = nullptr;
+  // eigenvalue-estimate CG: per-block scalars and Lanczos coefficients
+  double* eig_sc = nullptr;
+  double* eig_al = nullptr;
+  double* eig_be = nullptr;
   double* host_red = nullptr;   // pinned
   double* V = nullptr;          // GMRES basis
   double* ccg_s = nullptr;      // coarse CG scalars
@@ -532,6 +536,11 @@ struct pff_ctx {
 
   // Extreme Ritz values of D^{-1} A (free unknowns of one block) from
   // `its` Jacobi-preconditioned CG steps on A x = 1.
+  // Extreme eigenvalues of D^-1 A on each block of level l by `its` steps of
+  // Jacobi-preconditioned CG from r = 1 on the free unknowns, through the
+  // Lanczos tridiagonal of its coefficients. The level operator is block
+  // diagonal, so both blocks run at once (one operator application per step);
+  // their scalars stay on the device and are read back once at the end.
   void eig_estimate(int l, int its) {
     DevLevel& L = lv[l];
     LevelWork<double>& w = w64of(L);
@@ -540,46 +549,67 @@ struct pff_ctx {
     double* z = w.x[1];
     double* pv = w.dir[0];
     double* q = w.dir[1];
-    for (int blk = 0; blk < 2; ++blk) {
-      const int64_t off = blk == 0 ? 0 : 2 * nl, len = blk == 0 ? 2 * nl : nl;
-      // r = 1 on free unknowns of the block (dinv != 0 exactly there), else 0
-      hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(3 * nl)), dim3(256), 0, s, r, 0.0, 3 * nl);
-      hipLaunchKernelGGL(k_free_ones, dim3(grid_for(len)), dim3(256), 0, s, r + off, w.dinv + off, len);
-      hipLaunchKernelGGL(k_mul, dim3(grid_for(3 * nl)), dim3(256), 0, s, z, w.dinv, r, 3 * nl);
-      HIPCHK(hipMemcpyAsync(pv, z, sizeof(double) * 3 * nl, hipMemcpyDeviceToDevice, s));
-      const double n_free = dot(r + off, r + off, len);
-      double rz = dot(r + off, z + off, len);
-      const double rz0 = rz;
-      std::vector<double> al, be;
-      // at most `its` steps and never more than the number of free unknowns;
-      // stop once the residual has dropped by 1e-12
-      const int max_it = int(std::min<double>(its, n_free));
-      for (int it = 0; it < max_it && rz > 0.0; ++it) {
-        level_apply<double>(l, pv, q, EPI_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr);
-        // only the block's free rows matter: p is zero elsewhere
-        const double pq = dot(pv + off, q + off, len);
-        if (!(pq > 0.0)) break;
-        const double alpha = rz / pq;
-        hipLaunchKernelGGL(k_cg_update, dim3(grid_for(len)), dim3(256), 0, s, r + off, z + off, q + off,
-                           w.dinv + off, alpha, len);
-        const double rz2 = dot(r + off, z + off, len);
-        const double beta = rz2 / rz;
-        al.push_back(alpha);
-        be.push_back(beta);
-        hipLaunchKernelGGL(k_waxpy, dim3(grid_for(len)), dim3(256), 0, s, pv + off, z + off, pv + off, beta, len);
-        rz = rz2;
-        if (rz <= 1e-24 * rz0) break;
-      }
-      const int m = int(al.size());
+    const int64_t off[2] = {0, 2 * nl}, len[2] = {2 * nl, nl};
+    // r = 1 on free unknowns (dinv != 0 exactly there), z = D^-1 r, p = z
+    hipLaunchKernelGGL(k_free_ones, dim3(grid_for(3 * nl)), dim3(256), 0, s, r, w.dinv, 3 * nl);
+    hipLaunchKernelGGL(k_mul, dim3(grid_for(3 * nl)), dim3(256), 0, s, z, w.dinv, r, 3 * nl);
+    HIPCHK(hipMemcpyAsync(pv, z, sizeof(double) * 3 * nl, hipMemcpyDeviceToDevice, s));
+    double* sc = eig_sc;
+    for (int b = 0; b < 2; ++b) {
+      dot2_async(r + off[b], r + off[b], len[b], sc + EIG_SC * b + EIG_PQ);   // n_free (scratch slot)
+      dot2_async(r + off[b], z + off[b], len[b], sc + EIG_SC * b + EIG_RZ);
+    }
+    double h[2 * EIG_SC];
+    HIPCHK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // at most `its` steps and never more than the number of free unknowns;
+    // stop once r.z has dropped by 1e-24
+    int max_it = 0;
+    for (int b = 0; b < 2; ++b) {
+      double* c = h + EIG_SC * b;
+      const double n_free = c[EIG_PQ];
+      c[EIG_RZ0] = c[EIG_RZ];
+      c[EIG_MAX] = std::min<double>(its, n_free);
+      c[EIG_ACTIVE] = (c[EIG_MAX] >= 1.0 && c[EIG_RZ] > 0.0) ? 1.0 : 0.0;
+      c[EIG_STEPS] = 0.0;
+      max_it = std::max(max_it, int(c[EIG_MAX]));
+    }
+    HIPCHK(hipMemcpyAsync(sc, h, sizeof(h), hipMemcpyHostToDevice, s));
+    const int stride = EIG_MAX_ITS;
+    max_it = std::min(max_it, stride);
+    for (int it = 0; it < max_it; ++it) {
+      level_apply<double>(l, pv, q, EPI_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr);
+      for (int b = 0; b < 2; ++b) dot2_async(pv + off[b], q + off[b], len[b], sc + EIG_SC * b + EIG_PQ);
+      hipLaunchKernelGGL(k_eig_alpha, dim3(1), dim3(64), 0, s, sc, eig_al, stride, it);
+      for (int b = 0; b < 2; ++b)
+        hipLaunchKernelGGL(k_cg_update_dev, dim3(grid_for(len[b])), dim3(256), 0, s, r + off[b], z + off[b],
+                           q + off[b], w.dinv + off[b], sc + EIG_SC * b, len[b]);
+      for (int b = 0; b < 2; ++b) dot2_async(r + off[b], z + off[b], len[b], sc + EIG_SC * b + EIG_RZ2);
+      hipLaunchKernelGGL(k_eig_beta, dim3(1), dim3(64), 0, s, sc, eig_be, stride, it);
+      for (int b = 0; b < 2; ++b)
+        hipLaunchKernelGGL(k_waxpy_dev, dim3(grid_for(len[b])), dim3(256), 0, s, pv + off[b], z + off[b],
+                           sc + EIG_SC * b, len[b]);
+    }
+    std::vector<double> al(2 * stride), be(2 * stride);
+    HIPCHK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
+    if (max_it > 0) {
+      HIPCHK(hipMemcpyAsync(al.data(), eig_al, sizeof(double) * 2 * stride, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(be.data(), eig_be, sizeof(double) * 2 * stride, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (int b = 0; b < 2; ++b) {
+      const int m = int(h[EIG_SC * b + EIG_STEPS]);
       double lo = 1.0, hi = 1.0;
       if (m > 0) {
+        const double* A = al.data() + b * stride;
+        const double* B = be.data() + b * stride;
         std::vector<double> dg(m), of(m > 1 ? m - 1 : 0);
-        for (int j = 0; j < m; ++j) dg[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
-        for (int j = 0; j + 1 < m; ++j) of[j] = std::sqrt(be[j]) / al[j];
+        for (int j = 0; j < m; ++j) dg[j] = 1.0 / A[j] + (j > 0 ? B[j - 1] / A[j - 1] : 0.0);
+        for (int j = 0; j + 1 < m; ++j) of[j] = std::sqrt(B[j]) / A[j];
         tridiag_extremes(dg, of, &lo, &hi);
       }
-      L.lam_max[blk] = hi;
-      L.lam_min[blk] = lo;
+      L.lam_max[b] = hi;
+      L.lam_min[b] = lo;
     }
   }
 
@@ -825,7 +855,9 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
   ms.tile_x = spec->tile_x;
   ms.tile_y = spec->tile_y;
   if (params->cheb_degree < 1 || params->coarse_its < 1 || params->gmres_restart < 1 ||
-      params->gmres_restart > 60 || params->coarse_mode < 0 || params->coarse_mode > 1)
+      params->gmres_restart > 60 || params->coarse_mode < 0 || params->coarse_mode > 1 ||
+      params->eig_cg_its < 1 || params->eig_cg_its > EIG_MAX_ITS || params->coarse_eig_its < 1 ||
+      params->coarse_eig_its > EIG_MAX_ITS)
     return PFF_E_ARG;
   try {
     bool built = false;
@@ -876,6 +908,9 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
     c->part = dalloc<double>(3 * std::max<int64_t>(slots, 1));
     c->red_part = dalloc<double>(RED_BLOCKS * 64);
     c->red_out = dalloc<double>(256);
+    c->eig_sc = dalloc<double>(2 * EIG_SC);
+    c->eig_al = dalloc<double>(2 * EIG_MAX_ITS);
+    c->eig_be = dalloc<double>(2 * EIG_MAX_ITS);
     c->ccg_s = dalloc<double>(8);
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->host_red), 256 * sizeof(double), hipHostMallocDefault));
     // lumped phase-field mass (the B of Alg. 2)
@@ -911,7 +946,7 @@ int pff_destroy(pff_ctx* c) {
   }
   f(c->U); f(c->phio); f(c->phit); f(c->mass);
   for (int i = 0; i < 8; ++i) f(c->wv[i]);
-  f(c->red_part); f(c->red_out); f(c->V); f(c->part); f(c->ccg_s);
+  f(c->red_part); f(c->red_out); f(c->V); f(c->part); f(c->ccg_s); f(c->eig_sc); f(c->eig_al); f(c->eig_be);
   if (c->host_red) hipHostFree(c->host_red);
   delete c;
   return PFF_OK;
@@ -920,7 +955,8 @@ int pff_destroy(pff_ctx* c) {
 int pff_set_params(pff_ctx* c, const pff_params* p) {
   if (!c || !p) return PFF_E_ARG;
   if (p->cheb_degree < 1 || p->coarse_its < 1 || p->gmres_restart < 1 || p->gmres_restart > 60 ||
-      p->coarse_mode < 0 || p->coarse_mode > 1)
+      p->coarse_mode < 0 || p->coarse_mode > 1 || p->eig_cg_its < 1 || p->eig_cg_its > EIG_MAX_ITS ||
+      p->coarse_eig_its < 1 || p->coarse_eig_its > EIG_MAX_ITS)
     return PFF_E_ARG;
   c->prm = *p;
   c->mg_ready = false;

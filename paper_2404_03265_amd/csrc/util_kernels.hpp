@@ -325,6 +325,60 @@ __global__ void k_cg_update(double* r, double* z, const double* q, const double*
   }
 }
 
+// ---- eigenvalue-estimate CG with its scalars on the device ----------------
+// Both blocks of a level (u rows, phi rows) run their CG at once; sc holds
+// EIG_SC doubles per block: rz, pq, rz2, alpha, beta, rz0, active, steps,
+// max_steps. The step kernels reproduce the host recurrence: alpha = rz / pq
+// (stop if pq <= 0), beta = rz2 / rz, stop once rz2 <= 1e-24 rz0 or after
+// max_steps; al / be collect the coefficients of the Lanczos tridiagonal.
+constexpr int EIG_SC = 9;
+constexpr int EIG_MAX_ITS = 200;   // largest accepted eig_cg_its / coarse_eig_its
+enum { EIG_RZ = 0, EIG_PQ, EIG_RZ2, EIG_ALPHA, EIG_BETA, EIG_RZ0, EIG_ACTIVE, EIG_STEPS, EIG_MAX };
+
+__global__ void k_eig_alpha(double* sc, double* al, int stride, int it) {
+  const int b = threadIdx.x;
+  if (b >= 2) return;
+  double* c = sc + EIG_SC * b;
+  if (c[EIG_ACTIVE] == 0.0) return;
+  const double pq = c[EIG_PQ];
+  if (!(pq > 0.0)) {
+    c[EIG_ACTIVE] = 0.0;
+    return;
+  }
+  const double alpha = c[EIG_RZ] / pq;
+  c[EIG_ALPHA] = alpha;
+  al[b * stride + it] = alpha;
+}
+__global__ void k_eig_beta(double* sc, double* be, int stride, int it) {
+  const int b = threadIdx.x;
+  if (b >= 2) return;
+  double* c = sc + EIG_SC * b;
+  if (c[EIG_ACTIVE] == 0.0) return;
+  const double rz2 = c[EIG_RZ2];
+  const double beta = rz2 / c[EIG_RZ];
+  c[EIG_BETA] = beta;
+  be[b * stride + it] = beta;
+  c[EIG_RZ] = rz2;
+  c[EIG_STEPS] = double(it + 1);
+  if (rz2 <= 1e-24 * c[EIG_RZ0] || double(it + 1) >= c[EIG_MAX]) c[EIG_ACTIVE] = 0.0;
+}
+// r -= alpha q on free rows, z = D^-1 r (no-op once the block has stopped)
+__global__ void k_cg_update_dev(double* r, double* z, const double* q, const double* dinv, const double* c,
+                                int64_t len) {
+  if (c[EIG_ACTIVE] == 0.0) return;
+  const double alpha = c[EIG_ALPHA];
+  GRID_LOOP(i, len) {
+    if (dinv[i] != 0.0) r[i] -= alpha * q[i];
+    z[i] = dinv[i] * r[i];
+  }
+}
+// p = z + beta p (no-op once the block has stopped)
+__global__ void k_waxpy_dev(double* p, const double* z, const double* c, int64_t len) {
+  if (c[EIG_ACTIVE] == 0.0) return;
+  const double beta = c[EIG_BETA];
+  GRID_LOOP(i, len) p[i] = z[i] + beta * p[i];
+}
+
 // stage 1 of a dot product: one partial per block, fixed order
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) k_dot_partial(const T* a, const T* b, int64_t len, double* part) {
