@@ -267,7 +267,7 @@ struct pff_ctx {
     using TR = ModeTraits<MODE>;
     constexpr int NF = TR::n_src + TR::n_state;
     // staged fields (the accumulators reuse the first three), node flags
-    const size_t lds = size_t((NF > 3 ? NF : 3) * t.max_local) * sizeof(T) + size_t(t.max_local);
+    const size_t lds = size_t((NF > 3 ? NF : 3) * t.max_local) * sizeof(double) + size_t(t.max_local);
     // one thread per cell of the largest tile
     const int threads = std::max(64, ((t.max_cells + 63) / 64) * 64);
     if (threads > 256) throw std::runtime_error("a tile holds at most 256 cells");

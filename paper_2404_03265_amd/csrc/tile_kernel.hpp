@@ -148,11 +148,12 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   constexpr int NF = TR::n_src + TR::n_state;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ML = a.max_local;
-  T* lds = reinterpret_cast<T*>(smem_raw);   // staged fields [NF][max_local]
+  using LT = double;   // LDS values (FP64 for both precisions)
+  LT* lds = reinterpret_cast<LT*>(smem_raw);   // staged fields [NF][max_local]
   // the accumulators [3][max_local] reuse the first three field arrays once
   // every cell has gathered its values (one LDS region of max(NF, 3) arrays
   // keeps the footprint per tile, and so the tiles per CU, at its minimum)
-  T* acc = lds;
+  LT* acc = lds;
   uint8_t* lflag = reinterpret_cast<uint8_t*>(lds + (NF > 3 ? NF : 3) * ML);     // [max_local]
 
   // XCD-aware order: workgroups go to the 8 XCDs round-robin, so XCD x
@@ -314,7 +315,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
               if (fixed) x = T(0);
             }
           }
-          lds[c * ML + l] = x;
+          lds[c * ML + l] = LT(x);
         }
       }
     };
@@ -357,7 +358,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         const T w0 = T(hw[0]), w1 = T(hw[1]), w2 = T(hw[2]);
 #pragma unroll
         for (int f = 0; f < NF; ++f)
-          lds[f * ML + h] = w0 * lds[f * ML + m0] + w1 * lds[f * ML + m1] + w2 * lds[f * ML + m2];
+          lds[f * ML + h] = LT(w0 * T(lds[f * ML + m0]) + w1 * T(lds[f * ML + m1]) + w2 * T(lds[f * ML + m2]));
       }
       __syncthreads();
     }
@@ -379,7 +380,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       const bool hang = HANG && MODE == MODE_DIAG_LEAF && (info & 15u);
       auto gather = [&](int field, T(&u)[NL]) {
 #pragma unroll
-        for (int k = 0; k < NL; ++k) u[k] = lds[field * ML + loc[k]];
+        for (int k = 0; k < NL; ++k) u[k] = T(lds[field * ML + loc[k]]);
         if (hang) hang_apply<P, T>(a.B, u, info);
       };
       T wq[NQ];
@@ -652,9 +653,9 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
     // every gather is done: the accumulators take over the field arrays
     __syncthreads();
     for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
-      acc[l] = T(0);
-      acc[ML + l] = T(0);
-      acc[2 * ML + l] = T(0);
+      acc[l] = LT(0);
+      acc[ML + l] = LT(0);
+      acc[2 * ML + l] = LT(0);
     }
     __syncthreads();
     // LDS atomic adds without return: no read-modify-write round trip per
@@ -672,7 +673,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
           const int l = loc[k];
 #pragma unroll
           for (int c = 0; c < 3; ++c)
-            __hip_atomic_fetch_add(&acc[c * ML + l], out[c][k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&acc[c * ML + l], LT(out[c][k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
       __syncthreads();
@@ -689,10 +690,10 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         const int h = hr[0];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const T v = acc[c * ML + h];
+          const LT v = acc[c * ML + h];
 #pragma unroll
           for (int k = 0; k <= P; ++k)
-            __hip_atomic_fetch_add(&acc[c * ML + hr[1 + k]], T(hw[k]) * v, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(&acc[c * ML + hr[1 + k]], LT(T(hw[k])) * v, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
@@ -711,7 +712,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const int64_t i = c * n + g;
-          const T v = acc[c * ML + l];
+          const T v = T(acc[c * ML + l]);
           if constexpr (JMODE) {
             const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
             a.dst[i] = cons ? raw[k][c] : v;
@@ -734,12 +735,12 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
     for (int l = threadIdx.x; l < no; l += blockDim.x) {
       const uint8_t f = lflag[l];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, true, T>(a, c, int64_t(o0) + l, f, acc[c * ML + l]);
+      for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, true, T>(a, c, int64_t(o0) + l, f, T(acc[c * ML + l]));
     }
   }
   for (int r = threadIdx.x; r < ns; r += blockDim.x) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.part[c * a.n_slots + slot0 + r] = acc[c * ML + no + r];
+    for (int c = 0; c < 3; ++c) a.part[c * a.n_slots + slot0 + r] = T(acc[c * ML + no + r]);
   }
 }
 
