@@ -434,7 +434,12 @@ def scenario_quasistatic(g, spec, sp_, increments, log):
         g.set_params(sp_)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        active, infos = solve_load_step(g, U, phi_old, phi_old, active=active, tol=1e-7, max_steps=400)
+        def progress(j, info, k=k):
+            if j % 10 == 0:
+                log(f"  increment {k}: {j} Newton steps, |R~| {info['residual_before']:.2e}, "
+                    f"{info['n_active']} active")
+        active, infos = solve_load_step(g, U, phi_old, phi_old, active=active, tol=1e-7, max_steps=400,
+                                        progress=progress)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         tcv = g.tcv(U)

@@ -24,9 +24,10 @@ class JacobianApply(torch.autograd.Function):
         return ctx.solver.vmult_T(grad.contiguous()), None
 
 
-def solve_load_step(solver, U, phi_old, phi_tilde, active=None, tol=1e-7, max_steps=30):
+def solve_load_step(solver, U, phi_old, phi_tilde, active=None, tol=1e-7, max_steps=30, progress=None):
     """Alg. 2 loop until the active set repeats and |R~| <= tol. U is updated
-    in place; returns (active, list of per-step info dicts)."""
+    in place; returns (active, list of per-step info dicts). progress, if
+    given, is called as progress(step_count, info) after every step."""
     if active is None:
         active = torch.zeros(solver.n, dtype=torch.uint8, device=U.device)
     infos = []
@@ -34,6 +35,8 @@ def solve_load_step(solver, U, phi_old, phi_tilde, active=None, tol=1e-7, max_st
         prev = active.clone()
         info, rc = solver.newton_step(U, phi_old, phi_tilde, active)
         infos.append(info)
+        if progress is not None:
+            progress(len(infos), info)
         if torch.equal(prev, active) and info["residual_before"] <= tol:
             break
     return active, infos
