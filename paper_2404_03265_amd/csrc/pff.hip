@@ -16,6 +16,7 @@
 #include "mesh.hpp"
 #include "tile_kernel.hpp"
 #include "util_kernels.hpp"
+#include "coarse_kernel.hpp"
 
 using namespace pff;
 
@@ -220,6 +221,11 @@ struct pff_ctx {
   double* host_red = nullptr;   // pinned
   double* V = nullptr;          // GMRES basis
   double* ccg_s = nullptr;      // coarse CG scalars
+  // level-0 cells for the one-kernel coarse solve: node ids sorted by colour
+  int32_t* coarse_nodes = nullptr;
+  int coarse_ncell = 0, coarse_ncolor = 0;
+  int coarse_cstart[COARSE_MAX_COLORS + 1] = {};
+  bool coarse_fusable = false;
   void* part = nullptr;         // partial sums of shared nodes (largest tile set)
   size_t part_bytes = 0;
   int V_cap = 0;
@@ -468,6 +474,113 @@ struct pff_ctx {
     return xi;
   }
 
+  // Level-0 cells for the one-kernel coarse solve: global node ids of every
+  // cell, cells coloured greedily so that cells of one colour share no node
+  // and sorted by colour. The solve runs in one kernel when the level fits
+  // one workgroup (at most COARSE_THREADS cells, level-0 cells only, five
+  // vectors in LDS); otherwise the per-step launches are used.
+  void setup_coarse_cells() {
+    const Level& HL = mesh.levels[0];
+    const TileSet& t = HL.tiles;
+    const int NL = (p + 1) * (p + 1);
+    std::vector<std::vector<int32_t>> cells;
+    bool ok = true;
+    for (int tile = 0; tile < t.n_tiles; ++tile) {
+      const int32_t* ti = t.tile_info.data() + TILE_STRIDE * tile;
+      const int o0 = ti[TILE_OWNED0], no = ti[TILE_NOWNED], s0 = ti[TILE_SHARED0];
+      for (int r = ti[TILE_CELL0]; r < ti[TILE_CELL0] + ti[TILE_NCELL]; ++r) {
+        if (((t.cell_info[size_t(r)] >> CELL_LEVEL_SHIFT) & 31u) != 0u || (t.cell_info[size_t(r)] & 15u)) ok = false;
+        std::vector<int32_t> g(static_cast<size_t>(NL), 0);
+        for (int k = 0; k < NL; ++k) {
+          const int l = t.cell_loc[size_t(r) * size_t(NL) + size_t(k)];
+          g[size_t(k)] = l < no ? o0 + l : t.shared[size_t(s0 + l - no)];
+        }
+        cells.push_back(std::move(g));
+      }
+    }
+    const int ncell = int(cells.size());
+    std::vector<int> color(size_t(ncell), 0);
+    std::vector<uint32_t> used(size_t(HL.n), 0u);   // colour bit mask per node
+    int ncolor = 0;
+    for (int c = 0; c < ncell; ++c) {
+      uint32_t m = 0;
+      for (int32_t g : cells[size_t(c)]) m |= used[size_t(g)];
+      int col = 0;
+      while (col < 32 && (m >> col) & 1u) ++col;
+      color[size_t(c)] = col;
+      for (int32_t g : cells[size_t(c)]) used[size_t(g)] |= 1u << col;
+      ncolor = std::max(ncolor, col + 1);
+    }
+    const size_t lds = size_t(15 * HL.n) * sizeof(double) + size_t(HL.n);
+    coarse_fusable = ok && ncell > 0 && ncell <= COARSE_THREADS && ncolor <= COARSE_MAX_COLORS &&
+                     lds <= size_t(160 * 1024);
+    if (!coarse_fusable) return;
+    std::vector<int32_t> flat;
+    flat.reserve(size_t(ncell) * size_t(NL));
+    coarse_cstart[0] = 0;
+    for (int col = 0; col < ncolor; ++col) {
+      for (int c = 0; c < ncell; ++c)
+        if (color[size_t(c)] == col) flat.insert(flat.end(), cells[size_t(c)].begin(), cells[size_t(c)].end());
+      coarse_cstart[col + 1] = int(flat.size() / size_t(NL));
+    }
+    coarse_nodes = upload(flat);
+    coarse_ncell = ncell;
+    coarse_ncolor = ncolor;
+  }
+
+  // the whole level-0 solve in one kernel (Chebyshev or CG, as the
+  // per-step path); result in w.x[0]
+  template <typename T>
+  int coarse_fused() {
+    DevLevel& L = lv[0];
+    LevelWork<T>& w = work<T>(L);
+    CoarseArgs<T> a{};
+    a.n0 = int(L.n);
+    a.ncell = coarse_ncell;
+    a.ncolor = coarse_ncolor;
+    for (int c = 0; c <= coarse_ncolor; ++c) a.cstart[c] = coarse_cstart[c];
+    a.steps = prm.coarse_its;
+    a.cg = prm.coarse_mode == 1 ? 1 : 0;
+    a.cell_nodes = coarse_nodes;
+    a.flags = L.flags;
+    a.state = w.state;
+    a.b = w.d;
+    a.dinv = w.dinv;
+    a.x = w.x[0];
+    a.H = T(mesh.level_H[0]);
+    a.B = make_basis<T>(p);
+    a.mat = mat();
+    if (!a.cg) {
+      // the coefficients of chebyshev(0, b, start from zero, coarse_its)
+      double lo[2], hi[2], theta[2], delta[2], rho_prev[2];
+      interval(0, lo, hi);
+      for (int k = 0; k < 2; ++k) {
+        theta[k] = 0.5 * (hi[k] + lo[k]);
+        delta[k] = 0.5 * (hi[k] - lo[k]);
+        rho_prev[k] = delta[k] / theta[k];
+        a.c1[0][k] = T(0);
+        a.c2[0][k] = T(1.0 / theta[k]);
+      }
+      for (int j = 1; j < a.steps; ++j)
+        for (int k = 0; k < 2; ++k) {
+          const double rho = 1.0 / (2.0 * theta[k] / delta[k] - rho_prev[k]);
+          a.c1[j][k] = T(rho * rho_prev[k]);
+          a.c2[j][k] = T(2.0 * rho / delta[k]);
+          rho_prev[k] = rho;
+        }
+    }
+    const size_t lds = size_t(15 * L.n) * sizeof(double) + size_t(L.n);
+    const void* kfn = p == 1 ? reinterpret_cast<const void*>(&coarse_kernel<1, T>)
+                             : reinterpret_cast<const void*>(&coarse_kernel<2, T>);
+    if (lds > size_t(64 * 1024)) HIPCHK(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    if (p == 1)
+      hipLaunchKernelGGL((coarse_kernel<1, T>), dim3(1), dim3(COARSE_THREADS), lds, s, a);
+    else
+      hipLaunchKernelGGL((coarse_kernel<2, T>), dim3(1), dim3(COARSE_THREADS), lds, s, a);
+    HIPCHK(hipGetLastError());
+    return 0;
+  }
+
   // Coarse solve by a fixed number of Jacobi-preconditioned CG steps from
   // x = 0 (both blocks, each with its own scalars) on level 0's right-hand
   // side; the result is left in w.x[0].
@@ -513,7 +626,10 @@ struct pff_ctx {
     }
     {
       LevelWork<T>& w0 = work<T>(lv[0]);
-      xi[0] = prm.coarse_mode == 1 ? coarse_cg<T>() : chebyshev<T>(0, w0.d, -1, prm.coarse_its);
+      if (coarse_fusable && prm.coarse_its <= COARSE_MAX_STEPS)
+        xi[0] = coarse_fused<T>();
+      else
+        xi[0] = prm.coarse_mode == 1 ? coarse_cg<T>() : chebyshev<T>(0, w0.d, -1, prm.coarse_its);
     }
     for (int l = 1; l <= L; ++l) {
       DevLevel& D = lv[l];
@@ -897,6 +1013,7 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
         upload_transfers(HL, D);
       }
     }
+    c->setup_coarse_cells();
     c->U = dalloc<double>(3 * n);
     c->phio = dalloc<double>(n);
     c->phit = dalloc<double>(n);
@@ -946,7 +1063,7 @@ int pff_destroy(pff_ctx* c) {
   }
   f(c->U); f(c->phio); f(c->phit); f(c->mass);
   for (int i = 0; i < 8; ++i) f(c->wv[i]);
-  f(c->red_part); f(c->red_out); f(c->V); f(c->part); f(c->ccg_s); f(c->eig_sc); f(c->eig_al); f(c->eig_be);
+  f(c->red_part); f(c->red_out); f(c->V); f(c->part); f(c->ccg_s); f(c->coarse_nodes); f(c->eig_sc); f(c->eig_al); f(c->eig_be);
   if (c->host_red) hipHostFree(c->host_red);
   delete c;
   return PFF_OK;

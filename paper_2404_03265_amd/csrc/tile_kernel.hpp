@@ -141,6 +141,102 @@ __device__ __forceinline__ void node_epilogue(const TileArgs<T>& a, int c, int64
   }
 }
 
+// One cell of the Jacobian (CPL: with the u-phi coupling) or of the level
+// block operator (without it): gather(f, u) fetches the cell's nodal values of
+// field f (0..2 the operand, then the state fields: u_x, u_y, [phi,] phit),
+// out receives the cell's contributions to its nodes.
+template <int P, typename T, bool CPL, class Gather>
+__device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T lam, T kap, T pr, T Gc, T ell,
+                                              Gather&& gather, T (&out)[3][(P + 1) * (P + 1)]) {
+  constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
+  // Jacobian (Sec. 3.1) in reference units (gradients of the unit square,
+  // Gauss weights in the integration tables); with e^, sigma^ the
+  // reference strain and stress (e = e^ / H):
+  //   u rows:   g(phit) sigma^(du) : grad^ psi
+  //   phi rows: [H^2 c1 dphi + H B : e(du)] psi + Gc l grad^ dphi . grad^ psi
+  //   H^2 c1 = (1-k) S^ + 2 p H tr e^ + H^2 Gc/l,
+  //   H B    = 2 (1-k) phi sigma^(u) + 2 p H phi I   (coupling; not on levels)
+  // The level block operator diag(G_uu, G_phiphi) (Sec. 3.2) is the same
+  // without the coupling term, with the injected level state (u_x, u_y, phit).
+  constexpr int FUX = 3, FUY = 4, FPHI = 5, FPT = CPL ? 6 : 5;
+  const T twopH = T(2) * pr * H, gcl2 = H * H * Gc / ell, gcell = Gc * ell;
+  T c1[NQ], bxx[NQ], byy[NQ], bxy[NQ];
+  {
+    T u[NL], sx1[NQ], sy1[NQ], sx2[NQ], sy2[NQ];
+    gather(FUX, u);
+    interp_g<P, T>(B, u, sx1, sy1);
+    gather(FUY, u);
+    interp_g<P, T>(B, u, sx2, sy2);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const T exx = sx1[q], eyy = sy2[q], exy = T(0.5) * (sy1[q] + sx2[q]);
+      const T tr = exx + eyy;
+      const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+      const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
+      c1[q] = (T(1) - kap) * S + twopH * tr + gcl2;
+      bxx[q] = sxx;
+      byy[q] = syy;
+      bxy[q] = sxy;
+    }
+  }
+  if constexpr (CPL) {
+    T u[NL], pq[NQ];
+    gather(FPHI, u);
+    interp_v<P, T>(B, u, pq);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const T f = T(2) * (T(1) - kap) * pq[q], t = twopH * pq[q];
+      bxx[q] = f * bxx[q] + t;
+      byy[q] = f * byy[q] + t;
+      bxy[q] = f * bxy[q];
+    }
+  }
+  T dxx[NQ], dxy[NQ], dyx[NQ], dyy[NQ], be[NQ];
+  {
+    T u[NL];
+    gather(0, u);
+    interp_g<P, T>(B, u, dxx, dxy);
+    gather(1, u);
+    interp_g<P, T>(B, u, dyx, dyy);
+    if constexpr (CPL) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        be[q] = bxx[q] * dxx[q] + byy[q] * dyy[q] + bxy[q] * (dxy[q] + dyx[q]);
+    }
+  }
+  {
+    T u[NL], tq[NQ];
+    gather(FPT, u);
+    interp_v<P, T>(B, u, tq);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const T gq = (T(1) - kap) * tq[q] * tq[q] + kap;
+      const T exx = dxx[q], eyy = dyy[q], exy2 = dxy[q] + dyx[q];
+      const T tr = exx + eyy;
+      const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = mu * exy2;
+      dxx[q] = gq * sxx;
+      dxy[q] = gq * sxy;
+      dyx[q] = gq * sxy;
+      dyy[q] = gq * syy;
+    }
+  }
+  integrate_gw<P, T>(B, dxx, dxy, out[0]);
+  integrate_gw<P, T>(B, dyx, dyy, out[1]);
+  {
+    T u[NL], pv[NQ], px[NQ], py[NQ];
+    gather(2, u);
+    interp_vg<P, T>(B, u, pv, px, py);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if constexpr (CPL) pv[q] = c1[q] * pv[q] + be[q];
+      else pv[q] = c1[q] * pv[q];
+      px[q] = gcell * px[q];
+      py[q] = gcell * py[q];
+    }
+    integrate_w<P, T>(B, pv, px, py, out[2]);
+  }
+}
+
 template <int P, typename T, int MODE, int EPI, bool HANG>
 __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
@@ -391,93 +487,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       const T invH = T(1) / H;
 
       if constexpr (MODE == MODE_J || MODE == MODE_LEVEL) {
-        // Jacobian (Sec. 3.1) in reference units (gradients of the unit square,
-        // Gauss weights in the integration tables); with e^, sigma^ the
-        // reference strain and stress (e = e^ / H):
-        //   u rows:   g(phit) sigma^(du) : grad^ psi
-        //   phi rows: [H^2 c1 dphi + H B : e(du)] psi + Gc l grad^ dphi . grad^ psi
-        //   H^2 c1 = (1-k) S^ + 2 p H tr e^ + H^2 Gc/l,
-        //   H B    = 2 (1-k) phi sigma^(u) + 2 p H phi I   (coupling; not on levels)
-        // The level block operator diag(G_uu, G_phiphi) (Sec. 3.2) is the same
-        // without the coupling term, with the injected level state (u_x, u_y, phit).
-        constexpr bool CPL = (MODE == MODE_J);
-        constexpr int FUX = 3, FUY = 4, FPHI = 5, FPT = CPL ? 6 : 5;
-        const T twopH = T(2) * pr * H, gcl2 = H * H * Gc / ell, gcell = Gc * ell;
-        T c1[NQ], bxx[NQ], byy[NQ], bxy[NQ];
-        {
-          T u[NL], sx1[NQ], sy1[NQ], sx2[NQ], sy2[NQ];
-          gather(FUX, u);
-          interp_g<P, T>(a.B, u, sx1, sy1);
-          gather(FUY, u);
-          interp_g<P, T>(a.B, u, sx2, sy2);
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            const T exx = sx1[q], eyy = sy2[q], exy = T(0.5) * (sy1[q] + sx2[q]);
-            const T tr = exx + eyy;
-            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
-            const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
-            c1[q] = (T(1) - kap) * S + twopH * tr + gcl2;
-            bxx[q] = sxx;
-            byy[q] = syy;
-            bxy[q] = sxy;
-          }
-        }
-        if constexpr (CPL) {
-          T u[NL], pq[NQ];
-          gather(FPHI, u);
-          interp_v<P, T>(a.B, u, pq);
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            const T f = T(2) * (T(1) - kap) * pq[q], t = twopH * pq[q];
-            bxx[q] = f * bxx[q] + t;
-            byy[q] = f * byy[q] + t;
-            bxy[q] = f * bxy[q];
-          }
-        }
-        T dxx[NQ], dxy[NQ], dyx[NQ], dyy[NQ], be[NQ];
-        {
-          T u[NL];
-          gather(0, u);
-          interp_g<P, T>(a.B, u, dxx, dxy);
-          gather(1, u);
-          interp_g<P, T>(a.B, u, dyx, dyy);
-          if constexpr (CPL) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q)
-              be[q] = bxx[q] * dxx[q] + byy[q] * dyy[q] + bxy[q] * (dxy[q] + dyx[q]);
-          }
-        }
-        {
-          T u[NL], tq[NQ];
-          gather(FPT, u);
-          interp_v<P, T>(a.B, u, tq);
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            const T gq = (T(1) - kap) * tq[q] * tq[q] + kap;
-            const T exx = dxx[q], eyy = dyy[q], exy2 = dxy[q] + dyx[q];
-            const T tr = exx + eyy;
-            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = mu * exy2;
-            dxx[q] = gq * sxx;
-            dxy[q] = gq * sxy;
-            dyx[q] = gq * sxy;
-            dyy[q] = gq * syy;
-          }
-        }
-        integrate_gw<P, T>(a.B, dxx, dxy, out[0]);
-        integrate_gw<P, T>(a.B, dyx, dyy, out[1]);
-        {
-          T u[NL], pv[NQ], px[NQ], py[NQ];
-          gather(2, u);
-          interp_vg<P, T>(a.B, u, pv, px, py);
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            if constexpr (CPL) pv[q] = c1[q] * pv[q] + be[q];
-            else pv[q] = c1[q] * pv[q];
-            px[q] = gcell * px[q];
-            py[q] = gcell * py[q];
-          }
-          integrate_w<P, T>(a.B, pv, px, py, out[2]);
-        }
+        jacobian_cell<P, T, MODE == MODE_J>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
       } else if constexpr (MODE == MODE_JT || MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
         // state-derived coefficients at the Gauss points:
         //   g = (1-k) phit^2 + k, c1 = (1-k) S + 2 p tr e(u) + Gc/l,

@@ -126,6 +126,21 @@ def test_vcycle_coarse_cg(name, p):
     assert rel_err(got32, ref) <= 1e-5
 
 
+@pytest.mark.parametrize("coarse", ["cheb", "cg"])
+@pytest.mark.parametrize("p", [1, 2])
+def test_vcycle_per_step_coarse_path(p, coarse):
+    """More coarse steps than the one-kernel coarse solve holds (64): the
+    level-0 solve runs step by step (tile kernel, fix-up, CG scalars) and
+    must give the oracle cycle as well."""
+    c = mg_case("tiny", p, coarse_its=70, coarse=coarse)
+    src = inputs.random_vector(c.X, c.Y, 9)
+    ref = c.to_g(c.vc.apply(c.to_o(src)))
+    got = c.g.vcycle(c.dev(src)).cpu().numpy()
+    assert rel_err(got, ref) <= 1e-12
+    got32 = c.g.vcycle(c.dev(src), fp32=True).cpu().numpy()
+    assert rel_err(got32, ref) <= 1e-5
+
+
 @pytest.mark.parametrize("name,p", CASES)
 def test_gmres_matches_direct_solve(name, p):
     c = mg_case(name, p)
