@@ -211,8 +211,6 @@ __global__ void k_copy_from_level(double* out, const T* x, int64_t nl, const uin
   }
 }
 
-// x_f += P x_c (rows of P: fine nodes); unknowns held at zero on the fine
-// level (u on the boundary, phi on the level active set) stay zero
 // Grid transfers in a column-major ELL layout: entry e of row r at
 // E[e * rows + r], so the entries of one step are read with unit stride
 // across the lanes; padding entries have weight 0. The prolongation weights
