@@ -78,6 +78,9 @@ struct TileSet {
 // entry r lies in the last run k with TILE_RUN_OFF + k <= r and has id
 // TILE_RUN_START + k's value + (r - offset).
 constexpr int TILE_MAX_RUNS = 8;
+// slots per shared node in the fix-up table: a node of a conforming corner
+// touches 2 x 2 tiles; tables of meshes with more use a wider row
+constexpr int SHARED_SLOTS = 4;
 enum {
   TILE_OWNED0 = 0, TILE_NOWNED, TILE_SHARED0, TILE_NSHARED, TILE_CELL0, TILE_NCELL, TILE_NCOLOR, TILE_SLOT0,
   TILE_HANG0, TILE_NHANG, TILE_NHCOLOR, TILE_NRUN,

@@ -34,8 +34,8 @@ struct DevTiles {
   int n_regular = 0;
   int32_t* info = nullptr;
   int32_t* shared = nullptr;
-  int32_t* sh_ptr = nullptr;
-  int32_t* sh_slot = nullptr;
+  int32_t* sh_tab = nullptr;    // [n_shared][sh_w] slots, -1 padded
+  int sh_w = SHARED_SLOTS;
   uint16_t* loc = nullptr;
   uint16_t* loc_sub = nullptr;
   uint16_t* cinfo = nullptr;
@@ -139,8 +139,18 @@ DevTiles upload_tiles(const TileSet& t) {
   d.info = upload(t.tile_info);
   d.n_regular = t.n_regular;
   d.shared = upload(t.shared);
-  d.sh_ptr = upload(t.shared_ptr);
-  d.sh_slot = upload(t.shared_slot);
+  {
+    int w = SHARED_SLOTS;
+    for (int64_t sn = 0; sn < t.n_shared; ++sn)
+      w = std::max(w, t.shared_ptr[size_t(sn) + 1] - t.shared_ptr[size_t(sn)]);
+    std::vector<int32_t> tab(size_t(std::max<int64_t>(t.n_shared, 1)) * size_t(w), -1);
+    for (int64_t sn = 0; sn < t.n_shared; ++sn) {
+      const int j0 = t.shared_ptr[size_t(sn)], j1 = t.shared_ptr[size_t(sn) + 1];
+      for (int j = j0; j < j1; ++j) tab[size_t(sn) * size_t(w) + size_t(j - j0)] = t.shared_slot[size_t(j)];
+    }
+    d.sh_tab = upload(tab);
+    d.sh_w = w;
+  }
   d.loc = upload(t.cell_loc);
   d.loc_sub = upload(t.cell_loc_sub);
   d.cinfo = upload(t.cell_info);
@@ -265,8 +275,8 @@ struct pff_ctx {
     a.n_slots = t.n_slots;
     a.n_private = t.n_private;
     a.n_shared = t.n_shared;
-    a.sh_ptr = t.sh_ptr;
-    a.sh_slot = t.sh_slot;
+    a.sh_tab = t.sh_tab;
+    a.sh_w = t.sh_w;
     a.H0 = T(mesh.level_H[0]);
     a.B = make_basis<T>(p);
     a.mat = mat();
@@ -1046,7 +1056,7 @@ int pff_destroy(pff_ctx* c) {
   if (!c) return PFF_E_ARG;
   auto f = [](void* p) { if (p) hipFree(p); };
   auto ft = [&](DevTiles& t) {
-    f(t.info); f(t.shared); f(t.sh_ptr); f(t.sh_slot); f(t.loc); f(t.loc_sub); f(t.cinfo);
+    f(t.info); f(t.shared); f(t.sh_tab); f(t.loc); f(t.loc_sub); f(t.cinfo);
     f(t.hang_rec); f(t.hang_w); f(t.hang_col);
   };
   ft(c->tiles);

@@ -56,13 +56,14 @@ struct TileArgs {
   int64_t n;
   int max_local;
   // shared nodes: partial sums, [3][n_slots], tile-major; the slots of
-  // shared node s are sh_slot[sh_ptr[s] .. sh_ptr[s + 1]) in ascending tile order
+  // shared node s are sh_tab[s * sh_w ..], ascending tile order, padded
+  // with -1 (sh_w = SHARED_SLOTS unless a node touches more tiles)
   T* part;
   int64_t n_slots;
   int64_t n_private;
   int64_t n_shared;
-  const int32_t* sh_ptr;
-  const int32_t* sh_slot;
+  const int32_t* sh_tab;
+  int sh_w;
   T H0;             // cell edge on level 0; level l has H0 / 2^l
   Basis<T> B;
   Material mat;
@@ -761,13 +762,26 @@ __global__ void __launch_bounds__(256) shared_fixup(const TileArgs<T> a) {
   for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < a.n_shared;
        s += int64_t(gridDim.x) * blockDim.x) {
     const int64_t g = a.n_private + s;
-    const int j0 = a.sh_ptr[s], j1 = a.sh_ptr[s + 1];
     const uint8_t f = a.flags[g];
     T v[3] = {T(0), T(0), T(0)};
-    for (int j = j0; j < j1; ++j) {
-      const int64_t slot = a.sh_slot[j];
+    if (a.sh_w == SHARED_SLOTS) {
+      // the slot list in one 16-byte load: the partial sums are then one
+      // batch of independent loads
+      const int4 sl = reinterpret_cast<const int4*>(a.sh_tab)[s];
+      const int slot[SHARED_SLOTS] = {sl.x, sl.y, sl.z, sl.w};
 #pragma unroll
-      for (int c = 0; c < 3; ++c) v[c] += a.part[c * a.n_slots + slot];
+      for (int j = 0; j < SHARED_SLOTS; ++j)
+        if (slot[j] >= 0) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v[c] += a.part[c * a.n_slots + slot[j]];
+        }
+    } else {
+      for (int j = 0; j < a.sh_w; ++j) {
+        const int slot = a.sh_tab[s * a.sh_w + j];
+        if (slot < 0) break;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] += a.part[c * a.n_slots + slot];
+      }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, false, T>(a, c, g, f, v[c]);
