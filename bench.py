@@ -243,13 +243,20 @@ def main():
             act.zero_()
             torch.cuda.synchronize()
             t_a = time.perf_counter()
-            its = []
+            its, t_setup, t_solve = [], 0.0, 0.0
             for _ in range(args.steps):
                 info, _ = g.newton_step(Uw, phi0, phi0, act)
                 its.append(info["gmres_iterations"])
+                t_setup += info["setup_seconds"]
+                t_solve += info["solve_seconds"]
             torch.cuda.synchronize()
             t_b = time.perf_counter()
-            newton[mode] = {"ms_per_newton_step": (t_b - t_a) / args.steps * 1e3, "gmres_iterations": its}
+            newton[mode] = {"ms_per_newton_step": (t_b - t_a) / args.steps * 1e3, "gmres_iterations": its,
+                            # multigrid setup (level states, diagonals, eigenvalue estimates) and the
+                            # GMRES solve per step; the solve time per GMRES iteration (V-cycle,
+                            # vmult, orthogonalisation)
+                            "setup_ms": t_setup / args.steps * 1e3, "solve_ms": t_solve / args.steps * 1e3,
+                            "ms_per_gmres_iteration": t_solve / max(sum(its), 1) * 1e3}
             # the whole load step to convergence (active set unchanged and
             # |R~| <= 1e-7), once
             Uw.copy_(U0)
@@ -280,7 +287,9 @@ def main():
                 # error of the mixed-precision load step against the FP64 one
                 solve[mode]["rel_diff_U_vs_fp64"] = float(torch.linalg.norm(Uw - U_ref) / torch.linalg.norm(U_ref))
                 solve[mode]["rel_diff_tcv_vs_fp64"] = abs(tcv - tcv_ref) / abs(tcv_ref)
-            log(f"{mode}: Newton step {newton[mode]['ms_per_newton_step']:.1f} ms (gmres {its}); load step "
+            log(f"{mode}: Newton step {newton[mode]['ms_per_newton_step']:.1f} ms (gmres {its}; setup "
+                f"{newton[mode]['setup_ms']:.1f} ms, {newton[mode]['ms_per_gmres_iteration']:.2f} ms per GMRES "
+                f"iteration); load step "
                 f"{solve[mode]['seconds']:.2f} s, {len(infos)} Newton steps (converged {conv}), "
                 f"{solve[mode]['gmres_iterations_total']} GMRES iterations, final |R~| "
                 f"{solve[mode]['final_residual']:.2e}, TCV {tcv:.6e} "
