@@ -95,6 +95,16 @@ def load(path: str = LIB_PATH):
     if _lib is None:
         if not os.path.exists(path):
             raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+        # PyTorch brings its own HIP runtime: initialise it before the
+        # library's first HIP call, or device allocations of a process that
+        # loaded the library first (e.g. a host-only caller, then a solver)
+        # fail with an out-of-memory error
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         lib = C.CDLL(path)
         for name, (res, args) in _SIGS.items():
             fn = getattr(lib, name)
