@@ -65,9 +65,10 @@ struct DevLevel {
   int32_t* PT_col = nullptr;
   // transfers in ELL form: P over all nodes of this level, P^T over the
   // coarse rows that receive contributions
-  TransferEntry* P_ell = nullptr;
+  uint32_t* P_ell = nullptr;
   int P_width = 0;
-  TransferEntry* PT_ell = nullptr;
+  uint32_t* PT_ell = nullptr;
+  float* P_wtab = nullptr;      // distinct weights of P (index 0: 0)
   int32_t* PT_rows = nullptr;
   int64_t PT_nrows = 0;
   int PT_width = 0;
@@ -168,36 +169,47 @@ DevTiles upload_tiles(const TileSet& t) {
 }
 
 // Column-major ELL copies of P (all fine rows) and P^T (the coarse rows with
-// entries); weights must be exact in float (dyadic values).
-void ell_from_csr(const Csr& A, const std::vector<int64_t>& rows, std::vector<TransferEntry>& E, int& width) {
+// entries) with packed (column, weight index) entries; the weights must be
+// exact in float (dyadic values) and shared through one table per level.
+void ell_from_csr(const Csr& A, const std::vector<int64_t>& rows, std::vector<double>& wtab,
+                  std::vector<uint32_t>& E, int& width) {
   width = 0;
   for (int64_t r : rows) width = std::max<int>(width, int(A.ptr[r + 1] - A.ptr[r]));
   const int64_t nr = int64_t(rows.size());
-  E.assign(size_t(std::max(width, 1)) * size_t(std::max<int64_t>(nr, 1)), TransferEntry{0, 0.0f});
+  E.assign(size_t(std::max(width, 1)) * size_t(std::max<int64_t>(nr, 1)), 0u);
   for (int64_t k = 0; k < nr; ++k) {
     const int64_t r = rows[k];
     for (int64_t e = A.ptr[r]; e < A.ptr[r + 1]; ++e) {
-      const float w = float(A.val[e]);
-      if (double(w) != A.val[e]) throw std::runtime_error("transfer weight not exact in float");
-      E[size_t(e - A.ptr[r]) * size_t(nr) + size_t(k)] = TransferEntry{A.col[e], w};
+      const double v = A.val[e];
+      if (double(float(v)) != v) throw std::runtime_error("transfer weight not exact in float");
+      size_t wi = size_t(std::find(wtab.begin(), wtab.end(), v) - wtab.begin());
+      if (wi == wtab.size()) wtab.push_back(v);
+      if (wi >= size_t(TRANSFER_WEIGHTS)) throw std::runtime_error("too many distinct transfer weights");
+      if (uint32_t(A.col[e]) > TRANSFER_COL_MASK) throw std::runtime_error("level too large for packed transfers");
+      E[size_t(e - A.ptr[r]) * size_t(nr) + size_t(k)] =
+          uint32_t(A.col[e]) | (uint32_t(wi) << TRANSFER_COL_BITS);
     }
   }
 }
 
 void upload_transfers(const Level& HL, DevLevel& D) {
-  std::vector<TransferEntry> E;
+  std::vector<uint32_t> E;
+  std::vector<double> wtab(1, 0.0);   // index 0: padding
   std::vector<int64_t> rows(size_t(HL.P.rows));
   std::iota(rows.begin(), rows.end(), 0);
-  ell_from_csr(HL.P, rows, E, D.P_width);
+  ell_from_csr(HL.P, rows, wtab, E, D.P_width);
   D.P_ell = upload(E);
   rows.clear();
   for (int64_t r = 0; r < HL.PT.rows; ++r)
     if (HL.PT.ptr[r + 1] > HL.PT.ptr[r]) rows.push_back(r);
-  ell_from_csr(HL.PT, rows, E, D.PT_width);
+  ell_from_csr(HL.PT, rows, wtab, E, D.PT_width);
   D.PT_ell = upload(E);
   std::vector<int32_t> r32(rows.begin(), rows.end());
   D.PT_rows = upload(r32);
   D.PT_nrows = int64_t(rows.size());
+  std::vector<float> wf(size_t(TRANSFER_WEIGHTS), 0.0f);
+  for (size_t i = 0; i < wtab.size(); ++i) wf[i] = float(wtab[i]);
+  D.P_wtab = upload(wf);
 }
 
 inline int grid_for(int64_t n, int threads = 256) {
@@ -632,7 +644,7 @@ struct pff_ctx {
       LevelWork<T>& wc = work<T>(C);
       if (D.PT_nrows > 0)
         hipLaunchKernelGGL((k_restrict_add<T>), dim3(grid_for(D.PT_nrows)), dim3(256), 0, s, wc.d, t, C.n, D.n,
-                           D.PT_nrows, D.PT_rows, D.PT_width, D.PT_ell);
+                           D.PT_nrows, D.PT_rows, D.PT_width, D.PT_ell, D.P_wtab);
     }
     {
       LevelWork<T>& w0 = work<T>(lv[0]);
@@ -646,7 +658,7 @@ struct pff_ctx {
       LevelWork<T>& w = work<T>(D);
       LevelWork<T>& wc = work<T>(lv[l - 1]);
       hipLaunchKernelGGL((k_prolong_add<T>), dim3(grid_for(D.n)), dim3(256), 0, s, w.x[xi[l]], wc.x[xi[l - 1]], D.n,
-                         lv[l - 1].n, D.P_width, D.P_ell, D.flags);
+                         lv[l - 1].n, D.P_width, D.P_ell, D.P_wtab, D.flags);
       xi[l] = chebyshev<T>(l, w.d, xi[l], k);
     }
     for (int l = 0; l <= L; ++l) {
@@ -1064,7 +1076,7 @@ int pff_destroy(pff_ctx* c) {
   f(c->hang);
   for (DevLevel& D : c->lv) {
     ft(D.tiles);
-    f(D.flags); f(D.leaf_index); f(D.PT_ptr); f(D.PT_col); f(D.P_ell); f(D.PT_ell); f(D.PT_rows);
+    f(D.flags); f(D.leaf_index); f(D.PT_ptr); f(D.PT_col); f(D.P_ell); f(D.PT_ell); f(D.PT_rows); f(D.P_wtab);
     for (auto* w : {&D.w64}) {
       f(w->state); f(w->d); f(w->x[0]); f(w->x[1]); f(w->dir[0]); f(w->dir[1]); f(w->dinv);
     }

@@ -213,26 +213,35 @@ __global__ void k_copy_from_level(double* out, const T* x, int64_t nl, const uin
 
 // Grid transfers in a column-major ELL layout: entry e of row r at
 // E[e * rows + r], so the entries of one step are read with unit stride
-// across the lanes; padding entries have weight 0. The prolongation weights
-// are exact dyadic values, stored as float for both precisions.
-struct TransferEntry {
-  int32_t col;
-  float w;
-};
+// across the lanes. An entry packs the column (low TRANSFER_COL_BITS bits) and
+// the index of its weight in the level's table of distinct weights (high
+// bits); the weights are exact dyadic values, the table holds them as float
+// for both precisions, and index 0 is the weight 0 of padding entries.
+constexpr int TRANSFER_COL_BITS = 27;   // levels up to 134 M nodes, 32 distinct weights
+constexpr int TRANSFER_WEIGHTS = 1 << (32 - TRANSFER_COL_BITS);
+constexpr uint32_t TRANSFER_COL_MASK = (1u << TRANSFER_COL_BITS) - 1u;
+
+__device__ __forceinline__ void load_weight_table(float* W, const float* wtab) {
+  for (int i = threadIdx.x; i < TRANSFER_WEIGHTS; i += blockDim.x) W[i] = wtab[i];
+  __syncthreads();
+}
 
 // x_f += P x_c on unknowns the fine level does not hold at zero
 // (Dirichlet for u, active for phi)
 template <typename T>
-__global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, int width, const TransferEntry* E,
-                              const uint8_t* ff) {
+__global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, int width, const uint32_t* E,
+                              const float* wtab, const uint8_t* ff) {
+  __shared__ float W[TRANSFER_WEIGHTS];
+  load_weight_table(W, wtab);
   GRID_LOOP(i, nf) {
     T s0 = T(0), s1 = T(0), s2 = T(0);
     for (int e = 0; e < width; ++e) {
-      const TransferEntry t = E[int64_t(e) * nf + i];
-      const T w = T(t.w);
-      s0 += w * xc[t.col];
-      s1 += w * xc[nc + t.col];
-      s2 += w * xc[2 * nc + t.col];
+      const uint32_t t = E[int64_t(e) * nf + i];
+      const int64_t col = t & TRANSFER_COL_MASK;
+      const T w = T(W[t >> TRANSFER_COL_BITS]);
+      s0 += w * xc[col];
+      s1 += w * xc[nc + col];
+      s2 += w * xc[2 * nc + col];
     }
     const uint8_t f = ff[i];
     if (!(f & NODE_DIRICHLET)) {
@@ -246,15 +255,18 @@ __global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, int wi
 // d_c += P^T t_f over the coarse rows that receive fine contributions
 template <typename T>
 __global__ void k_restrict_add(T* dc, const T* tf, int64_t nc, int64_t nf, int64_t nrows, const int32_t* rows,
-                               int width, const TransferEntry* E) {
+                               int width, const uint32_t* E, const float* wtab) {
+  __shared__ float W[TRANSFER_WEIGHTS];
+  load_weight_table(W, wtab);
   GRID_LOOP(r, nrows) {
     T s0 = T(0), s1 = T(0), s2 = T(0);
     for (int e = 0; e < width; ++e) {
-      const TransferEntry t = E[int64_t(e) * nrows + r];
-      const T w = T(t.w);
-      s0 += w * tf[t.col];
-      s1 += w * tf[nf + t.col];
-      s2 += w * tf[2 * nf + t.col];
+      const uint32_t t = E[int64_t(e) * nrows + r];
+      const int64_t col = t & TRANSFER_COL_MASK;
+      const T w = T(W[t >> TRANSFER_COL_BITS]);
+      s0 += w * tf[col];
+      s1 += w * tf[nf + col];
+      s2 += w * tf[2 * nf + col];
     }
     const int64_t i = rows[r];
     dc[i] += s0;
