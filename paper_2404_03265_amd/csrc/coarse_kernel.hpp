@@ -17,6 +17,7 @@ namespace pff {
 constexpr int COARSE_THREADS = 256;    // one cell per thread: level 0 has at most 256 cells
 constexpr int COARSE_MAX_STEPS = 64;
 constexpr int COARSE_MAX_COLORS = 8;
+constexpr int COARSE_PER_THREAD = 16;  // unknowns per thread: 3 n0 <= COARSE_THREADS * COARSE_PER_THREAD
 
 template <typename T>
 struct CoarseArgs {
@@ -116,27 +117,43 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
 
   if (!a.cg) {
     // Chebyshev: d = c2 D^-1 b, x = d; then r = b - A x,
-    // d = c1 d + c2 D^-1 r and x += d on free rows (d = 0 on held rows)
-    for (int i = tid; i < N; i += COARSE_THREADS) {
-      const int blk = i < 2 * n0 ? 0 : 1;
-      const T v = a.c2[0][blk] * a.dinv[i] * a.b[i];
-      v1[i] = double(v);
-      xo[i] = double(v);
+    // d = c1 d + c2 D^-1 r and x += d on free rows (d = 0 on held rows).
+    // b, D^-1 and the held flag of the thread's unknowns stay in registers.
+    T bi[COARSE_PER_THREAD], di[COARSE_PER_THREAD];
+    bool held[COARSE_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < COARSE_PER_THREAD; ++k) {
+      const int i = tid + k * COARSE_THREADS;
+      bi[k] = T(0);
+      di[k] = T(0);
+      held[k] = true;
+      if (i < N) {
+        const int c = i / n0, blk = c < 2 ? 0 : 1;
+        const uint8_t f = a.flags[i - c * n0];
+        bi[k] = a.b[i];
+        di[k] = a.dinv[i];
+        held[k] = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
+        const T v = a.c2[0][blk] * di[k] * bi[k];
+        v1[i] = double(v);
+        xo[i] = double(v);
+      }
     }
     __syncthreads();
     for (int j = 1; j < a.steps; ++j) {
       apply();
-      for (int i = tid; i < N; i += COARSE_THREADS) {
-        const int c = i / n0, blk = c < 2 ? 0 : 1;
-        const uint8_t f = fl[i - c * n0];
-        const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
-        if (fixed) {
-          v1[i] = 0.0;
-        } else {
-          const T r = a.b[i] - T(acc[i]);
-          const T dn = a.c1[j][blk] * T(v1[i]) + a.c2[j][blk] * a.dinv[i] * r;
-          v1[i] = double(dn);
-          xo[i] = double(T(xo[i]) + dn);
+#pragma unroll
+      for (int k = 0; k < COARSE_PER_THREAD; ++k) {
+        const int i = tid + k * COARSE_THREADS;
+        if (i < N) {
+          const int blk = i < 2 * n0 ? 0 : 1;
+          if (held[k]) {
+            v1[i] = 0.0;
+          } else {
+            const T r = bi[k] - T(acc[i]);
+            const T dn = a.c1[j][blk] * T(v1[i]) + a.c2[j][blk] * di[k] * r;
+            v1[i] = double(dn);
+            xo[i] = double(T(xo[i]) + dn);
+          }
         }
       }
       __syncthreads();

@@ -535,7 +535,7 @@ struct pff_ctx {
     }
     const size_t lds = size_t(15 * HL.n) * sizeof(double) + size_t(HL.n);
     coarse_fusable = ok && ncell > 0 && ncell <= COARSE_THREADS && ncolor <= COARSE_MAX_COLORS &&
-                     lds <= size_t(160 * 1024);
+                     lds <= size_t(160 * 1024) && 3 * HL.n <= int64_t(COARSE_THREADS) * COARSE_PER_THREAD;
     if (!coarse_fusable) return;
     std::vector<int32_t> flat;
     flat.reserve(size_t(ncell) * size_t(NL));
