@@ -164,45 +164,63 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
 
   // CG: r = b on free rows, x = 0, p = D^-1 r; per step alpha = r.z / p.q,
   // x += alpha p, r -= alpha q, beta = r.z_new / r.z, p = D^-1 r + beta p;
-  // a block whose r.z is exactly zero stays where it is
+  // a block whose r.z is exactly zero stays where it is. D^-1 of the thread's
+  // unknowns stays in registers.
+  T di[COARSE_PER_THREAD];
   double rz0 = 0.0, rz1 = 0.0;
-  for (int i = tid; i < N; i += COARSE_THREADS) {
-    const T di = a.dinv[i];
-    const T ri = di != T(0) ? a.b[i] : T(0);
-    v2[i] = 0.0;
-    v1[i] = double(ri);
-    xo[i] = double(di * ri);
-    const double c = double(ri) * double(di * ri);
-    if (i < 2 * n0) rz0 += c; else rz1 += c;
+#pragma unroll
+  for (int k = 0; k < COARSE_PER_THREAD; ++k) {
+    const int i = tid + k * COARSE_THREADS;
+    di[k] = T(0);
+    if (i < N) {
+      di[k] = a.dinv[i];
+      const T ri = di[k] != T(0) ? a.b[i] : T(0);
+      v2[i] = 0.0;
+      v1[i] = double(ri);
+      xo[i] = double(di[k] * ri);
+      const double c = double(ri) * double(di[k] * ri);
+      if (i < 2 * n0) rz0 += c; else rz1 += c;
+    }
   }
   coarse_sum2(rz0, rz1, red);
   double rz[2] = {rz0, rz1};
   for (int it = 0; it < a.steps; ++it) {
     apply();
     double pq0 = 0.0, pq1 = 0.0;
-    for (int i = tid; i < N; i += COARSE_THREADS) {
-      const double c = a.dinv[i] != T(0) ? double(T(xo[i])) * double(T(acc[i])) : 0.0;
-      if (i < 2 * n0) pq0 += c; else pq1 += c;
+#pragma unroll
+    for (int k = 0; k < COARSE_PER_THREAD; ++k) {
+      const int i = tid + k * COARSE_THREADS;
+      if (i < N) {
+        const double c = di[k] != T(0) ? double(T(xo[i])) * double(T(acc[i])) : 0.0;
+        if (i < 2 * n0) pq0 += c; else pq1 += c;
+      }
     }
     coarse_sum2(pq0, pq1, red);
     const double alpha[2] = {rz[0] == 0.0 ? 0.0 : rz[0] / pq0, rz[1] == 0.0 ? 0.0 : rz[1] / pq1};
     double rn0 = 0.0, rn1 = 0.0;
-    for (int i = tid; i < N; i += COARSE_THREADS) {
-      const int blk = i < 2 * n0 ? 0 : 1;
-      const T di = a.dinv[i];
-      const T qi = di != T(0) ? T(acc[i]) : T(0);
-      const T al = T(alpha[blk]);
-      v2[i] = double(T(v2[i]) + al * T(xo[i]));
-      const T ri = T(v1[i]) - al * qi;
-      v1[i] = double(ri);
-      const double c = double(ri) * double(di * ri);
-      if (blk == 0) rn0 += c; else rn1 += c;
+#pragma unroll
+    for (int k = 0; k < COARSE_PER_THREAD; ++k) {
+      const int i = tid + k * COARSE_THREADS;
+      if (i < N) {
+        const int blk = i < 2 * n0 ? 0 : 1;
+        const T qi = di[k] != T(0) ? T(acc[i]) : T(0);
+        const T al = T(alpha[blk]);
+        v2[i] = double(T(v2[i]) + al * T(xo[i]));
+        const T ri = T(v1[i]) - al * qi;
+        v1[i] = double(ri);
+        const double c = double(ri) * double(di[k] * ri);
+        if (blk == 0) rn0 += c; else rn1 += c;
+      }
     }
     coarse_sum2(rn0, rn1, red);
     const double beta[2] = {rz[0] == 0.0 ? 0.0 : rn0 / rz[0], rz[1] == 0.0 ? 0.0 : rn1 / rz[1]};
-    for (int i = tid; i < N; i += COARSE_THREADS) {
-      const int blk = i < 2 * n0 ? 0 : 1;
-      xo[i] = double(a.dinv[i] * T(v1[i]) + T(beta[blk]) * T(xo[i]));
+#pragma unroll
+    for (int k = 0; k < COARSE_PER_THREAD; ++k) {
+      const int i = tid + k * COARSE_THREADS;
+      if (i < N) {
+        const int blk = i < 2 * n0 ? 0 : 1;
+        xo[i] = double(di[k] * T(v1[i]) + T(beta[blk]) * T(xo[i]));
+      }
     }
     rz[0] = rn0;
     rz[1] = rn1;
