@@ -223,6 +223,35 @@ def test_full_size_vmult_sampled_rows():
     assert np.abs(got - ref).max() <= 1e-12 * scale
 
 
+def test_full_size_vcycle_properties():
+    """The benchmark workload at full size (20.5 M unknowns), where the oracle
+    cannot run the cycle: properties that hold at any size. The FP64 V-cycle
+    (symmetric smoothing, Chebyshev coarse solve) is a symmetric operator,
+    w.(P^-1 v) = v.(P^-1 w); the FP32 V-cycle stays within 1e-5 of it; the
+    transposed Jacobian satisfies w.(J v) = (J^T w).v."""
+    import time
+    import torch
+    t0 = time.time()
+    c = Case(1024, 3, 2, mask="bernoulli", u_std=1e-4, build_oracle=False)
+    c.load_state(setup_mg=True)
+    print(f"[full] state and multigrid set up {time.time() - t0:.1f}s", flush=True)
+    v = c.dev(inputs.random_vector(c.X, c.Y, 31))
+    w = c.dev(inputs.random_vector(c.X, c.Y, 32))
+    Pv = c.g.vcycle(v)
+    Pw = c.g.vcycle(w)
+    a, b = torch.dot(w, Pv).item(), torch.dot(v, Pw).item()
+    scale = (torch.linalg.norm(w) * torch.linalg.norm(Pv)).item()
+    assert abs(a - b) <= 1e-12 * scale, (a, b, scale)
+    Pv32 = c.g.vcycle(v, fp32=True)
+    assert rel_err(Pv32.cpu().numpy(), Pv.cpu().numpy()) <= 1e-5
+    Jv = c.g.vmult(v)
+    JTw = c.g.vmult_T(w)
+    a, b = torch.dot(w, Jv).item(), torch.dot(JTw, v).item()
+    scale = (torch.linalg.norm(w) * torch.linalg.norm(Jv)).item()
+    assert abs(a - b) <= 1e-12 * scale, (a, b, scale)
+    print(f"[full] done {time.time() - t0:.1f}s", flush=True)
+
+
 @pytest.mark.parametrize("name,p", CASES)
 def test_adjoint_crack_volume_gradient(name, p):
     """Adjoint gradient of TCV w.r.t. (Gc, E, p) at a converged load step with
