@@ -630,7 +630,7 @@ struct pff_ctx {
     for (int l = 0; l <= L; ++l) {
       DevLevel& D = lv[l];
       LevelWork<T>& w = work<T>(D);
-      hipLaunchKernelGGL((k_copy_to_level<T>), dim3(grid_for(3 * D.n)), dim3(256), 0, s, w.d, D.n, D.flags,
+      hipLaunchKernelGGL((k_copy_to_level<T>), dim3(grid_for(D.n)), dim3(256), 0, s, w.d, D.n, D.flags,
                          D.leaf_index, src, flags, n);
     }
     for (int l = L; l >= 1; --l) {
@@ -664,7 +664,7 @@ struct pff_ctx {
     for (int l = 0; l <= L; ++l) {
       DevLevel& D = lv[l];
       LevelWork<T>& w = work<T>(D);
-      hipLaunchKernelGGL((k_copy_from_level<T>), dim3(grid_for(3 * D.n)), dim3(256), 0, s, dst, w.x[xi[l]], D.n,
+      hipLaunchKernelGGL((k_copy_from_level<T>), dim3(grid_for(D.n)), dim3(256), 0, s, dst, w.x[xi[l]], D.n,
                          D.flags, D.leaf_index, src, flags, n);
     }
     if (n_hang)

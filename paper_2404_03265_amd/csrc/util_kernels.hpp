@@ -143,9 +143,11 @@ __global__ void k_apply_active(double* U, const double* phio, const uint8_t* fla
 
 // zero constrained rows of a leaf vector
 __global__ void k_mask_leaf(double* v, const uint8_t* flags, int64_t n) {
-  GRID_LOOP(i, 3 * n) {
-    const int c = int(i / n);
-    if (leaf_constrained(flags[i % n], c)) v[i] = 0.0;
+  GRID_LOOP(k, n) {
+    const uint8_t f = flags[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (leaf_constrained(f, c)) v[c * n + k] = 0.0;
   }
 }
 
@@ -185,15 +187,17 @@ __global__ void k_level_active(uint8_t* fl, int64_t nl, const int32_t* leaf_inde
 template <typename T>
 __global__ void k_copy_to_level(T* d, int64_t nl, const uint8_t* fl, const int32_t* leaf_index,
                                 const double* b, const uint8_t* leaf_flags, int64_t n) {
-  GRID_LOOP(i, 3 * nl) {
-    const int c = int(i / nl);
-    const int64_t k = i % nl;
-    T v = T(0);
+  GRID_LOOP(k, nl) {
+    T v[3] = {T(0), T(0), T(0)};
     if (fl[k] & NODE_COPY) {
       const int64_t g = leaf_index[k];
-      if (!leaf_constrained(leaf_flags[g], c)) v = T(b[c * n + g]);
+      const uint8_t lf = leaf_flags[g];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (!leaf_constrained(lf, c)) v[c] = T(b[c * n + g]);
     }
-    d[i] = v;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[c * nl + k] = v[c];
   }
 }
 
@@ -201,12 +205,13 @@ template <typename T>
 __global__ void k_copy_from_level(double* out, const T* x, int64_t nl, const uint8_t* fl,
                                   const int32_t* leaf_index, const double* b, const uint8_t* leaf_flags,
                                   int64_t n) {
-  GRID_LOOP(i, 3 * nl) {
-    const int c = int(i / nl);
-    const int64_t k = i % nl;
+  GRID_LOOP(k, nl) {
     if (fl[k] & NODE_COPY) {
       const int64_t g = leaf_index[k];
-      out[c * n + g] = leaf_constrained(leaf_flags[g], c) ? b[c * n + g] : double(x[i]);
+      const uint8_t lf = leaf_flags[g];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        out[c * n + g] = leaf_constrained(lf, c) ? b[c * n + g] : double(x[c * nl + k]);
     }
   }
 }
