@@ -715,18 +715,17 @@ struct pff_ctx {
     HIPCHK(hipMemcpyAsync(sc, h, sizeof(h), hipMemcpyHostToDevice, s));
     const int stride = EIG_MAX_ITS;
     max_it = std::min(max_it, stride);
+    // per step: operator, p.q partials, alpha, update fused with the r.z
+    // partials, beta, direction update (both blocks in every launch)
+    const int nb = std::min(RED_BLOCKS, grid_for(3 * nl));
     for (int it = 0; it < max_it; ++it) {
       level_apply<double>(l, pv, q, EPI_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr);
-      for (int b = 0; b < 2; ++b) dot2_async(pv + off[b], q + off[b], len[b], sc + EIG_SC * b + EIG_PQ);
-      hipLaunchKernelGGL(k_eig_alpha, dim3(1), dim3(64), 0, s, sc, eig_al, stride, it);
-      for (int b = 0; b < 2; ++b)
-        hipLaunchKernelGGL(k_cg_update_dev, dim3(grid_for(len[b])), dim3(256), 0, s, r + off[b], z + off[b],
-                           q + off[b], w.dinv + off[b], sc + EIG_SC * b, len[b]);
-      for (int b = 0; b < 2; ++b) dot2_async(r + off[b], z + off[b], len[b], sc + EIG_SC * b + EIG_RZ2);
-      hipLaunchKernelGGL(k_eig_beta, dim3(1), dim3(64), 0, s, sc, eig_be, stride, it);
-      for (int b = 0; b < 2; ++b)
-        hipLaunchKernelGGL(k_waxpy_dev, dim3(grid_for(len[b])), dim3(256), 0, s, pv + off[b], z + off[b],
-                           sc + EIG_SC * b, len[b]);
+      hipLaunchKernelGGL(k_eig_pq_partial, dim3(nb), dim3(RED_THREADS), 0, s, pv, q, nl, red_part);
+      hipLaunchKernelGGL(k_eig_alpha_reduce, dim3(1), dim3(RED_THREADS), 0, s, red_part, nb, sc, eig_al, stride, it);
+      hipLaunchKernelGGL(k_eig_update_partial, dim3(nb), dim3(RED_THREADS), 0, s, r, z, q, w.dinv, sc, nl,
+                         red_part);
+      hipLaunchKernelGGL(k_eig_beta_reduce, dim3(1), dim3(RED_THREADS), 0, s, red_part, nb, sc, eig_be, stride, it);
+      hipLaunchKernelGGL(k_eig_waxpy, dim3(grid_for(3 * nl)), dim3(256), 0, s, pv, z, sc, nl);
     }
     std::vector<double> al(2 * stride), be(2 * stride);
     HIPCHK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));

@@ -350,50 +350,6 @@ constexpr int EIG_SC = 9;
 constexpr int EIG_MAX_ITS = 200;   // largest accepted eig_cg_its / coarse_eig_its
 enum { EIG_RZ = 0, EIG_PQ, EIG_RZ2, EIG_ALPHA, EIG_BETA, EIG_RZ0, EIG_ACTIVE, EIG_STEPS, EIG_MAX };
 
-__global__ void k_eig_alpha(double* sc, double* al, int stride, int it) {
-  const int b = threadIdx.x;
-  if (b >= 2) return;
-  double* c = sc + EIG_SC * b;
-  if (c[EIG_ACTIVE] == 0.0) return;
-  const double pq = c[EIG_PQ];
-  if (!(pq > 0.0)) {
-    c[EIG_ACTIVE] = 0.0;
-    return;
-  }
-  const double alpha = c[EIG_RZ] / pq;
-  c[EIG_ALPHA] = alpha;
-  al[b * stride + it] = alpha;
-}
-__global__ void k_eig_beta(double* sc, double* be, int stride, int it) {
-  const int b = threadIdx.x;
-  if (b >= 2) return;
-  double* c = sc + EIG_SC * b;
-  if (c[EIG_ACTIVE] == 0.0) return;
-  const double rz2 = c[EIG_RZ2];
-  const double beta = rz2 / c[EIG_RZ];
-  c[EIG_BETA] = beta;
-  be[b * stride + it] = beta;
-  c[EIG_RZ] = rz2;
-  c[EIG_STEPS] = double(it + 1);
-  if (rz2 <= 1e-24 * c[EIG_RZ0] || double(it + 1) >= c[EIG_MAX]) c[EIG_ACTIVE] = 0.0;
-}
-// r -= alpha q on free rows, z = D^-1 r (no-op once the block has stopped)
-__global__ void k_cg_update_dev(double* r, double* z, const double* q, const double* dinv, const double* c,
-                                int64_t len) {
-  if (c[EIG_ACTIVE] == 0.0) return;
-  const double alpha = c[EIG_ALPHA];
-  GRID_LOOP(i, len) {
-    if (dinv[i] != 0.0) r[i] -= alpha * q[i];
-    z[i] = dinv[i] * r[i];
-  }
-}
-// p = z + beta p (no-op once the block has stopped)
-__global__ void k_waxpy_dev(double* p, const double* z, const double* c, int64_t len) {
-  if (c[EIG_ACTIVE] == 0.0) return;
-  const double beta = c[EIG_BETA];
-  GRID_LOOP(i, len) p[i] = z[i] + beta * p[i];
-}
-
 // stage 1 of a dot product: one partial per block, fixed order
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) k_dot_partial(const T* a, const T* b, int64_t len, double* part) {
@@ -518,6 +474,126 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double* part
       out[j] = t;
     }
     __syncthreads();
+  }
+}
+
+// ---- eigenvalue-estimate CG, both blocks of a level per launch ------------
+// Block 0 is rows [0, 2 nl) (u), block 1 rows [2 nl, 3 nl) (phi); sc holds the
+// per-block scalars (EIG_*). Partial sums per workgroup and block go to
+// part[2 * workgroup + block] and are reduced in fixed order.
+__device__ __forceinline__ void eig_block_partials(double s0, double s1, double* part) {
+  __shared__ double sh[2][RED_THREADS / 64];
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    sh[0][wave] = s0;
+    sh[1][wave] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int w = 0; w < RED_THREADS / 64; ++w) t += sh[threadIdx.x][w];
+    part[2 * blockIdx.x + threadIdx.x] = t;
+  }
+}
+// sums of the two columns of part over nb workgroups (one thread each, fixed order)
+__device__ __forceinline__ void eig_reduce2(const double* part, int nb, double* out2) {
+  __shared__ double sh[2][RED_THREADS / 64];
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    s0 += part[2 * i];
+    s1 += part[2 * i + 1];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    sh[0][wave] = s0;
+    sh[1][wave] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int w = 0; w < RED_THREADS / 64; ++w) t += sh[threadIdx.x][w];
+    out2[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// partials of p.q per block
+__global__ void __launch_bounds__(RED_THREADS) k_eig_pq_partial(const double* p, const double* q, int64_t nl,
+                                                                  double* part) {
+  double s0 = 0.0, s1 = 0.0;
+  GRID_LOOP(i, 3 * nl) {
+    const double c = p[i] * q[i];
+    if (i < 2 * nl) s0 += c; else s1 += c;
+  }
+  eig_block_partials(s0, s1, part);
+}
+// p.q per block, then alpha = r.z / p.q (a block with p.q <= 0 stops)
+__global__ void __launch_bounds__(RED_THREADS) k_eig_alpha_reduce(const double* part, int nb, double* sc, double* al,
+                                                                    int stride, int it) {
+  __shared__ double pq[2];
+  eig_reduce2(part, nb, pq);
+  const int b = threadIdx.x;
+  if (b >= 2) return;
+  double* c = sc + EIG_SC * b;
+  if (c[EIG_ACTIVE] == 0.0) return;
+  if (!(pq[b] > 0.0)) {
+    c[EIG_ACTIVE] = 0.0;
+    return;
+  }
+  const double alpha = c[EIG_RZ] / pq[b];
+  c[EIG_ALPHA] = alpha;
+  al[b * stride + it] = alpha;
+}
+// r -= alpha q on free rows, z = D^-1 r (active blocks), partials of r.z
+__global__ void __launch_bounds__(RED_THREADS) k_eig_update_partial(double* r, double* z, const double* q,
+                                                                      const double* dinv, const double* sc,
+                                                                      int64_t nl, double* part) {
+  const bool act[2] = {sc[EIG_ACTIVE] != 0.0, sc[EIG_SC + EIG_ACTIVE] != 0.0};
+  const double alpha[2] = {sc[EIG_ALPHA], sc[EIG_SC + EIG_ALPHA]};
+  double s0 = 0.0, s1 = 0.0;
+  GRID_LOOP(i, 3 * nl) {
+    const int b = i < 2 * nl ? 0 : 1;
+    double ri = r[i], zi = z[i];
+    if (act[b]) {
+      const double di = dinv[i];
+      if (di != 0.0) ri -= alpha[b] * q[i];
+      zi = di * ri;
+      r[i] = ri;
+      z[i] = zi;
+    }
+    const double c = ri * zi;
+    if (b == 0) s0 += c; else s1 += c;
+  }
+  eig_block_partials(s0, s1, part);
+}
+// r.z per block, beta = r.z_new / r.z; stop once r.z <= 1e-24 r.z_0 or after
+// the block's step count
+__global__ void __launch_bounds__(RED_THREADS) k_eig_beta_reduce(const double* part, int nb, double* sc, double* be,
+                                                                   int stride, int it) {
+  __shared__ double rz2[2];
+  eig_reduce2(part, nb, rz2);
+  const int b = threadIdx.x;
+  if (b >= 2) return;
+  double* c = sc + EIG_SC * b;
+  if (c[EIG_ACTIVE] == 0.0) return;
+  const double beta = rz2[b] / c[EIG_RZ];
+  c[EIG_BETA] = beta;
+  be[b * stride + it] = beta;
+  c[EIG_RZ] = rz2[b];
+  c[EIG_STEPS] = double(it + 1);
+  if (rz2[b] <= 1e-24 * c[EIG_RZ0] || double(it + 1) >= c[EIG_MAX]) c[EIG_ACTIVE] = 0.0;
+}
+// p = z + beta p on active blocks
+__global__ void k_eig_waxpy(double* p, const double* z, const double* sc, int64_t nl) {
+  const bool act[2] = {sc[EIG_ACTIVE] != 0.0, sc[EIG_SC + EIG_ACTIVE] != 0.0};
+  const double beta[2] = {sc[EIG_BETA], sc[EIG_SC + EIG_BETA]};
+  GRID_LOOP(i, 3 * nl) {
+    const int b = i < 2 * nl ? 0 : 1;
+    if (act[b]) p[i] = z[i] + beta[b] * p[i];
   }
 }
 
