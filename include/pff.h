@@ -79,8 +79,10 @@ typedef struct {
  *  level 0 with coarse_its updates (Sec. 3.2); coarse_mode 1: coarse_its
  *  Jacobi-preconditioned CG steps from zero on level 0, each block with its
  *  own scalars (a fixed number of steps, so the cycle is reproducible; it is
- *  not a linear operator); coarse_eig_its: CG steps for the level-0 estimate
- *  (1..200).
+ *  not a linear operator). Either runs in one kernel when level 0 fits one
+ *  workgroup (at most 256 cells) and coarse_its <= 64, else step by step;
+ *  the results agree to rounding. coarse_eig_its: CG steps for the level-0
+ *  estimate (1..200).
  *  gmres_restart, gmres_max_its, gmres_rtol, gmres_atol: GMRES(m) stops when
  *  the preconditioned residual is below max(atol, rtol * |rhs|) (Table 1).
  *  ls_omega, ls_max: line-search damping omega and l_max (Alg. 2).
