@@ -403,9 +403,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_mdot_partial(const double* V, c
   for (int j = 0; j < K; ++j) s[j] = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x) {
     const double wi = w[i];
+    // all k values of element i requested before the first product
+    double v[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j)
-      if (j < k) s[j] += V[int64_t(j) * len + i] * wi;
+    for (int j = 0; j < K; ++j) v[j] = j < k ? V[int64_t(j) * len + i] : 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) s[j] += v[j] * wi;
   }
   block_partials<K>(s, k, part);
 }
