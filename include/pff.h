@@ -86,7 +86,12 @@ typedef struct {
  *  gmres_restart, gmres_max_its, gmres_rtol, gmres_atol: GMRES(m) stops when
  *  the preconditioned residual is below max(atol, rtol * |rhs|) (Table 1).
  *  ls_omega, ls_max: line-search damping omega and l_max (Alg. 2).
- *  vcycle_fp32: 1 = the V-cycle inside gmres_solve/newton_step runs in FP32. */
+ *  vcycle_fp32: 1 = the V-cycle inside gmres_solve/newton_step runs in FP32.
+ *  pdas_c: the active-set constant c of Sec. 2 (an unknown is active when
+ *  lambda + c (phi - phi_old) > 0). 0 (default) takes the per-unknown choice
+ *  c_i = 2 |lambda_i / (phi_i - phi_old_i)| (Sec. 2, with c_i * 0 := 0); a
+ *  positive value is used as one constant for every unknown (the paper notes
+ *  c may be chosen freely). Negative or non-finite: PFF_E_ARG. */
 typedef struct {
   double E, nu, Gc, pressure, kappa, ell;
   int32_t cheb_degree;
@@ -100,6 +105,7 @@ typedef struct {
   double ls_omega;
   int32_t ls_max;
   int32_t vcycle_fp32;
+  double pdas_c;
 } pff_params;
 
 typedef struct {
@@ -156,7 +162,7 @@ int pff_tile_stats(const pff_ctx* ctx, int32_t level, int64_t* n_tiles, int64_t*
  * phase field of the linearised degradation, Sec. 2). The library copies them
  * and sets hanging entries of its copies from their masters. active: device
  * n bytes (nonzero = active) or NULL to evaluate the active-set rule of
- * Alg. 2 at this state. setup_mg != 0 also prepares the V-cycle: level states
+ * Alg. 2 (constant c as selected by pdas_c) at this state. setup_mg != 0 also prepares the V-cycle: level states
  * and active sets (Sec. 3.2), inverse diagonals and eigenvalue estimates.
  * Synchronises the stream when setup_mg != 0. */
 int pff_set_state(pff_ctx* ctx, const double* U, const double* phi_old, const double* phi_tilde,

@@ -38,6 +38,7 @@ class NewtonParams:
     gmres_atol: float = 1e-12
     ls_omega: float = 0.5
     ls_max: int = 10
+    pdas_c: float = 0.0           # 0: c_i = 2 |lambda_i / (phi_i - phi_old_i)|; > 0: that constant
 
 
 @dataclass
@@ -52,15 +53,21 @@ class NewtonInfo:
     active_changed: int = 0
 
 
-def active_set(lp: LeafProblem, R, phi, phi_old):
-    """Sec. 2 / Alg. 2 active-set rule, per phase-field unknown."""
+def active_set(lp: LeafProblem, R, phi, phi_old, c_fixed=0.0):
+    """Sec. 2 / Alg. 2 active-set rule, per phase-field unknown: active where
+    lambda + c (phi - phi_old) > 0. c_fixed = 0 takes the paper's choice
+    c_i = 2 |lambda_i / (phi_i - phi_old_i)|; c_fixed > 0 is one constant for
+    every unknown (Sec. 2 leaves c free)."""
     n = lp.n
     B = lp.lumped_phi_mass()
     hang = lp.mesh.hanging
     lam = np.where(hang, 0.0, R[2 * n:] / np.where(hang, 1.0, B))
     diff = phi - phi_old
-    nz = diff != 0.0
-    c = np.where(nz, 2.0 * np.abs(lam / np.where(nz, diff, 1.0)), 0.0)
+    if c_fixed > 0.0:
+        c = np.full(n, float(c_fixed))
+    else:
+        nz = diff != 0.0
+        c = np.where(nz, 2.0 * np.abs(lam / np.where(nz, diff, 1.0)), 0.0)
     val = lam + c * diff
     # exact ties (lambda = 0 where the state makes the phase-field residual
     # vanish) arrive as rounding noise; values below 1e-12 max|lambda| count
@@ -78,7 +85,7 @@ def newton_step(lp: LeafProblem, hier: Hierarchy, mgp: MGParams, nwp: NewtonPara
     n = lp.n
     info = NewtonInfo()
     R = lp.residual(U, phit)
-    active = active_set(lp, R, U[2 * n:], phi_old)
+    active = active_set(lp, R, U[2 * n:], phi_old, nwp.pdas_c)
     info.n_active = int(active.sum())
     if active_prev is not None:
         info.active_changed = int(np.sum(active != active_prev))

@@ -43,6 +43,7 @@ class SolverParams:
     ls_omega: float = 0.5
     ls_max: int = 10
     vcycle_fp32: int = 0
+    pdas_c: float = 0.0
 
     def to_c(self):
         p = _lib.Params()

@@ -950,6 +950,12 @@ LevelWork<float>& pff_ctx::work<float>(DevLevel& L) { return L.w32; }
     return PFF_E_HIP;                                       \
   }
 
+static bool params_valid(const pff_params& p) {
+  return p.cheb_degree >= 1 && p.coarse_its >= 1 && p.gmres_restart >= 1 && p.gmres_restart <= 60 &&
+         p.coarse_mode >= 0 && p.coarse_mode <= 1 && p.eig_cg_its >= 1 && p.eig_cg_its <= EIG_MAX_ITS &&
+         p.coarse_eig_its >= 1 && p.coarse_eig_its <= EIG_MAX_ITS && std::isfinite(p.pdas_c) && p.pdas_c >= 0.0;
+}
+
 extern "C" {
 
 int pff_default_params(pff_params* p) {
@@ -975,6 +981,7 @@ int pff_default_params(pff_params* p) {
   p->ls_omega = 0.5;
   p->ls_max = 10;
   p->vcycle_fp32 = 0;
+  p->pdas_c = 0.0;
   return PFF_OK;
 }
 
@@ -991,11 +998,7 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
   ms.band_y = spec->band_y;
   ms.tile_x = spec->tile_x;
   ms.tile_y = spec->tile_y;
-  if (params->cheb_degree < 1 || params->coarse_its < 1 || params->gmres_restart < 1 ||
-      params->gmres_restart > 60 || params->coarse_mode < 0 || params->coarse_mode > 1 ||
-      params->eig_cg_its < 1 || params->eig_cg_its > EIG_MAX_ITS || params->coarse_eig_its < 1 ||
-      params->coarse_eig_its > EIG_MAX_ITS)
-    return PFF_E_ARG;
+  if (!params_valid(*params)) return PFF_E_ARG;
   try {
     bool built = false;
     try {
@@ -1092,10 +1095,7 @@ int pff_destroy(pff_ctx* c) {
 
 int pff_set_params(pff_ctx* c, const pff_params* p) {
   if (!c || !p) return PFF_E_ARG;
-  if (p->cheb_degree < 1 || p->coarse_its < 1 || p->gmres_restart < 1 || p->gmres_restart > 60 ||
-      p->coarse_mode < 0 || p->coarse_mode > 1 || p->eig_cg_its < 1 || p->eig_cg_its > EIG_MAX_ITS ||
-      p->coarse_eig_its < 1 || p->coarse_eig_its > EIG_MAX_ITS)
-    return PFF_E_ARG;
+  if (!params_valid(*p)) return PFF_E_ARG;
   c->prm = *p;
   c->mg_ready = false;
   return PFF_OK;
@@ -1170,7 +1170,7 @@ int pff_set_state(pff_ctx* c, const double* U, const double* phi_old, const doub
                        c->flags, n, c->red_part);
     hipLaunchKernelGGL(k_reduce_max_final, dim3(1), dim3(RED_THREADS), 0, c->s, c->red_part, RED_BLOCKS, 1e-12, tau);
     hipLaunchKernelGGL(k_active_rule, dim3(grid_for(n)), dim3(256), 0, c->s, c->flags, R, c->mass + 2 * n,
-                       c->U + 2 * n, c->phio, n, tau);
+                       c->U + 2 * n, c->phio, n, tau, c->prm.pdas_c);
   }
   HIPCHK(hipGetLastError());
   c->has_state = true;

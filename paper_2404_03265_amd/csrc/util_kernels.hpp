@@ -52,19 +52,21 @@ __global__ void k_set_active(uint8_t* flags, const uint8_t* active, int64_t n) {
   }
 }
 
-// Active-set rule of Alg. 2 with c_i = 2 |lambda_i / (phi_i - phi_old_i)|
-// (c_i * 0 := 0), lambda = R_phi / B: active <=> lambda + c (phi - phi_old)
-// exceeds tau, tau = 1e-12 max |lambda| (*tau_ptr): exact ties that quadrature
-// turns into rounding noise count as zero, i.e. inactive.
+// Active-set rule of Sec. 2 / Alg. 2, lambda = R_phi / B: active <=>
+// lambda + c (phi - phi_old) exceeds tau, tau = 1e-12 max |lambda| (*tau_ptr):
+// exact ties that quadrature turns into rounding noise count as zero, i.e.
+// inactive. c_fixed = 0 selects the per-unknown constant
+// c_i = 2 |lambda_i / (phi_i - phi_old_i)| (c_i * 0 := 0); c_fixed > 0 is
+// used for every unknown.
 __global__ void k_active_rule(uint8_t* flags, const double* R, const double* mass, const double* phi,
-                              const double* phio, int64_t n, const double* tau_ptr) {
+                              const double* phio, int64_t n, const double* tau_ptr, double c_fixed) {
   const double tau = *tau_ptr;
   GRID_LOOP(i, n) {
     uint8_t f = flags[i] & uint8_t(~NODE_ACTIVE);
     if (!(f & NODE_HANGING)) {
       const double lam = R[2 * n + i] / mass[i];
       const double diff = phi[i] - phio[i];
-      const double c = diff != 0.0 ? 2.0 * fabs(lam / diff) : 0.0;
+      const double c = c_fixed > 0.0 ? c_fixed : (diff != 0.0 ? 2.0 * fabs(lam / diff) : 0.0);
       const double val = lam + c * diff;
       if (val > tau) f |= NODE_ACTIVE;
     }

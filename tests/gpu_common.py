@@ -16,10 +16,14 @@ def torch_cuda():
 
 
 class Case:
-    """Library solver + oracle problem for one mesh / degree / state recipe."""
+    """Library solver + oracle problem for one mesh / degree / state recipe.
+
+    phit="phi": phi~ equals the phase field of U (the start of a load step);
+    "shifted": phi~ = 0.9 phi + 0.05 + 0.02 N(0, 1), seeded."""
 
     def __init__(self, n_base, n_local, p, coarse=16, band=(2.0, 0.5), seed=0, u_std=1e-4,
-                 mask="bernoulli", prm=None, solver_params=None, tile=(0, 0), build_oracle=True):
+                 mask="bernoulli", prm=None, solver_params=None, tile=(0, 0), build_oracle=True,
+                 phit="phi"):
         import torch
         from paper_2404_03265_amd import PhaseFieldSolver, SolverParams
         self.torch = torch
@@ -42,7 +46,12 @@ class Case:
         uy = np.where(dirichlet, 0.0, uy)
         self.U_raw = np.concatenate([ux, uy, phi])
         self.phi_old_raw = phi.copy()
-        self.phit_raw = phi.copy()
+        if phit == "shifted":
+            # a linearisation phase field distinct from phi, so that a kernel
+            # reading one in place of the other fails parity
+            self.phit_raw = 0.9 * phi + 0.05 + 0.02 * inputs.normal(seed, 41, X, Y)
+        else:
+            self.phit_raw = phi.copy()
         self.mask_kind = mask
         if mask == "bernoulli":
             self.active = inputs.bernoulli_mask(X, Y, 2, 0.1) & ((flags & 2) == 0)

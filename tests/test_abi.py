@@ -45,6 +45,16 @@ def test_host_only_calls():
     p = _lib.Params()
     assert lib.pff_default_params(C.byref(p)) == 0
     assert p.cheb_degree == 3 and p.gmres_restart == 30 and abs(p.smooth_range - 0.08) < 1e-15
+    assert p.pdas_c == 0.0
+    # invalid parameters are refused before any device work
+    ctx = C.c_void_p()
+    mspec = _lib.MeshSpec(32, 1, 1, 16, 2.0, 0.5, 0, 0)
+    for field, value in (("pdas_c", -1.0), ("pdas_c", float("inf")), ("cheb_degree", 0), ("eig_cg_its", 201)):
+        bad = _lib.Params()
+        lib.pff_default_params(C.byref(bad))
+        setattr(bad, field, value)
+        assert lib.pff_create(C.byref(mspec), C.byref(bad), C.byref(ctx)) == -1, field
+        assert not ctx.value
     # argument errors are reported without touching a device
     assert lib.pff_default_params(None) < 0
     assert lib.pff_vmult(None, None, None, None) < 0

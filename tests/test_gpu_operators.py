@@ -31,7 +31,7 @@ def case(name, p, mask="bernoulli"):
         m = MESHES[name]
         print(f"[case] {key}", flush=True)
         c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask=mask,
-                 u_std=1e-2)
+                 u_std=1e-2, phit="shifted")
         c.load_state()
         _cases[key] = c
     return _cases[key]
@@ -54,6 +54,35 @@ def test_active_set_matches_rule(name, p, mask):
         R = c.lp.residual(c.U_o, c.phit_o)[2 * c.n:]
         scale = np.abs(R).max()
         assert np.all(np.abs(R[c.g2o][diff]) <= 1e-12 * scale), diff
+
+
+@pytest.mark.parametrize("p", (1, 2))
+@pytest.mark.parametrize("c_fixed", (0.0, 0.5, 50.0))
+def test_active_set_rule_with_phase_field_change(p, c_fixed):
+    """Active-set rule of Sec. 2 where phi - phi_old takes both signs (phi_old
+    = phi + 0.02 N(0, 1), seeded): the per-unknown c (pdas_c = 0) and constant
+    values of c. Both sides decide in FP64; they may differ only where
+    lambda + c (phi - phi_old) is within rounding of zero."""
+    from oracle.newton import active_set
+    from paper_2404_03265_amd import SolverParams
+    m = MESHES["tiny"]
+    print(f"[case] tiny p={p} pdas_c={c_fixed}", flush=True)
+    c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="rule", u_std=1e-2,
+             solver_params=SolverParams(pdas_c=c_fixed), build_oracle=False)
+    c.phi_old_raw = c.phi_old_raw + 0.02 * inputs.normal(5, 40, c.X, c.Y)
+    c.build_oracle(m["n_base"], m["n_local"], p, m["coarse"], m["band"])
+    c.load_state()
+    act = c.g.active().cpu().numpy().astype(bool)
+    R = c.lp.residual(c.U_o, c.phit_o)
+    ref = active_set(c.lp, R, c.U_o[2 * c.n:], c.phio_o, c_fixed)[c.g2o]
+    d = (c.U_o[2 * c.n:] - c.phio_o)[c.g2o]
+    assert np.count_nonzero(d > 0) > 0.2 * c.n and np.count_nonzero(d < 0) > 0.2 * c.n
+    assert 0 < np.count_nonzero(ref) < c.n
+    lam = (R[2 * c.n:] / np.where(c.om.hanging, 1.0, c.lp.lumped_phi_mass()))[c.g2o]
+    diff = np.flatnonzero(act != ref)
+    scale = np.abs(lam).max()
+    cc = c_fixed if c_fixed > 0 else 2.0 * np.abs(lam[diff] / np.where(d[diff] != 0, d[diff], 1.0))
+    assert np.all(np.abs(lam[diff] + cc * d[diff]) <= 1e-11 * scale), diff
 
 
 @pytest.mark.parametrize("name,p,mask", PARAMS)

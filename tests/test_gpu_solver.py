@@ -26,7 +26,7 @@ def mg_case(name, p, mask="bernoulli", cheb=3, coarse_its=30, coarse="cheb"):
         print(f"[case] {key}", flush=True)
         sp_ = SolverParams(cheb_degree=cheb, coarse_its=coarse_its, coarse_mode={"cheb": 0, "cg": 1}[coarse])
         c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask=mask,
-                 u_std=1e-2, solver_params=sp_)
+                 u_std=1e-2, solver_params=sp_, phit="shifted")
         c.load_state(setup_mg=True)
         c.hier = Hierarchy(c.om)
         mgp = MGParams(cheb_degree=cheb, coarse_its=coarse_its, coarse_mode=coarse)
@@ -195,7 +195,7 @@ def test_full_size_vmult_sampled_rows():
     (every class of node included) against the oracle row by row."""
     import time
     t0 = time.time()
-    c = Case(1024, 3, 2, mask="bernoulli", u_std=1e-4, build_oracle=False)
+    c = Case(1024, 3, 2, mask="bernoulli", u_std=1e-4, build_oracle=False, phit="shifted")
     c.load_state()
     src = inputs.random_vector(c.X, c.Y, 1)
     dst = c.g.vmult(c.dev(src)).cpu().numpy()

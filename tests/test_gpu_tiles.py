@@ -27,7 +27,7 @@ def case(p, tile):
     if key not in _cases:
         print(f"[case] tiles {key}", flush=True)
         c = Case(MESH["n_base"], MESH["n_local"], p, coarse=MESH["coarse"], band=MESH["band"], u_std=1e-2,
-                 tile=tile)
+                 tile=tile, phit="shifted")
         c.load_state(setup_mg=True)
         _cases[key] = c
     return _cases[key]

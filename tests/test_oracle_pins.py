@@ -464,6 +464,57 @@ def test_active_set_rule_cases():
         assert np.array_equal(a, expect)
 
 
+def test_active_set_fixed_c_cases():
+    """Constant c (Sec. 2 leaves c free): lambda + c (phi - phi_old) > 0 flips
+    exactly at c = lambda / |phi - phi_old| when phi < phi_old; c -> 0 leaves
+    the sign of lambda, a large c the sign of phi - phi_old."""
+    m = Mesh(16, 0, 1)
+    lp = LeafProblem(m, Params())
+    n = m.n_nodes
+    B = lp.lumped_phi_mass()
+    phi_old = np.full(n, 0.5)
+    lamv = np.tile([1.0, -1.0, 0.0], n // 3 + 1)[:n]
+    R = np.concatenate([np.zeros(2 * n), lamv * B])
+    down, up = phi_old - 0.1, phi_old + 0.1
+    assert np.array_equal(active_set(lp, R, down, phi_old, 9.99), lamv > 0)   # 1 - 0.999 > 0
+    assert not active_set(lp, R, down, phi_old, 10.01).any()                 # 1 - 1.001 < 0
+    for phi in (down, up, phi_old):
+        assert np.array_equal(active_set(lp, R, phi, phi_old, 1e-300), lamv > 0)
+    assert np.array_equal(active_set(lp, R, up, phi_old, 1e30), np.ones(n, bool))
+    assert not active_set(lp, R, down, phi_old, 1e30).any()
+    assert np.array_equal(active_set(lp, R, phi_old, phi_old, 1e30), lamv > 0)
+
+
+def test_fixed_c_pdas_reaches_the_same_solution():
+    """Newton / PDAS with a constant c converges to the solution of the
+    complementarity problem (Problem 2) that the per-unknown c reaches: the
+    converged states agree up to nodes where lambda is within rounding of zero
+    (either set is then consistent), and both satisfy complementarity."""
+    mesh = Mesh(32, 2, 1)
+    n = mesh.n_nodes
+    ell = 2 * np.sqrt(2) * 20 / (32 * 4)
+    sols = []
+    for c in (0.0, 1.0, 1e4):
+        lp, U, phi_old = _sneddon(mesh, dict(ell=ell, kappa=1e-10))
+        act = np.zeros(n, bool)
+        for _ in range(30):
+            Un, act_new, info = newton_step(lp, Hierarchy(mesh), MGParams(), NewtonParams(pdas_c=c), U, phi_old,
+                                            phi_old, act, linear_solver="direct")
+            unchanged = np.array_equal(act_new, act)
+            U, act = Un, act_new
+            if unchanged and info.residual_before <= 1e-10:
+                break
+        else:
+            raise AssertionError(f"c = {c}: no convergence")
+        R = lp.residual(U, phi_old)
+        lam = R[2 * n:] / np.where(mesh.hanging, 1, lp.lumped_phi_mass())
+        assert np.all(U[2 * n:][~act] <= phi_old[~act] + 1e-8)
+        assert np.all(lam[act] >= -1e-10)
+        sols.append(U)
+    for U in sols[1:]:
+        assert np.abs(U - sols[0]).max() <= 1e-7 * np.abs(sols[0]).max()
+
+
 # --------------------------------------------------------------- adjoint ---
 def test_adjoint_gradient_matches_finite_differences():
     mesh = Mesh(16, 1, 1, coarse=4, band=(3.0, 1.0))
