@@ -150,6 +150,8 @@ def main():
                          "quasistatic: pressure increments p = 1e-3 k with the active set carried, "
                          "FP32 V-cycle, adjoint at the last step (use with sneddon_2048x2048_L4_Q2)")
     ap.add_argument("--increments", type=int, default=10)
+    ap.add_argument("--extrapolate", action="store_true",
+                    help="quasistatic: phi~ extrapolated from the last two load steps (from the third increment)")
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--profile-pass", action="store_true",
                     help="only a few vmults and one plain device copy of the same vector "
@@ -336,7 +338,7 @@ def main():
     if args.scenario == "diff":
         out["scenario"] = scenario_diff(g, spec, sp_, log)
     elif args.scenario == "quasistatic":
-        out["scenario"] = scenario_quasistatic(g, spec, sp_, args.increments, log)
+        out["scenario"] = scenario_quasistatic(g, spec, sp_, args.increments, log, args.extrapolate)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb = cpu_baseline()
@@ -422,49 +424,56 @@ def scenario_diff(g, spec, sp_, log):
     }
 
 
-def scenario_quasistatic(g, spec, sp_, increments, log):
+def scenario_quasistatic(g, spec, sp_, increments, log, extrapolate=False):
     """Pressure increments p = 1e-3 k (k = 1..K): each load step solved by
-    Newton / active set iterations from the previous solution, phi_old and
-    phi~ the previous step's phase field, active set carried over; FP32
+    Newton / active set iterations from the previous solution, phi_old the
+    previous step's phase field, phi~ = phi_old or (extrapolate) the linear
+    extrapolation from the last two steps, active set carried over; FP32
     V-cycle (Chebyshev 4, coarse CG), FP64 outer loop; adjoint gradient of
     TCV at the last step."""
     import torch
 
-    from paper_2404_03265_amd.autograd import adjoint_tcv_gradient, solve_load_step
+    from paper_2404_03265_amd.autograd import adjoint_tcv_gradient, solve_load_path
     U, phi0, _, _ = make_state(g, spec, random=False)
     for k, v in dict(vcycle_fp32=1, cheb_degree=4, coarse_mode=1, coarse_its=30).items():
         setattr(sp_, k, v)
-    active = None
+    g.set_params(sp_)
+    pressures = [1e-3 * k for k in range(1, increments + 1)]
     steps = []
-    phi_old = phi0.clone()
-    t_all = time.perf_counter()
-    for k in range(1, increments + 1):
-        sp_.pressure = 1e-3 * k
-        g.set_params(sp_)
+    clock = {"t": time.perf_counter()}
+
+    def progress(k, j, info):
+        if j % 10 == 0:
+            log(f"  increment {k + 1}: {j} Newton steps, |R~| {info['residual_before']:.2e}, "
+                f"{info['n_active']} active")
+
+    def record(k, phi_tilde, infos):
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        def progress(j, info, k=k):
-            if j % 10 == 0:
-                log(f"  increment {k}: {j} Newton steps, |R~| {info['residual_before']:.2e}, "
-                    f"{info['n_active']} active")
-        active, infos = solve_load_step(g, U, phi_old, phi_old, active=active, tol=1e-7, max_steps=400,
-                                        progress=progress)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        now = time.perf_counter()
+        dt, clock["t"] = now - clock["t"], now
         tcv = g.tcv(U)
-        steps.append({"pressure": sp_.pressure, "seconds": dt, "newton_steps": len(infos),
+        steps.append({"pressure": pressures[k], "seconds": dt, "newton_steps": len(infos),
                       "gmres_iterations": [i["gmres_iterations"] for i in infos],
                       "final_residual": infos[-1]["residual_before"], "n_active": infos[-1]["n_active"],
                       "tcv": tcv})
-        log(f"increment {k}: p={sp_.pressure:.0e} {dt:.2f} s, {len(infos)} Newton steps, "
+        log(f"increment {k + 1}: p={pressures[k]:.0e} {dt:.2f} s, {len(infos)} Newton steps, "
             f"gmres {steps[-1]['gmres_iterations']}, |R~| {steps[-1]['final_residual']:.2e}, TCV {tcv:.6e}")
-        phi_old = U[2 * g.n:].clone()
+        clock["t"] = time.perf_counter()
+
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    clock["t"] = t_all
+    active, out = solve_load_path(g, U, phi0, pressures, extrapolate=extrapolate, tol=1e-7,
+                                  progress=progress, done=record)
     total = time.perf_counter() - t_all
+    phi_old = out[-1][2]
+    phi_tilde = out[-1][0]
     t0 = time.perf_counter()
-    tcv, grad, _, ginfo = adjoint_tcv_gradient(g, U, phi_old, phi_old, active)
+    tcv, grad, _, ginfo = adjoint_tcv_gradient(g, U, phi_old, phi_tilde, active)
     t_adj = time.perf_counter() - t0
     log(f"adjoint at the last step: {t_adj:.2f} s, {ginfo['iterations']} GMRES iterations, grad {grad.tolist()}")
-    return {"name": "quasistatic", "workload": spec.name, "increments": steps, "total_seconds": total,
+    return {"name": "quasistatic", "workload": spec.name, "extrapolated_phi_tilde": bool(extrapolate),
+            "increments": steps, "total_seconds": total,
             "adjoint_seconds": t_adj, "adjoint_gmres_iterations": ginfo["iterations"],
             "grad_Gc_E_p": [float(x) for x in grad.tolist()]}
 

@@ -167,6 +167,18 @@ int pff_tile_stats(const pff_ctx* ctx, int32_t level, int64_t* n_tiles, int64_t*
  * Synchronises the stream when setup_mg != 0. */
 int pff_set_state(pff_ctx* ctx, const double* U, const double* phi_old, const double* phi_tilde,
                   const uint8_t* active, int32_t setup_mg, void* stream);
+/* Linearisation phase field for the next load step (Sec. 2: phi~ is the
+ * previous step's phase field or an extrapolation from earlier steps):
+ * out = min(1, max(0, phi_prev + theta (phi_prev - phi_prev2))) over the n
+ * leaf nodes; device pointers, n doubles each, owned by the caller; out may
+ * alias either input. theta = (t_n - t_{n-1}) / (t_{n-1} - t_{n-2}) for load
+ * parameters t (1 for equal increments); theta = 0 gives phi_prev. The clip
+ * keeps phi~ in the range of the phase field. Hanging entries follow the
+ * formula; set_state replaces them by the interpolation of their masters.
+ * Needs no state. Errors: PFF_E_ARG (null pointer, theta negative or not
+ * finite). */
+int pff_extrapolate_phi(pff_ctx* ctx, const double* phi_prev, const double* phi_prev2, double theta,
+                        double* out, void* stream);
 /* Copy the current active set (device n bytes, 1 = active). */
 int pff_get_active(pff_ctx* ctx, uint8_t* active, void* stream);
 

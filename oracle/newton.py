@@ -76,6 +76,14 @@ def active_set(lp: LeafProblem, R, phi, phi_old, c_fixed=0.0):
     return (val > tau) & ~hang
 
 
+def extrapolate_phase_field(phi_prev, phi_prev2, theta=1.0):
+    """Sec. 2: the linearisation field phi~ of a load step may be extrapolated
+    from earlier steps. Linear extrapolation in the load parameter t,
+    theta = (t_n - t_{n-1}) / (t_{n-1} - t_{n-2}), kept in the phase field's
+    range [0, 1]."""
+    return np.clip(phi_prev + theta * (phi_prev - phi_prev2), 0.0, 1.0)
+
+
 def masked_residual(lp: LeafProblem, U, phit, active):
     return lp.residual(U, phit) * lp.free_mask(active)
 

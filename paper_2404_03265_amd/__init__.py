@@ -136,6 +136,13 @@ class PhaseFieldSolver:
         self._check(self.lib.pff_set_state(self.h, _ptr(U), _ptr(phi_old), _ptr(phi_tilde),
                                            _ptr(active), int(setup_mg), _stream()))
 
+    def extrapolate_phi(self, phi_prev, phi_prev2, theta: float = 1.0, out=None):
+        import torch
+        out = torch.empty_like(phi_prev) if out is None else out
+        self._check(self.lib.pff_extrapolate_phi(self.h, _ptr(phi_prev), _ptr(phi_prev2), float(theta), _ptr(out),
+                                                 _stream()))
+        return out
+
     def active(self):
         import torch
         a = torch.empty(self.n, dtype=torch.uint8, device="cuda")

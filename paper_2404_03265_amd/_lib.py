@@ -55,6 +55,7 @@ _SIGS = {
                                  C.POINTER(C.c_int64)]),
     "pff_set_state": (C.c_int, [VP, VP, VP, VP, VP, C.c_int32, VP]),
     "pff_get_active": (C.c_int, [VP, VP, VP]),
+    "pff_extrapolate_phi": (C.c_int, [VP, VP, VP, C.c_double, VP, VP]),
     "pff_vmult": (C.c_int, [VP, VP, VP, VP]),
     "pff_vmult_T": (C.c_int, [VP, VP, VP, C.c_int32, VP]),
     "pff_inverse_diagonal": (C.c_int, [VP, C.c_int32, VP, C.c_int32, VP]),

@@ -7,6 +7,8 @@
       J~^T z = dTCV/dU (constrained rows zero),  dTCV/dtheta = -z^T dF~/dtheta.
 * TcvOfParams: torch.autograd.Function theta -> TCV(U(theta)) whose forward runs
   Newton / active set iterations (Alg. 2) and whose backward is the adjoint.
+* solve_load_step / solve_load_path: one load step, and a sequence of pressure
+  increments with the active set carried over (quasi-static loading, Sec. 4).
 """
 from __future__ import annotations
 
@@ -40,6 +42,42 @@ def solve_load_step(solver, U, phi_old, phi_tilde, active=None, tol=1e-7, max_st
         if torch.equal(prev, active) and info["residual_before"] <= tol:
             break
     return active, infos
+
+
+def solve_load_path(solver, U, phi0, pressures, extrapolate=False, tol=1e-7, max_steps=400, progress=None,
+                    done=None):
+    """Quasi-static pressure increments: for each p_k in pressures, solve the
+    load step (Alg. 2) from the previous solution with the previous active set,
+    phi_old = the previous step's phase field (phi0 for the first) and the
+    linearisation field phi~ (Sec. 2) either phi_old or, with
+    extrapolate=True and two solved steps behind, the linear extrapolation in
+    p from the last two (pff_extrapolate_phi, clipped to [0, 1]). U is updated
+    in place. progress(k, j, info), if given, is called after Newton step j of
+    increment k, done(k, phi~, infos) after increment k. Returns (active,
+    per-increment list of (phi~ used, infos, phi_old used))."""
+    from dataclasses import replace
+    n = solver.n
+    active = None
+    phi_old = phi0.clone()
+    phi_prev2 = None
+    out = []
+    for k, p in enumerate(pressures):
+        solver.set_params(replace(solver.params, pressure=float(p)))
+        if extrapolate and phi_prev2 is not None:
+            theta = (float(p) - float(pressures[k - 1])) / (float(pressures[k - 1]) - float(pressures[k - 2]))
+            phi_tilde = solver.extrapolate_phi(phi_old, phi_prev2, theta)
+        else:
+            phi_tilde = phi_old
+        cb = None if progress is None else (lambda j, info, k=k: progress(k, j, info))
+        active, infos = solve_load_step(solver, U, phi_old, phi_tilde, active=active, tol=tol,
+                                        max_steps=max_steps, progress=cb)
+        out.append((phi_tilde, infos, phi_old))
+        if done is not None:
+            done(k, phi_tilde, infos)
+        if k >= 1:
+            phi_prev2 = phi_old
+        phi_old = U[2 * n:].clone()
+    return active, out
 
 
 def solve_frozen(solver, U, phi_old, phi_tilde, active, tol=1e-10, max_steps=20):

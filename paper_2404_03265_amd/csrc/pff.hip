@@ -1193,6 +1193,18 @@ int pff_get_active(pff_ctx* c, uint8_t* active, void* stream) {
   GUARD_END(c)
 }
 
+int pff_extrapolate_phi(pff_ctx* c, const double* phi_prev, const double* phi_prev2, double theta, double* out,
+                        void* stream) {
+  if (!c || !phi_prev || !phi_prev2 || !out || !std::isfinite(theta) || theta < 0.0) return PFF_E_ARG;
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_extrapolate_phi, dim3(grid_for(c->n)), dim3(256), 0, c->s, out, phi_prev, phi_prev2, theta,
+                     c->n);
+  HIPCHK(hipGetLastError());
+  return PFF_OK;
+  GUARD_END(c)
+}
+
 int pff_vmult(pff_ctx* c, double* dst, const double* src, void* stream) {
   if (!c || !dst || !src || dst == src) return PFF_E_ARG;
   if (!c->has_state) { c->err = "vmult needs a state"; return PFF_E_STATE; }

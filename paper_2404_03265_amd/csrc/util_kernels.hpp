@@ -74,6 +74,19 @@ __global__ void k_active_rule(uint8_t* flags, const double* R, const double* mas
   }
 }
 
+// Linearisation phase field extrapolated from two earlier load steps (Sec. 2):
+// out = phi_prev + theta (phi_prev - phi_prev2), clipped to [0, 1]. Products
+// and sums are rounded separately (no fused multiply-add), so the result is
+// the correctly rounded value of each step.
+__global__ void k_extrapolate_phi(double* out, const double* a, const double* b, double theta, int64_t n) {
+#pragma clang fp contract(off)
+  GRID_LOOP(i, n) {
+    const double ai = a[i];
+    const double step = theta * (ai - b[i]);
+    out[i] = fmin(1.0, fmax(0.0, ai + step));
+  }
+}
+
 // per-block maxima of |R_phi / B| over non-hanging nodes
 __global__ void __launch_bounds__(RED_THREADS) k_lambda_max_partial(const double* R, const double* mass,
                                                                       const uint8_t* flags, int64_t n,

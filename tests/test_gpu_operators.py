@@ -85,6 +85,24 @@ def test_active_set_rule_with_phase_field_change(p, c_fixed):
     assert np.all(np.abs(lam[diff] + cc * d[diff]) <= 1e-11 * scale), diff
 
 
+@pytest.mark.parametrize("theta", (0.0, 1.0, 0.75))
+def test_extrapolate_phi_matches_oracle(theta):
+    """phi~ extrapolated from two load steps and clipped to [0, 1] (Sec. 2):
+    bitwise equal to the oracle (each product and sum rounded separately),
+    also when the output overwrites an input."""
+    from oracle.newton import extrapolate_phase_field
+    c = case("tiny", 2)
+    x = -0.5 + 2.0 * inputs.uniform01(7, 50, c.X, c.Y)
+    y = -0.5 + 2.0 * inputs.uniform01(7, 51, c.X, c.Y)
+    ref = extrapolate_phase_field(x, y, theta)
+    got = c.g.extrapolate_phi(c.dev(x), c.dev(y), theta).cpu().numpy()
+    assert np.array_equal(got, ref)
+    xd = c.dev(x)
+    c.g.extrapolate_phi(xd, c.dev(y), theta, out=xd)
+    assert np.array_equal(xd.cpu().numpy(), ref)
+    assert 0 < np.count_nonzero(ref == 0.0) and 0 < np.count_nonzero(ref == 1.0)
+
+
 @pytest.mark.parametrize("name,p,mask", PARAMS)
 def test_vmult_matches_oracle(name, p, mask):
     c = case(name, p, mask)

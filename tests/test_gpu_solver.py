@@ -189,6 +189,58 @@ def test_newton_step_matches_oracle(name, p):
     assert abs(info["residual_after"] - oinfo.residual_after) <= 1e-6 * oinfo.residual_before + 1e-12
 
 
+@pytest.mark.parametrize("p", (1, 2))
+def test_load_path_with_extrapolated_phi_tilde(p):
+    """Three pressure increments with the active set carried over and phi~
+    extrapolated from the last two steps in the third (Sec. 2, Sec. 4), against
+    the oracle's Newton / PDAS loop with direct solves: the phi~ used, the
+    converged states per block and the crack volume agree to the Newton
+    tolerance; the active sets agree up to nodes whose decision is a tie."""
+    import dataclasses
+    from oracle.newton import extrapolate_phase_field
+    from paper_2404_03265_amd.autograd import solve_load_path
+    m = MESHES["tiny"]
+    print(f"[case] load path tiny p={p}", flush=True)
+    c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="rule")
+    n = c.n
+    lp = c.lp
+    ux, uy, phi = inputs.sneddon_state(c.X, c.Y, c.M, p, random=False)
+    Uo = lp.distribute(c.to_o(np.concatenate([ux, uy, phi])))
+    U = c.dev(c.to_g(Uo))
+    pres = [1e-3, 2e-3, 3.5e-3]
+    act, out = solve_load_path(c.g, U, U[2 * n:].clone(), pres, extrapolate=True, tol=1e-10)
+    phi_old, prev2 = Uo[2 * n:].copy(), None
+    act_o = np.zeros(n, bool)
+    for k, pk in enumerate(pres):
+        lp.prm = dataclasses.replace(lp.prm, pressure=pk)
+        if prev2 is not None:
+            theta = (pk - pres[k - 1]) / (pres[k - 1] - pres[k - 2])
+            phit = lp.distribute(extrapolate_phase_field(phi_old, prev2, theta))
+            assert np.abs(phit - phi_old).max() > 1e-9          # the extrapolation changes phi~
+        else:
+            phit = phi_old
+        for _ in range(60):
+            Un, an, info = newton_step(lp, None, None, NewtonParams(), Uo, phi_old, phit, act_o,
+                                       linear_solver="direct")
+            same = np.array_equal(an, act_o)
+            Uo, act_o = Un, an
+            if same and info.residual_before <= 1e-10:
+                break
+        phit_g = lp.distribute(c.to_o(out[k][0].cpu().numpy()))
+        assert np.abs(phit_g - phit).max() <= 1e-6, k
+        assert out[k][1][-1]["residual_before"] <= 1e-10
+        if k >= 1:
+            prev2 = phi_old
+        phi_old = Uo[2 * n:].copy()
+    Ug = c.to_o(U.cpu().numpy())
+    for b in range(3):
+        sl = slice(b * n, (b + 1) * n)
+        assert rel_err(Ug[sl], Uo[sl]) <= 1e-6, b
+    assert abs(c.g.tcv(U) - lp.tcv(Uo)) <= 1e-6 * abs(lp.tcv(Uo))
+    diff = np.flatnonzero(act.cpu().numpy().astype(bool)[c.o2g] != act_o)
+    assert diff.size <= 0.01 * n, diff
+
+
 def test_full_size_vmult_sampled_rows():
     """The benchmark workload (1024 x 1024 base cells + 3 local levels, Q2,
     20.5 M unknowns) in the benchmark's launch configuration: 600 sampled rows

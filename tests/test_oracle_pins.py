@@ -14,8 +14,8 @@ from oracle.fe import Element
 from oracle.mesh import Mesh
 from oracle.mg import Hierarchy, MGParams, VCycle, cg_eigs, chebyshev
 from oracle.krylov import gmres
-from oracle.newton import (NewtonParams, active_set, adjoint_gradient, newton_step,
-                           solve_frozen)
+from oracle.newton import (NewtonParams, active_set, adjoint_gradient, extrapolate_phase_field,
+                           newton_step, solve_frozen)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
 
@@ -513,6 +513,25 @@ def test_fixed_c_pdas_reaches_the_same_solution():
         sols.append(U)
     for U in sols[1:]:
         assert np.abs(U - sols[0]).max() <= 1e-7 * np.abs(sols[0]).max()
+
+
+def test_phase_field_extrapolation():
+    """Linear extrapolation of phi~ in the load parameter (Sec. 2): a field
+    affine in t is continued exactly for unequal steps; theta = 0 returns the
+    previous step; a continuation outside [0, 1] takes the nearest bound."""
+    rng = np.random.default_rng(3)
+    a, b = rng.uniform(0.3, 0.7, 64), rng.uniform(-0.05, 0.05, 64)
+    t = (0.3, 1.1, 2.0)
+    f = [a + b * tk for tk in t]
+    theta = (t[2] - t[1]) / (t[1] - t[0])
+    assert np.abs(extrapolate_phase_field(f[1], f[0], theta) - f[2]).max() <= 1e-15
+    assert np.array_equal(extrapolate_phase_field(f[1], f[0], 0.0), f[1])
+    x = rng.uniform(-0.5, 1.5, 1000)
+    y = rng.uniform(-0.5, 1.5, 1000)
+    e = extrapolate_phase_field(x, y, 0.75)
+    assert e.min() >= 0.0 and e.max() <= 1.0
+    line = x + 0.75 * (x - y)
+    assert np.all(e[line >= 1.0] == 1.0) and np.all(e[line <= 0.0] == 0.0)
 
 
 # --------------------------------------------------------------- adjoint ---
