@@ -229,6 +229,7 @@ def test_load_path_with_extrapolated_phi_tilde(p):
         phit_g = lp.distribute(c.to_o(out[k][0].cpu().numpy()))
         assert np.abs(phit_g - phit).max() <= 1e-6, k
         assert out[k][1][-1]["residual_before"] <= 1e-10
+        phi_prev_o = phi_old
         if k >= 1:
             prev2 = phi_old
         phi_old = Uo[2 * n:].copy()
@@ -237,8 +238,60 @@ def test_load_path_with_extrapolated_phi_tilde(p):
         sl = slice(b * n, (b + 1) * n)
         assert rel_err(Ug[sl], Uo[sl]) <= 1e-6, b
     assert abs(c.g.tcv(U) - lp.tcv(Uo)) <= 1e-6 * abs(lp.tcv(Uo))
+    # differing flags only where the state sits on the obstacle (a tie)
     diff = np.flatnonzero(act.cpu().numpy().astype(bool)[c.o2g] != act_o)
-    assert diff.size <= 0.01 * n, diff
+    assert np.abs(Uo[2 * n:][diff] - phi_prev_o[diff]).max(initial=0.0) <= 1e-8
+
+
+@pytest.mark.parametrize("p", (1, 2))
+def test_mixed_precision_load_step(p):
+    """A load step (Alg. 2 to |R~| <= 1e-10) with the FP32 V-cycle inside the
+    FP64 GMRES / Newton loop (Chebyshev 4, coarse CG) reaches the state the
+    FP64 configuration reaches and the oracle's loop with direct solves: the
+    preconditioner's precision changes the iteration counts, not the
+    converged residual or the solution."""
+    from paper_2404_03265_amd import SolverParams
+    from paper_2404_03265_amd.autograd import solve_load_step
+    m = MESHES["small"]
+    print(f"[case] mixed-precision load step small p={p}", flush=True)
+    states = {}
+    for label, extra in (("fp64", {}), ("mixed", dict(vcycle_fp32=1, cheb_degree=4, coarse_mode=1))):
+        c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="rule",
+                 solver_params=SolverParams(**extra), build_oracle=(label == "fp64"))
+        ux, uy, phi = inputs.sneddon_state(c.X, c.Y, c.M, p, random=False)
+        U = c.dev(np.concatenate([ux, uy, phi]))
+        ph = c.dev(phi)
+        act, infos = solve_load_step(c.g, U, ph, ph, tol=1e-10, max_steps=60)
+        assert infos[-1]["residual_before"] <= 1e-10, label
+        states[label] = (U.cpu().numpy(), act.cpu().numpy().astype(bool), infos)
+        if label == "fp64":
+            co = c
+    n = co.n
+    U64, a64, _ = states["fp64"]
+    U32, a32, _ = states["mixed"]
+    for b in range(3):
+        sl = slice(b * n, (b + 1) * n)
+        assert rel_err(U32[sl], U64[sl]) <= 1e-8, b
+    # nodes whose flag differs sit on the obstacle (phi = phi_old) in both
+    # states: active or not, the state is the same there (a tie)
+    diff = np.flatnonzero(a32 != a64)
+    assert np.abs(U64[2 * n:][diff] - phi[diff]).max(initial=0.0) <= 1e-8
+    assert np.abs(U32[2 * n:][diff] - phi[diff]).max(initial=0.0) <= 1e-8
+    # oracle: the same loop with direct solves
+    lp = co.lp
+    Uo = lp.distribute(co.to_o(np.concatenate([ux, uy, phi])))
+    pho = Uo[2 * n:].copy()
+    act_o = np.zeros(n, bool)
+    for _ in range(60):
+        Un, an, info = newton_step(lp, None, None, NewtonParams(), Uo, pho, pho, act_o, linear_solver="direct")
+        same = np.array_equal(an, act_o)
+        Uo, act_o = Un, an
+        if same and info.residual_before <= 1e-10:
+            break
+    Ug = co.to_o(U32)
+    for b in range(3):
+        sl = slice(b * n, (b + 1) * n)
+        assert rel_err(Ug[sl], Uo[sl]) <= 1e-8, b
 
 
 def test_full_size_vmult_sampled_rows():
