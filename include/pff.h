@@ -133,13 +133,32 @@ typedef struct {
 int pff_default_params(pff_params* p);
 
 /* Build the mesh, tile tables and multigrid levels on the host and upload
- * them to the current HIP device. The context owns those device tables and
- * its internal work vectors (allocated here and on first use). Errors:
+ * them to the current HIP device. The context owns those device tables; its
+ * work vectors come from a bound workspace (pff_bind_workspace) or are
+ * allocated on first use. Errors:
  * PFF_E_ARG, PFF_E_MESH, PFF_E_NOMEM, PFF_E_HIP. */
 int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** out);
 int pff_destroy(pff_ctx* ctx);
 /* Replace material/solver parameters (takes effect at the next set_state). */
 int pff_set_params(pff_ctx* ctx, const pff_params* params);
+
+/* Device memory for the context's work buffers, to be owned by the caller
+ * (e.g. a torch uint8 tensor): the leaf state copies and work vectors (10
+ * vectors of 3n doubles and 2 of n), the partial sums of shared nodes, both
+ * precisions of every level's vectors (7 of 3 n_level each) and the GMRES
+ * basis for the current gmres_restart ((restart + 1) vectors of 3n doubles),
+ * each rounded up to 256 bytes. The mesh, tile and transfer tables and a few
+ * KB of scalars stay allocated by the library (pff_create). */
+int pff_workspace_bytes(const pff_ctx* ctx, size_t* bytes);
+/* Bind a caller-owned device buffer of at least pff_workspace_bytes bytes,
+ * 256-byte aligned, as the home of every work buffer: after this call the
+ * library allocates no device memory for them (without it they are allocated
+ * on first use). Must precede every call that uses work vectors (set_state,
+ * newton_step, tcv); the buffer must stay valid until pff_destroy, which does
+ * not free it. While bound, pff_set_params refuses a gmres_restart above the
+ * one the workspace was sized for. Errors: PFF_E_ARG (null, misaligned or too
+ * small), PFF_E_STATE (work vectors already exist or a workspace is bound). */
+int pff_bind_workspace(pff_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Sizes: leaf nodes n (vectors have 3n entries), number of multigrid levels,
  * and (if level_nodes != NULL, host, n_levels entries) nodes per level. */

@@ -64,10 +64,15 @@ def _stream():
 
 
 class PhaseFieldSolver:
-    """One mesh + parameter set on the current HIP device."""
+    """One mesh + parameter set on the current HIP device.
+
+    torch_workspace=True: the library's work buffers live in one torch uint8
+    tensor bound with pff_bind_workspace (sized for the current
+    gmres_restart); False: the library allocates them on first use."""
 
     def __init__(self, n_base: int, n_local: int, degree: int, coarse: int = 16,
-                 band=(2.0, 0.5), tile=(0, 0), params: SolverParams | None = None):
+                 band=(2.0, 0.5), tile=(0, 0), params: SolverParams | None = None,
+                 torch_workspace: bool = True):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("PhaseFieldSolver needs a HIP device")
@@ -91,11 +96,21 @@ class PhaseFieldSolver:
         self._check(self.lib.pff_lattice(self.h, C.byref(M)))
         self.M = M.value
         self.degree = degree
+        self._ws = None
+        if torch_workspace:
+            self._ws = torch.empty(self.workspace_bytes(), dtype=torch.uint8, device="cuda")
+            self._check(self.lib.pff_bind_workspace(self.h, _ptr(self._ws), self._ws.numel()))
+
+    def workspace_bytes(self) -> int:
+        b = C.c_size_t()
+        self._check(self.lib.pff_workspace_bytes(self.h, C.byref(b)))
+        return b.value
 
     def close(self):
         if getattr(self, "h", None):
             self.lib.pff_destroy(self.h)
             self.h = None
+        self._ws = None      # the bound workspace outlives the context
 
     def __del__(self):
         try:
@@ -128,8 +143,8 @@ class PhaseFieldSolver:
         return a.value, b.value, c.value
 
     def set_params(self, params: SolverParams):
-        self.params = params
         self._check(self.lib.pff_set_params(self.h, C.byref(params.to_c())))
+        self.params = params
 
     # ---- state and operators ---------------------------------------------------
     def set_state(self, U, phi_old, phi_tilde, active=None, setup_mg: bool = True):

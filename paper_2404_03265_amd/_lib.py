@@ -48,6 +48,8 @@ _SIGS = {
     "pff_destroy": (C.c_int, [VP]),
     "pff_set_params": (C.c_int, [VP, C.POINTER(Params)]),
     "pff_sizes": (C.c_int, [VP, C.POINTER(C.c_int64), C.POINTER(C.c_int32), VP]),
+    "pff_workspace_bytes": (C.c_int, [VP, C.POINTER(C.c_size_t)]),
+    "pff_bind_workspace": (C.c_int, [VP, VP, C.c_size_t]),
     "pff_lattice": (C.c_int, [VP, C.POINTER(C.c_int64)]),
     "pff_node_coords": (C.c_int, [VP, C.c_int32, VP]),
     "pff_node_flags": (C.c_int, [VP, C.c_int32, VP]),

@@ -10,6 +10,7 @@
 #include <memory>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/pff.h"
@@ -251,8 +252,15 @@ struct pff_ctx {
   void* part = nullptr;         // partial sums of shared nodes (largest tile set)
   size_t part_bytes = 0;
   int V_cap = 0;
+  // caller-bound workspace (pff_bind_workspace): the work vectors, level
+  // vectors and GMRES basis are carved from it instead of allocated
+  char* ws = nullptr;
+  size_t ws_size = 0;
+  int ws_restart = 0;           // GMRES restart the bound basis holds
+  bool work_ready = false;      // leaf work vectors exist and the lumped mass is computed
   bool has_state = false;
   bool mg_ready = false;
+  bool fp32_ready = false;      // FP32 level states and diagonals belong to the current setup
   bool eig_fixed = false;
   std::string err;
   hipStream_t s = nullptr;
@@ -389,6 +397,66 @@ struct pff_ctx {
     reduce_to_host(k, host_out);
   }
   double norm(const double* a, int64_t len) { return std::sqrt(dot(a, a, len)); }
+
+  // -------------------------------------------------------- workspace -----
+  // The work buffers in a fixed order, each rounded up to 256 bytes. With
+  // carve == false only their sizes are summed (restart m for the basis);
+  // with carve == true they are placed in the bound workspace.
+  size_t layout_work(bool carve, int m) {
+    size_t off = 0;
+    auto take = [&](auto*& ptr, int64_t count) {
+      using E = std::remove_pointer_t<std::remove_reference_t<decltype(ptr)>>;
+      const size_t b = (size_t(std::max<int64_t>(count, 1)) * sizeof(E) + 255) & ~size_t(255);
+      if (carve) ptr = reinterpret_cast<E*>(ws + off);
+      off += b;
+    };
+    const int64_t N = 3 * n;
+    double* dummy = nullptr;
+    take(carve ? U : dummy, N);
+    take(carve ? phio : dummy, n);
+    take(carve ? phit : dummy, n);
+    take(carve ? mass : dummy, N);
+    for (int i = 0; i < 8; ++i) take(carve ? wv[i] : dummy, N);
+    double* pp = nullptr;
+    take(pp, int64_t(part_bytes / sizeof(double)));
+    if (carve) part = pp;
+    for (DevLevel& L : lv) {
+      const int64_t nl = 3 * L.n;
+      LevelWork<double>& a = L.w64;
+      LevelWork<float>& b = L.w32;
+      double* d64 = nullptr;
+      float* d32 = nullptr;
+      take(carve ? a.state : d64, nl); take(carve ? a.d : d64, nl); take(carve ? a.x[0] : d64, nl);
+      take(carve ? a.x[1] : d64, nl); take(carve ? a.dir[0] : d64, nl); take(carve ? a.dir[1] : d64, nl);
+      take(carve ? a.dinv : d64, nl);
+      take(carve ? b.state : d32, nl); take(carve ? b.d : d32, nl); take(carve ? b.x[0] : d32, nl);
+      take(carve ? b.x[1] : d32, nl); take(carve ? b.dir[0] : d32, nl); take(carve ? b.dir[1] : d32, nl);
+      take(carve ? b.dinv : d32, nl);
+      if (carve) a.ready = b.ready = true;
+    }
+    take(carve ? V : dummy, int64_t(m + 1) * N);
+    if (carve) V_cap = m + 1;
+    return off;
+  }
+  size_t workspace_bytes() { return layout_work(false, std::max(1, prm.gmres_restart)); }
+
+  // leaf work vectors (from the workspace if one is bound) and the lumped
+  // phase-field mass; called by every entry point that uses them
+  void ensure_work() {
+    if (work_ready) return;
+    if (!ws) {
+      U = dalloc<double>(3 * n);
+      phio = dalloc<double>(n);
+      phit = dalloc<double>(n);
+      mass = dalloc<double>(3 * n);
+      for (int i = 0; i < 8; ++i) wv[i] = dalloc<double>(3 * n);
+      part = dalloc<double>(int64_t(part_bytes / sizeof(double)));
+    }
+    // lumped phase-field mass (the B of Alg. 2)
+    leaf_op<MODE_MASS>(mass, nullptr, nullptr);
+    HIPCHK(hipStreamSynchronize(s));
+    work_ready = true;
+  }
 
   // ------------------------------------------------------------ levels -----
   template <typename T>
@@ -811,12 +879,18 @@ struct pff_ctx {
   }
 
   void setup_mg() {
+    fp32_ready = false;
     level_active_sets();
     setup_levels<double>();
     if (!eig_fixed)
       for (int l = 0; l < int(lv.size()); ++l) eig_estimate(l, l == 0 ? prm.coarse_eig_its : prm.eig_cg_its);
-    if (prm.vcycle_fp32) setup_levels<float>();
+    if (prm.vcycle_fp32) setup_fp32();
     mg_ready = true;
+  }
+  // FP32 copies of the level states and diagonals, made once per setup
+  void setup_fp32() {
+    setup_levels<float>();
+    fp32_ready = true;
   }
 
   void residual(double* R, const double* Ust) {
@@ -833,7 +907,7 @@ struct pff_ctx {
   }
   void apply_Minv(double* dst, const double* src, bool fp32) {
     if (fp32) {
-      if (!lv[0].w32.ready) setup_levels<float>();
+      if (!fp32_ready) setup_fp32();
       vcycle_impl<float>(dst, src);
     } else {
       vcycle_impl<double>(dst, src);
@@ -844,6 +918,7 @@ struct pff_ctx {
     const int64_t N = 3 * n;
     const int m = std::max(1, prm.gmres_restart);
     if (V_cap < m + 1) {
+      if (ws) throw std::runtime_error("gmres_restart exceeds the bound workspace");
       if (V) hipFree(V);
       V = dalloc<double>(int64_t(m + 1) * N);
       V_cap = m + 1;
@@ -1038,15 +1113,9 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
       }
     }
     c->setup_coarse_cells();
-    c->U = dalloc<double>(3 * n);
-    c->phio = dalloc<double>(n);
-    c->phit = dalloc<double>(n);
-    c->mass = dalloc<double>(3 * n);
-    for (int i = 0; i < 8; ++i) c->wv[i] = dalloc<double>(3 * n);
     int64_t slots = c->mesh.tiles.n_slots;
     for (const Level& L : c->mesh.levels) slots = std::max(slots, L.tiles.n_slots);
     c->part_bytes = size_t(3 * std::max<int64_t>(slots, 1)) * sizeof(double);
-    c->part = dalloc<double>(3 * std::max<int64_t>(slots, 1));
     c->red_part = dalloc<double>(RED_BLOCKS * 64);
     c->red_out = dalloc<double>(256);
     c->eig_sc = dalloc<double>(2 * EIG_SC);
@@ -1054,9 +1123,7 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
     c->eig_be = dalloc<double>(2 * EIG_MAX_ITS);
     c->ccg_s = dalloc<double>(8);
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->host_red), 256 * sizeof(double), hipHostMallocDefault));
-    // lumped phase-field mass (the B of Alg. 2)
-    c->leaf_op<MODE_MASS>(c->mass, nullptr, nullptr);
-    HIPCHK(hipStreamSynchronize(c->s));
+    (void)n;
   } catch (const std::bad_alloc&) {
     return PFF_E_NOMEM;
   } catch (const std::exception&) {
@@ -1079,15 +1146,19 @@ int pff_destroy(pff_ctx* c) {
   for (DevLevel& D : c->lv) {
     ft(D.tiles);
     f(D.flags); f(D.leaf_index); f(D.PT_ptr); f(D.PT_col); f(D.P_ell); f(D.PT_ell); f(D.PT_rows); f(D.P_wtab);
-    for (auto* w : {&D.w64}) {
-      f(w->state); f(w->d); f(w->x[0]); f(w->x[1]); f(w->dir[0]); f(w->dir[1]); f(w->dinv);
+    if (!c->ws) {   // a bound workspace belongs to the caller
+      LevelWork<double>& a = D.w64;
+      f(a.state); f(a.d); f(a.x[0]); f(a.x[1]); f(a.dir[0]); f(a.dir[1]); f(a.dinv);
+      LevelWork<float>& b = D.w32;
+      f(b.state); f(b.d); f(b.x[0]); f(b.x[1]); f(b.dir[0]); f(b.dir[1]); f(b.dinv);
     }
-    LevelWork<float>& w = D.w32;
-    f(w.state); f(w.d); f(w.x[0]); f(w.x[1]); f(w.dir[0]); f(w.dir[1]); f(w.dinv);
   }
-  f(c->U); f(c->phio); f(c->phit); f(c->mass);
-  for (int i = 0; i < 8; ++i) f(c->wv[i]);
-  f(c->red_part); f(c->red_out); f(c->V); f(c->part); f(c->ccg_s); f(c->coarse_nodes); f(c->eig_sc); f(c->eig_al); f(c->eig_be);
+  if (!c->ws) {
+    f(c->U); f(c->phio); f(c->phit); f(c->mass);
+    for (int i = 0; i < 8; ++i) f(c->wv[i]);
+    f(c->V); f(c->part);
+  }
+  f(c->red_part); f(c->red_out); f(c->ccg_s); f(c->coarse_nodes); f(c->eig_sc); f(c->eig_al); f(c->eig_be);
   if (c->host_red) hipHostFree(c->host_red);
   delete c;
   return PFF_OK;
@@ -1096,9 +1167,41 @@ int pff_destroy(pff_ctx* c) {
 int pff_set_params(pff_ctx* c, const pff_params* p) {
   if (!c || !p) return PFF_E_ARG;
   if (!params_valid(*p)) return PFF_E_ARG;
+  if (c->ws && p->gmres_restart > c->ws_restart) {
+    c->err = "gmres_restart exceeds the restart the bound workspace was sized for";
+    return PFF_E_ARG;
+  }
   c->prm = *p;
   c->mg_ready = false;
+  c->fp32_ready = false;
   return PFF_OK;
+}
+
+int pff_workspace_bytes(const pff_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return PFF_E_ARG;
+  *bytes = const_cast<pff_ctx*>(c)->workspace_bytes();   // sizes only: nothing is modified
+  return PFF_OK;
+}
+
+int pff_bind_workspace(pff_ctx* c, void* ptr, size_t bytes) {
+  if (!c || !ptr || (reinterpret_cast<uintptr_t>(ptr) & 255) != 0) return PFF_E_ARG;
+  if (c->ws || c->work_ready) {
+    c->err = "bind_workspace must come before the first call that uses work vectors";
+    return PFF_E_STATE;
+  }
+  const int m = std::max(1, c->prm.gmres_restart);
+  if (bytes < c->layout_work(false, m)) {
+    c->err = "workspace smaller than pff_workspace_bytes";
+    return PFF_E_ARG;
+  }
+  GUARD_BEGIN
+  c->ws = static_cast<char*>(ptr);
+  c->ws_size = bytes;
+  c->ws_restart = m;
+  c->layout_work(true, m);
+  c->ensure_work();
+  return PFF_OK;
+  GUARD_END(c)
 }
 
 int pff_sizes(const pff_ctx* c, int64_t* n_nodes, int32_t* n_levels, int64_t* level_nodes) {
@@ -1147,6 +1250,7 @@ int pff_set_state(pff_ctx* c, const double* U, const double* phi_old, const doub
   if (!c || !U || !phi_old || !phi_tilde) return PFF_E_ARG;
   GUARD_BEGIN
   c->s = static_cast<hipStream_t>(stream);
+  c->ensure_work();
   const int64_t n = c->n;
   HIPCHK(hipMemcpyAsync(c->U, U, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, c->s));
   HIPCHK(hipMemcpyAsync(c->phio, phi_old, sizeof(double) * n, hipMemcpyDeviceToDevice, c->s));
@@ -1175,6 +1279,7 @@ int pff_set_state(pff_ctx* c, const double* U, const double* phi_old, const doub
   HIPCHK(hipGetLastError());
   c->has_state = true;
   c->mg_ready = false;
+  c->fp32_ready = false;
   if (setup_mg) {
     c->setup_mg();
     HIPCHK(hipStreamSynchronize(c->s));
@@ -1242,7 +1347,7 @@ int pff_inverse_diagonal(pff_ctx* c, int32_t level, void* dst, int32_t fp32, voi
   if (!c->mg_ready) { c->err = "level diagonals need set_state with setup_mg"; return PFF_E_STATE; }
   DevLevel& D = c->lv[level];
   if (fp32) {
-    if (!D.w32.ready) c->setup_levels<float>();
+    if (!c->fp32_ready) c->setup_fp32();
     HIPCHK(hipMemcpyAsync(dst, D.w32.dinv, sizeof(float) * 3 * D.n, hipMemcpyDeviceToDevice, c->s));
   } else {
     HIPCHK(hipMemcpyAsync(dst, D.w64.dinv, sizeof(double) * 3 * D.n, hipMemcpyDeviceToDevice, c->s));
@@ -1313,6 +1418,7 @@ int pff_newton_step(pff_ctx* c, double* U, const double* phi_old, const double* 
   using clk = std::chrono::steady_clock;
   auto t0 = clk::now();
   c->s = static_cast<hipStream_t>(stream);
+  c->ensure_work();
   const int64_t n = c->n, N = 3 * n;
   pff_newton_info inf{};
   // state at U (hanging entries distributed), residual, active set
@@ -1392,6 +1498,7 @@ int pff_tcv(pff_ctx* c, const double* U, double* tcv, double* dTCVdU, void* stre
   if (!c || !U) return PFF_E_ARG;
   GUARD_BEGIN
   c->s = static_cast<hipStream_t>(stream);
+  c->ensure_work();
   double* g = dTCVdU ? dTCVdU : c->wv[7];
   c->leaf_op<MODE_TCVGRAD>(g, U, nullptr);
   // TCV is bilinear: int u . grad phi = (dTCV/dphi) . phi over master nodes

@@ -394,3 +394,79 @@ def test_adjoint_crack_volume_gradient(name, p):
     y = JacobianApply.apply(vv, c.g)
     y.backward(w)
     assert torch.allclose(vv.grad, c.g.vmult_T(w), rtol=0, atol=1e-13 * w.abs().max().item())
+
+
+@pytest.mark.parametrize("p", (1, 2))
+def test_bound_workspace_matches_library_allocation(p):
+    """Work buffers carved from a caller-owned torch tensor (pff_bind_workspace)
+    give bitwise the results of buffers the library allocates itself: vmult,
+    its transpose, both V-cycles, GMRES and a Newton step; binding rules."""
+    import ctypes as C
+    import torch
+    from paper_2404_03265_amd import PhaseFieldSolver, SolverParams
+    from paper_2404_03265_amd.autograd import solve_load_step
+    m = MESHES["tiny"]
+    print(f"[case] workspace tiny p={p}", flush=True)
+    ref = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="rule", build_oracle=False)
+    mk = lambda ws: PhaseFieldSolver(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"],
+                                     params=ref.sp, torch_workspace=ws)
+    solvers = {"library": mk(False), "torch": mk(True)}
+    assert solvers["torch"]._ws.numel() == solvers["torch"].workspace_bytes() > 0
+    U = ref.dev(ref.U_raw)
+    pho = ref.dev(ref.phi_old_raw)
+    pht = ref.dev(0.9 * ref.phit_raw + 0.05)
+    v = ref.dev(inputs.random_vector(ref.X, ref.Y, 61))
+    res = {}
+    for name, g in solvers.items():
+        g.set_state(U, pho, pht, None, setup_mg=True)
+        out = [g.vmult(v), g.vmult_T(v), g.vcycle(v), g.vcycle(v, fp32=True), g.gmres(v)[0]]
+        Uw = U.clone()
+        act = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+        g.newton_step(Uw, pho, pht, act)
+        out += [Uw, act]
+        res[name] = [t.cpu().numpy() for t in out]
+    for a, b in zip(res["library"], res["torch"]):
+        assert np.array_equal(a, b)
+    g = solvers["torch"]
+    # a second binding, or one after the work vectors exist, is refused
+    assert g.lib.pff_bind_workspace(g.h, C.c_void_p(g._ws.data_ptr()), g._ws.numel()) == -2
+    assert solvers["library"].lib.pff_bind_workspace(solvers["library"].h, C.c_void_p(g._ws.data_ptr()),
+                                                     g._ws.numel()) == -2
+    # the bound basis holds the restart it was sized for, not more
+    with pytest.raises(RuntimeError):
+        g.set_params(SolverParams(**{**ref.sp.__dict__, "gmres_restart": ref.sp.gmres_restart + 1}))
+    fresh = mk(False)
+    need = fresh.workspace_bytes()
+    buf = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    assert fresh.lib.pff_bind_workspace(fresh.h, C.c_void_p(buf.data_ptr() + 8), need) == -1     # misaligned
+    assert fresh.lib.pff_bind_workspace(fresh.h, C.c_void_p(buf.data_ptr()), need - 1) == -1     # too small
+    assert fresh.lib.pff_bind_workspace(fresh.h, C.c_void_p(buf.data_ptr()), need) == 0
+    fresh.close()
+    act, infos = solve_load_step(g, U.clone(), pho, pht, tol=1e-9)
+    assert infos[-1]["residual_before"] <= 1e-9
+
+
+@pytest.mark.parametrize("p", (1, 2))
+def test_fp32_levels_follow_each_new_state(p):
+    """The FP32 copies of the level states and diagonals are rebuilt for every
+    multigrid setup, also when the FP32 V-cycle is only requested per call
+    (vcycle_fp32 = 0): after a second set_state the FP32 V-cycle equals the one
+    of a context that only ever saw the second state."""
+    m = MESHES["tiny"]
+    print(f"[case] fp32 levels after a new state tiny p={p}", flush=True)
+    a = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="rule", build_oracle=False)
+    b = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="rule", build_oracle=False,
+             seed=7, u_std=1e-2)
+    v = a.dev(inputs.random_vector(a.X, a.Y, 62))
+    a.load_state(setup_mg=True)
+    first = a.g.vcycle(v, fp32=True).cpu().numpy()
+    a.g.set_state(a.dev(b.U_raw), a.dev(b.phi_old_raw), a.dev(b.phit_raw), None, setup_mg=True)
+    second = a.g.vcycle(v, fp32=True).cpu().numpy()
+    b.load_state(setup_mg=True)
+    lam_max, lam_min0 = b.g.get_eigen()
+    a.g.set_eigen(lam_max, lam_min0)
+    b.g.set_eigen(lam_max, lam_min0)
+    got = a.g.vcycle(v, fp32=True).cpu().numpy()
+    ref = b.g.vcycle(v, fp32=True).cpu().numpy()
+    assert not np.array_equal(first, second)
+    assert np.array_equal(got, ref)
