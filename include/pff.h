@@ -32,6 +32,10 @@
  *  - Return value: 0 on success; negative on error (PFF_E_*), with text from
  *    pff_last_error; positive PFF_W_* when an iteration did not converge
  *    (results are still written).
+ *  - Device memory of a context: its mesh, tile and transfer tables and a few
+ *    KB of scalars are allocated by pff_create; its work buffers live in a
+ *    caller-owned workspace (pff_bind_workspace) or, without one, are
+ *    allocated on first use. pff_destroy frees what the library allocated.
  *  - A context is not thread-safe; calls on one context must not overlap.
  */
 #ifndef PFF_H_
