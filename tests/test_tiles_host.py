@@ -31,6 +31,7 @@ pytestmark = pytest.mark.skipif(not _built(), reason="libpff.so not built")
 CASES = [
     dict(n_base=16, n_local=2, coarse=4, band=(3.0, 1.0)),
     dict(n_base=32, n_local=2, coarse=16, band=(2.0, 0.5)),
+    dict(n_base=32, n_local=0, coarse=8, band=(2.0, 0.5)),     # uniform: no hanging nodes
 ]
 TILES = [(0, 0), (1, 1), (3, 5), (8, 8), (16, 16)]
 
