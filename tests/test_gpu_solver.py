@@ -470,3 +470,45 @@ def test_fp32_levels_follow_each_new_state(p):
     ref = b.g.vcycle(v, fp32=True).cpu().numpy()
     assert not np.array_equal(first, second)
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("p", (1, 2))
+def test_tcv_of_params_autograd(p):
+    """theta = (Gc, E, p) -> TCV through torch.autograd: the forward solves the
+    load step (Alg. 2) at theta, the backward returns the adjoint gradient
+    (bitwise the one of adjoint_tcv_gradient at the same state, which the
+    oracle pins), scaled by the incoming gradient; in the linear-elastic
+    regime of the Sneddon test u scales with p / E, so dTCV/dp ~ TCV / p and
+    dTCV/dE ~ -TCV / E, and a central difference in p agrees."""
+    import torch
+    from paper_2404_03265_amd import SolverParams
+    from paper_2404_03265_amd.autograd import TcvOfParams, adjoint_tcv_gradient, solve_load_step
+    m = MESHES["tiny"]
+    print(f"[case] TcvOfParams tiny p={p}", flush=True)
+    sp_ = SolverParams(gmres_rtol=1e-13, gmres_atol=1e-15)
+    c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="rule",
+             solver_params=sp_, build_oracle=False)
+    ux, uy, phi = inputs.sneddon_state(c.X, c.Y, c.M, p, random=False)
+    U0 = c.dev(np.concatenate([ux, uy, phi]))
+    ph = c.dev(phi)
+    th0 = [c.prm.Gc, c.prm.E, c.prm.pressure]
+    theta = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
+    tcv = TcvOfParams.apply(theta, c.g, U0, ph, ph)
+    (2.0 * tcv).backward()
+    U = U0.clone()
+    act, _ = solve_load_step(c.g, U, ph, ph, tol=1e-10)
+    tcv_ref, grad_ref, _, _ = adjoint_tcv_gradient(c.g, U, ph, ph, act)
+    assert tcv.item() == tcv_ref
+    assert torch.equal(theta.grad, 2.0 * grad_ref)
+    T = tcv.item()
+    g = theta.grad.numpy() / 2.0
+    assert abs(g[2] - T / th0[2]) <= 1e-2 * T / th0[2]
+    assert abs(g[1] + T / th0[1]) <= 1e-2 * T / th0[1]
+    h = 1e-3 * th0[2]
+    vals = []
+    for s in (1.0, -1.0):
+        t = torch.tensor([th0[0], th0[1], th0[2] + s * h], dtype=torch.float64)
+        vals.append(TcvOfParams.apply(t, c.g, U0, ph, ph).item())
+    fd = (vals[0] - vals[1]) / (2 * h)
+    print(f"dTCV/dp adjoint {g[2]:.8e} central difference {fd:.8e} TCV/p {T / th0[2]:.8e}", flush=True)
+    assert abs(fd - g[2]) <= 1e-4 * abs(g[2])
