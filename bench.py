@@ -146,12 +146,16 @@ def main():
     ap.add_argument("--tile", type=int, nargs=2, default=(0, 0),
                     help="owned cells per tile (x, y); 0 0 = library default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--scenario", choices=("none", "diff", "quasistatic"), default="none",
+    ap.add_argument("--scenario", choices=("none", "diff", "quasistatic", "table2"), default="none",
                     help="diff: 16-vector vmult / vmult_T batch and the adjoint crack-volume gradient "
                          "checked by central differences (use with sneddon_512x512_L3_Q2); "
                          "quasistatic: pressure increments p = 1e-3 k with the active set carried, "
-                         "FP32 V-cycle, adjoint at the last step (use with sneddon_2048x2048_L4_Q2)")
+                         "FP32 V-cycle, adjoint at the last step (use with sneddon_2048x2048_L4_Q2); "
+                         "table2: the paper's mesh family (Q1, 40 x 40 base, 0-8 local levels), one "
+                         "load step each")
     ap.add_argument("--increments", type=int, default=10)
+    ap.add_argument("--table2-kappa", default="1e-10", help="table2: a value, or 'paper' for 1e-12 h")
+    ap.add_argument("--table2-local-max", type=int, default=8)
     ap.add_argument("--extrapolate", action="store_true",
                     help="quasistatic: phi~ extrapolated from the last two load steps (from the third increment)")
     ap.add_argument("--no-newton", action="store_true")
@@ -184,7 +188,8 @@ def main():
     sp_ = SolverParams(E=spec.E, nu=spec.nu, Gc=spec.Gc, pressure=spec.pressure, kappa=spec.kappa,
                        ell=spec.ell)
     t0 = time.time()
-    g = PhaseFieldSolver(spec.n_base, spec.n_local, spec.degree, tile=tuple(args.tile), params=sp_)
+    g = PhaseFieldSolver(spec.n_base, spec.n_local, spec.degree, coarse=spec.coarse, band=spec.band,
+                         tile=tuple(args.tile), params=sp_)
     n_tiles, n_rec, _ = g.tile_stats()
     log(f"{spec.name}: {3 * g.n} unknowns, {g.n_levels} levels, {n_tiles} tiles, "
         f"built in {time.time() - t0:.1f}s")
@@ -351,6 +356,8 @@ def main():
         out["scenario"] = scenario_diff(g, spec, sp_, log)
     elif args.scenario == "quasistatic":
         out["scenario"] = scenario_quasistatic(g, spec, sp_, args.increments, log, args.extrapolate)
+    elif args.scenario == "table2":
+        out["scenario"] = scenario_table2(log, args.table2_local_max, args.table2_kappa)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb = cpu_baseline()
@@ -488,6 +495,58 @@ def scenario_quasistatic(g, spec, sp_, increments, log, extrapolate=False):
             "increments": steps, "total_seconds": total,
             "adjoint_seconds": t_adj, "adjoint_gmres_iterations": ginfo["iterations"],
             "grad_Gc_E_p": [float(x) for x in grad.tolist()]}
+
+
+def scenario_table2(log, local_max=8, kappa="1e-10"):
+    """The Sneddon test on the paper's mesh family (Sec. 4, Tables 1 and 2): Q1
+    on a 40 x 40 base mesh (a 10 x 10 coarse grid with 2 global refinements)
+    and 0..local_max local refinements of the cells with centres in |x| < 3,
+    |y| < 1 (unknown counts within 10 % of Table 2's); l = 2h with h the
+    finest cell diagonal, p = 1e-3, Newton tolerance 1e-7 (Table 1); kappa =
+    1e-10 (the workloads' value) or, with kappa="paper", 1e-12 h (Table 1).
+    Per mesh, one load step from its start in the FP64 configuration (at most
+    100 Newton steps): unknowns, TCV error against Sneddon's value, Newton
+    steps, mean and largest GMRES iterations per Newton step, GPU wall time."""
+    import math
+
+    import torch
+
+    import inputs
+    from paper_2404_03265_amd import PhaseFieldSolver, SolverParams
+    from paper_2404_03265_amd.autograd import solve_load_step
+    rows = []
+    for L in range(local_max + 1):
+        base = inputs.WorkloadSpec(name="", n_base=40, n_local=L, degree=1)
+        h = math.sqrt(2.0) * base.finest_edge
+        kap = 1e-12 * h if kappa == "paper" else float(kappa)
+        spec = inputs.WorkloadSpec(name=f"sneddon_40x40_L{L}_Q1", n_base=40, n_local=L, degree=1,
+                                   kappa=kap, coarse=10, band=(3.0, 1.0))
+        sp = SolverParams(E=spec.E, nu=spec.nu, Gc=spec.Gc, pressure=spec.pressure, kappa=spec.kappa,
+                          ell=spec.ell)
+        g = PhaseFieldSolver(spec.n_base, spec.n_local, spec.degree, coarse=spec.coarse, band=spec.band, params=sp)
+        U, phi0, _, _ = make_state(g, spec, random=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        def progress(j, info, L=L):
+            if j % 10 == 0:
+                log(f"  table2 L={L}: {j} Newton steps, |R~| {info['residual_before']:.2e}, "
+                    f"GMRES {info['gmres_iterations']}")
+        act, infos = solve_load_step(g, U, phi0, phi0, tol=1e-7, max_steps=100, progress=progress)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tcv = g.tcv(U)
+        gm = [i["gmres_iterations"] for i in infos]
+        ref = tcv_sneddon(spec)
+        row = {"local_levels": L, "h": h, "kappa": kap, "unknowns": 3 * g.n, "tcv": tcv,
+               "tcv_error": abs(tcv - ref) / ref, "newton_steps": len(infos),
+               "converged": bool(infos[-1]["active_changed"] == 0 and infos[-1]["residual_before"] <= 1e-7),
+               "mean_gmres": sum(gm) / len(gm), "max_gmres": max(gm), "seconds": dt}
+        rows.append(row)
+        log(f"table2 L={L}: h {h:.4f}, {row['unknowns']} unknowns, TCV error {100 * row['tcv_error']:.2f} %, "
+            f"{len(infos)} Newton steps, GMRES mean {row['mean_gmres']:.2f} max {row['max_gmres']}, {dt:.2f} s")
+        g.close()
+        del g
+    return {"name": "table2", "kappa": kappa, "rows": rows}
 
 
 if __name__ == "__main__":

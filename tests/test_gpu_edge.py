@@ -1,7 +1,7 @@
 """GPU parity at the degenerate ends of the method and at the largest size.
 
 * a uniform mesh (no local refinement: no hanging nodes, no refinement edge,
-  global levels only);
+  global levels only), and the paper's 40 x 40 mesh family;
 * every phase-field unknown in the active set (the phi block of J~ is the
   identity, the phi block of every level is fixed: its eigenvalue estimate
   has no free unknown);
@@ -50,6 +50,18 @@ def test_uniform_mesh(p):
     assert not np.any(c.om.hanging)
     c.load_state(setup_mg=True)
     assert c.g.n_levels == 3
+    _check_operators(c)
+
+
+@pytest.mark.parametrize("p", (1, 2))
+def test_paper_mesh_family(p):
+    """The paper's mesh family (Sec. 4, Table 2): a 40 x 40 base mesh from a
+    10 x 10 coarse grid (tiles cut raggedly), two local levels: vmult, vmult_T
+    and both V-cycles against the oracle."""
+    print(f"[case] 40 x 40 + 2 p={p}", flush=True)
+    c = Case(40, 2, p, coarse=10, band=(3.0, 1.0), mask="bernoulli", u_std=1e-2, phit="shifted")
+    c.load_state(setup_mg=True)
+    assert c.g.n_levels == 5
     _check_operators(c)
 
 

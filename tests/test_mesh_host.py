@@ -15,6 +15,8 @@ CASES = [
     dict(n_base=16, n_local=2, coarse=4, band=(3.0, 1.0)),
     dict(n_base=32, n_local=2, coarse=16, band=(2.0, 0.5)),
     dict(n_base=32, n_local=3, coarse=8, band=(2.0, 0.5)),
+    dict(n_base=32, n_local=0, coarse=8, band=(2.0, 0.5)),     # uniform
+    dict(n_base=40, n_local=2, coarse=10, band=(3.0, 1.0)),    # the paper's mesh family
 ]
 
 
