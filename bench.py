@@ -161,8 +161,8 @@ def main():
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--no-load-step", action="store_true",
                     help="time the Newton steps only, not the whole load step (for profiler runs)")
-    ap.add_argument("--newton-modes", default="fp64,mixed",
-                    help="comma-separated subset of fp64,mixed")
+    ap.add_argument("--newton-modes", default="fp64,mixed,mixed_cheb3",
+                    help="comma-separated subset of fp64,mixed,mixed_cheb3")
     ap.add_argument("--profile-pass", action="store_true",
                     help="only a few vmults and one plain device copy of the same vector "
                          "(for hardware counter runs)")
@@ -236,8 +236,11 @@ def main():
         # FP64: Chebyshev degree 3 smoothing and coarse Chebyshev; mixed: the
         # whole V-cycle in FP32 with Chebyshev degree 4 and a coarse CG (30
         # steps); residual, GMRES and line search stay FP64 in both
+        # "mixed_cheb3": the FP32 V-cycle with the FP64 configuration's smoother
+        # and coarse solve, isolating the effect of the precision
         modes = {"fp64": dict(vcycle_fp32=0, cheb_degree=3, coarse_mode=0, coarse_its=30),
-                 "mixed": dict(vcycle_fp32=1, cheb_degree=4, coarse_mode=1, coarse_its=30)}
+                 "mixed": dict(vcycle_fp32=1, cheb_degree=4, coarse_mode=1, coarse_its=30),
+                 "mixed_cheb3": dict(vcycle_fp32=1, cheb_degree=3, coarse_mode=0, coarse_its=30)}
         modes = {k: v for k, v in modes.items() if k in args.newton_modes.split(",")}
         U_ref = None
         tcv_ref = None
