@@ -369,6 +369,25 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def solve_frozen(solver, U, phi_old, phi_tilde, active, tol=1e-10, max_steps=20):
+    """Newton iterations with the active set held fixed (phi = phi_old on it):
+    residual, GMRES with the V-cycle, hanging distribution; the re-solves of
+    the finite-difference check of the adjoint. U is updated in place;
+    returns the final masked residual norm."""
+    import torch
+    for _ in range(max_steps):
+        solver.set_state(U, phi_old, phi_tilde, active, setup_mg=True)
+        R = solver.residual(U, masked=True)
+        r = float(torch.linalg.norm(R))
+        if r <= tol:
+            return r
+        dU, info, rc = solver.gmres(R, tol=max(1e-3 * r, 1e-2 * tol))
+        solver.distribute(dU, 3)
+        U += dU
+    solver.set_state(U, phi_old, phi_tilde, active, setup_mg=False)
+    return float(torch.linalg.norm(solver.residual(U, masked=True)))
+
+
 def scenario_diff(g, spec, sp_, log):
     """Differentiation form: a converged load step, 16 seeded vectors through
     vmult and vmult_T (batched), the adjoint gradient of TCV with respect to
@@ -378,7 +397,7 @@ def scenario_diff(g, spec, sp_, log):
     import torch
 
     import inputs
-    from paper_2404_03265_amd.autograd import adjoint_tcv_gradient, solve_frozen, solve_load_step
+    from paper_2404_03265_amd.autograd import adjoint_tcv_gradient, solve_load_step
     X, Y = g.coords()
     U, phi0, _, _ = make_state(g, spec, random=False)
     for k, v in dict(vcycle_fp32=0, cheb_degree=3, coarse_mode=0, coarse_its=30,

@@ -80,23 +80,6 @@ def solve_load_path(solver, U, phi0, pressures, extrapolate=False, tol=1e-7, max
     return active, out
 
 
-def solve_frozen(solver, U, phi_old, phi_tilde, active, tol=1e-10, max_steps=20):
-    """Newton iterations with the active set held fixed (phi = phi_old on it):
-    residual, GMRES with the V-cycle, hanging distribution. U is updated in
-    place; returns the final masked residual norm."""
-    for _ in range(max_steps):
-        solver.set_state(U, phi_old, phi_tilde, active, setup_mg=True)
-        R = solver.residual(U, masked=True)
-        r = float(torch.linalg.norm(R))
-        if r <= tol:
-            return r
-        dU, info, rc = solver.gmres(R, tol=max(1e-3 * r, 1e-2 * tol))
-        solver.distribute(dU, 3)
-        U += dU
-    solver.set_state(U, phi_old, phi_tilde, active, setup_mg=False)
-    return float(torch.linalg.norm(solver.residual(U, masked=True)))
-
-
 def adjoint_tcv_gradient(solver, U, phi_old, phi_tilde, active, tol=0.0):
     """(TCV, dTCV/d(Gc, E, p)) at U with the active set frozen."""
     solver.set_state(U, phi_old, phi_tilde, active, setup_mg=True)
