@@ -695,12 +695,15 @@ struct pff_ctx {
     const int L = int(lv.size()) - 1;
     const int k = prm.cheb_degree;
     std::vector<int> xi(L + 1, 0);
+    LevelCopyArgs<T> ca{};
+    ca.nlev = L + 1;
     for (int l = 0; l <= L; ++l) {
-      DevLevel& D = lv[l];
-      LevelWork<T>& w = work<T>(D);
-      hipLaunchKernelGGL((k_copy_to_level<T>), dim3(grid_for(D.n)), dim3(256), 0, s, w.d, D.n, D.flags,
-                         D.leaf_index, src, flags, n);
+      ca.start[l + 1] = ca.start[l] + lv[l].n;
+      ca.vec[l] = work<T>(lv[l]).d;
+      ca.fl[l] = lv[l].flags;
+      ca.leaf_index[l] = lv[l].leaf_index;
     }
+    hipLaunchKernelGGL((k_copy_to_levels<T>), dim3(grid_for(ca.start[L + 1])), dim3(256), 0, s, ca, src, flags, n);
     for (int l = L; l >= 1; --l) {
       DevLevel& D = lv[l];
       LevelWork<T>& w = work<T>(D);
@@ -729,12 +732,9 @@ struct pff_ctx {
                          lv[l - 1].n, D.P_width, D.P_ell, D.P_wtab, D.flags);
       xi[l] = chebyshev<T>(l, w.d, xi[l], k);
     }
-    for (int l = 0; l <= L; ++l) {
-      DevLevel& D = lv[l];
-      LevelWork<T>& w = work<T>(D);
-      hipLaunchKernelGGL((k_copy_from_level<T>), dim3(grid_for(D.n)), dim3(256), 0, s, dst, w.x[xi[l]], D.n,
-                         D.flags, D.leaf_index, src, flags, n);
-    }
+    for (int l = 0; l <= L; ++l) ca.vec[l] = work<T>(lv[l]).x[xi[l]];
+    hipLaunchKernelGGL((k_copy_from_levels<T>), dim3(grid_for(ca.start[L + 1])), dim3(256), 0, s, dst, ca, src, flags,
+                       n);
     if (n_hang)
       hipLaunchKernelGGL(k_copy_hanging, dim3(grid_for(3 * n_hang)), dim3(256), 0, s, dst, src, n, hang, n_hang);
     HIPCHK(hipGetLastError());
@@ -1086,7 +1086,7 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
       msg = c->mesh.error;
       return PFF_E_MESH;
     }
-    if (c->mesh.n_levels > 16) return PFF_E_ARG;
+    if (c->mesh.n_levels > COPY_MAX_LEVELS) return PFF_E_ARG;
     for (const Level& L : c->mesh.levels)
       if (L.tiles.max_local > 65535) return PFF_E_MESH;
     if (c->mesh.tiles.max_local > 65535) return PFF_E_MESH;

@@ -197,36 +197,62 @@ __global__ void k_level_active(uint8_t* fl, int64_t nl, const int32_t* leaf_inde
   }
 }
 
-// leaf -> level: every free non-hanging leaf unknown goes to the coarsest
-// level whose leaf cells own it (the level nodes flagged NODE_COPY)
+// The leaf <-> level copies of every level in one launch: the threads walk
+// the concatenated level node ranges, start[l] .. start[l + 1] being level l.
+// Every free non-hanging leaf unknown belongs to the one level whose leaf
+// cells own it (the level nodes flagged NODE_COPY).
+constexpr int COPY_MAX_LEVELS = 16;
+
 template <typename T>
-__global__ void k_copy_to_level(T* d, int64_t nl, const uint8_t* fl, const int32_t* leaf_index,
-                                const double* b, const uint8_t* leaf_flags, int64_t n) {
-  GRID_LOOP(k, nl) {
+struct LevelCopyArgs {
+  int nlev;
+  int64_t start[COPY_MAX_LEVELS + 1];
+  T* vec[COPY_MAX_LEVELS];                  // level vector (3 x n_l) written or read
+  const uint8_t* fl[COPY_MAX_LEVELS];       // level node flags
+  const int32_t* leaf_index[COPY_MAX_LEVELS];
+};
+
+template <typename T>
+__device__ __forceinline__ int copy_level_of(const LevelCopyArgs<T>& a, int64_t t) {
+  int l = 0;
+  while (l + 1 < a.nlev && t >= a.start[l + 1]) ++l;
+  return l;
+}
+
+// level vectors = the leaf values of their copy targets (zero elsewhere and on
+// constrained leaf rows)
+template <typename T>
+__global__ void k_copy_to_levels(const LevelCopyArgs<T> a, const double* b, const uint8_t* leaf_flags, int64_t n) {
+  GRID_LOOP(t, a.start[a.nlev]) {
+    const int l = copy_level_of(a, t);
+    const int64_t k = t - a.start[l], nl = a.start[l + 1] - a.start[l];
     T v[3] = {T(0), T(0), T(0)};
-    if (fl[k] & NODE_COPY) {
-      const int64_t g = leaf_index[k];
+    if (a.fl[l][k] & NODE_COPY) {
+      const int64_t g = a.leaf_index[l][k];
       const uint8_t lf = leaf_flags[g];
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         if (!leaf_constrained(lf, c)) v[c] = T(b[c * n + g]);
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) d[c * nl + k] = v[c];
+    for (int c = 0; c < 3; ++c) a.vec[l][c * nl + k] = v[c];
   }
 }
 
+// leaf rows = the value of their copy level (the input on constrained rows);
+// every leaf node is the copy target of one level at most
 template <typename T>
-__global__ void k_copy_from_level(double* out, const T* x, int64_t nl, const uint8_t* fl,
-                                  const int32_t* leaf_index, const double* b, const uint8_t* leaf_flags,
-                                  int64_t n) {
-  GRID_LOOP(k, nl) {
-    if (fl[k] & NODE_COPY) {
-      const int64_t g = leaf_index[k];
+__global__ void k_copy_from_levels(double* out, const LevelCopyArgs<T> a, const double* b, const uint8_t* leaf_flags,
+                                   int64_t n) {
+  GRID_LOOP(t, a.start[a.nlev]) {
+    const int l = copy_level_of(a, t);
+    const int64_t k = t - a.start[l], nl = a.start[l + 1] - a.start[l];
+    if (a.fl[l][k] & NODE_COPY) {
+      const int64_t g = a.leaf_index[l][k];
       const uint8_t lf = leaf_flags[g];
 #pragma unroll
       for (int c = 0; c < 3; ++c)
-        out[c * n + g] = leaf_constrained(lf, c) ? b[c * n + g] : double(x[c * nl + k]);
+        out[c * n + g] = leaf_constrained(lf, c) ? b[c * n + g] : double(a.vec[l][c * nl + k]);
     }
   }
 }
