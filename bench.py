@@ -332,7 +332,9 @@ def main():
         ms_step = ms_vmult
 
     out = {
-        "metric": "GDoF/s of matrix-free Jacobian vmult",
+        # value: the first quantity (vmult GDoF/s); the second (seconds per
+        # Newton solve, FP64 against mixed precision) is in "load_step"
+        "metric": "GDoF/s of matrix-free Jacobian vmult; s per Newton solve, FP64 vs mixed",
         "value": gdofs,
         "unit": "GDoF/s",
         "n_gpus": 1,
