@@ -690,6 +690,37 @@ struct pff_ctx {
     return 0;
   }
 
+  // transfers of level D (to and from level D - 1) with the row width as a
+  // compile-time constant for the widths of Q1 and Q2 (4 and 9 for P,
+  // 9 and 25 for P^T)
+  template <typename T>
+  void prolong_add(T* xf, const T* xc, int64_t nc, const DevLevel& D) {
+    const dim3 g(grid_for(D.n)), b(256);
+    switch (D.P_width) {
+      case 4: hipLaunchKernelGGL((k_prolong_add<T, 4>), g, b, 0, s, xf, xc, D.n, nc, 4, D.P_ell, D.P_wtab, D.flags); break;
+      case 9: hipLaunchKernelGGL((k_prolong_add<T, 9>), g, b, 0, s, xf, xc, D.n, nc, 9, D.P_ell, D.P_wtab, D.flags); break;
+      default:
+        hipLaunchKernelGGL((k_prolong_add<T, 0>), g, b, 0, s, xf, xc, D.n, nc, D.P_width, D.P_ell, D.P_wtab, D.flags);
+    }
+  }
+  template <typename T>
+  void restrict_add(T* dc, const T* tf, int64_t nc, const DevLevel& D) {
+    const dim3 g(grid_for(D.PT_nrows)), b(256);
+    switch (D.PT_width) {
+      case 9:
+        hipLaunchKernelGGL((k_restrict_add<T, 9>), g, b, 0, s, dc, tf, nc, D.n, D.PT_nrows, D.PT_rows, 9, D.PT_ell,
+                           D.P_wtab);
+        break;
+      case 25:
+        hipLaunchKernelGGL((k_restrict_add<T, 25>), g, b, 0, s, dc, tf, nc, D.n, D.PT_nrows, D.PT_rows, 25, D.PT_ell,
+                           D.P_wtab);
+        break;
+      default:
+        hipLaunchKernelGGL((k_restrict_add<T, 0>), g, b, 0, s, dc, tf, nc, D.n, D.PT_nrows, D.PT_rows, D.PT_width,
+                           D.PT_ell, D.P_wtab);
+    }
+  }
+
   template <typename T>
   void vcycle_impl(double* dst, const double* src) {
     const int L = int(lv.size()) - 1;
@@ -714,8 +745,7 @@ struct pff_ctx {
       DevLevel& C = lv[l - 1];
       LevelWork<T>& wc = work<T>(C);
       if (D.PT_nrows > 0)
-        hipLaunchKernelGGL((k_restrict_add<T>), dim3(grid_for(D.PT_nrows)), dim3(256), 0, s, wc.d, t, C.n, D.n,
-                           D.PT_nrows, D.PT_rows, D.PT_width, D.PT_ell, D.P_wtab);
+        restrict_add<T>(wc.d, t, C.n, D);
     }
     {
       LevelWork<T>& w0 = work<T>(lv[0]);
@@ -728,8 +758,7 @@ struct pff_ctx {
       DevLevel& D = lv[l];
       LevelWork<T>& w = work<T>(D);
       LevelWork<T>& wc = work<T>(lv[l - 1]);
-      hipLaunchKernelGGL((k_prolong_add<T>), dim3(grid_for(D.n)), dim3(256), 0, s, w.x[xi[l]], wc.x[xi[l - 1]], D.n,
-                         lv[l - 1].n, D.P_width, D.P_ell, D.P_wtab, D.flags);
+      prolong_add<T>(w.x[xi[l]], wc.x[xi[l - 1]], lv[l - 1].n, D);
       xi[l] = chebyshev<T>(l, w.d, xi[l], k);
     }
     for (int l = 0; l <= L; ++l) ca.vec[l] = work<T>(lv[l]).x[xi[l]];

@@ -272,23 +272,47 @@ __device__ __forceinline__ void load_weight_table(float* W, const float* wtab) {
   __syncthreads();
 }
 
+// s_c += sum over the entries e of ELL row r of weight_e * x[c * nx + col_e]
+// (c = 0, 1, 2). WIDTH > 0: the row width is known at compile time and every
+// entry of the row is requested before the first gather (padding entries
+// have weight 0 and column 0); WIDTH == 0: runtime width.
+template <typename T, int WIDTH>
+__device__ __forceinline__ void ell_row3(const uint32_t* E, int64_t stride, int64_t r, int width, const float* W,
+                                         const T* x, int64_t nx, T& s0, T& s1, T& s2) {
+  if constexpr (WIDTH > 0) {
+    uint32_t t[WIDTH];
+#pragma unroll
+    for (int e = 0; e < WIDTH; ++e) t[e] = E[int64_t(e) * stride + r];
+#pragma unroll
+    for (int e = 0; e < WIDTH; ++e) {
+      const int64_t col = t[e] & TRANSFER_COL_MASK;
+      const T w = T(W[t[e] >> TRANSFER_COL_BITS]);
+      s0 += w * x[col];
+      s1 += w * x[nx + col];
+      s2 += w * x[2 * nx + col];
+    }
+  } else {
+    for (int e = 0; e < width; ++e) {
+      const uint32_t t = E[int64_t(e) * stride + r];
+      const int64_t col = t & TRANSFER_COL_MASK;
+      const T w = T(W[t >> TRANSFER_COL_BITS]);
+      s0 += w * x[col];
+      s1 += w * x[nx + col];
+      s2 += w * x[2 * nx + col];
+    }
+  }
+}
+
 // x_f += P x_c on unknowns the fine level does not hold at zero
 // (Dirichlet for u, active for phi)
-template <typename T>
+template <typename T, int WIDTH>
 __global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, int width, const uint32_t* E,
                               const float* wtab, const uint8_t* ff) {
   __shared__ float W[TRANSFER_WEIGHTS];
   load_weight_table(W, wtab);
   GRID_LOOP(i, nf) {
     T s0 = T(0), s1 = T(0), s2 = T(0);
-    for (int e = 0; e < width; ++e) {
-      const uint32_t t = E[int64_t(e) * nf + i];
-      const int64_t col = t & TRANSFER_COL_MASK;
-      const T w = T(W[t >> TRANSFER_COL_BITS]);
-      s0 += w * xc[col];
-      s1 += w * xc[nc + col];
-      s2 += w * xc[2 * nc + col];
-    }
+    ell_row3<T, WIDTH>(E, nf, i, width, W, xc, nc, s0, s1, s2);
     const uint8_t f = ff[i];
     if (!(f & NODE_DIRICHLET)) {
       xf[i] += s0;
@@ -299,21 +323,14 @@ __global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, int wi
 }
 
 // d_c += P^T t_f over the coarse rows that receive fine contributions
-template <typename T>
+template <typename T, int WIDTH>
 __global__ void k_restrict_add(T* dc, const T* tf, int64_t nc, int64_t nf, int64_t nrows, const int32_t* rows,
                                int width, const uint32_t* E, const float* wtab) {
   __shared__ float W[TRANSFER_WEIGHTS];
   load_weight_table(W, wtab);
   GRID_LOOP(r, nrows) {
     T s0 = T(0), s1 = T(0), s2 = T(0);
-    for (int e = 0; e < width; ++e) {
-      const uint32_t t = E[int64_t(e) * nrows + r];
-      const int64_t col = t & TRANSFER_COL_MASK;
-      const T w = T(W[t >> TRANSFER_COL_BITS]);
-      s0 += w * tf[col];
-      s1 += w * tf[nf + col];
-      s2 += w * tf[2 * nf + col];
-    }
+    ell_row3<T, WIDTH>(E, nrows, r, width, W, tf, nf, s0, s1, s2);
     const int64_t i = rows[r];
     dc[i] += s0;
     dc[nc + i] += s1;
