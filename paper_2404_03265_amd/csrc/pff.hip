@@ -477,7 +477,7 @@ struct pff_ctx {
 
   template <typename T>
   void level_apply(int l, const T* x, T* dst, int epi, const T* b, const T* dold, T* xnew, const T c1[2],
-                   const T c2[2]) {
+                   const T c2[2], const T* c0 = nullptr) {
     DevLevel& L = lv[l];
     LevelWork<T>& w = work<T>(L);
     TileArgs<T> a{};
@@ -490,9 +490,14 @@ struct pff_ctx {
     a.dold = dold;
     a.dinv = w.dinv;
     a.xnew = xnew;
-    for (int i = 0; i < 2; ++i) { a.c1[i] = c1 ? c1[i] : T(0); a.c2[i] = c2 ? c2[i] : T(0); }
+    for (int i = 0; i < 2; ++i) {
+      a.c1[i] = c1 ? c1[i] : T(0);
+      a.c2[i] = c2 ? c2[i] : T(0);
+      a.c0[i] = c0 ? c0[i] : T(0);
+    }
     if (epi == EPI_PLAIN) launch_tile<T, MODE_LEVEL, EPI_PLAIN>(L.tiles, L.flags, L.n, a);
     else if (epi == EPI_RESID) launch_tile<T, MODE_LEVEL, EPI_RESID>(L.tiles, L.flags, L.n, a);
+    else if (epi == EPI_CHEB_FIRST) launch_tile<T, MODE_LEVEL, EPI_CHEB_FIRST>(L.tiles, L.flags, L.n, a);
     else launch_tile<T, MODE_LEVEL, EPI_CHEB>(L.tiles, L.flags, L.n, a);
   }
 
@@ -538,9 +543,23 @@ struct pff_ctx {
       rho_prev[k] = delta[k] / theta[k];
     }
     const int64_t nl = L.n;
-    int xi, di = 0;
+    int xi, di = 0, j0 = 1;
     T c1[2], c2[2];
-    if (x_in_idx < 0) {
+    if (x_in_idx < 0 && degree >= 2) {
+      // first update (d_0 = D^-1 b / theta, x_1 = d_0) and the second in one
+      // pass: d_0 is formed inside the level kernel
+      const T c0[2] = {T(1.0 / theta[0]), T(1.0 / theta[1])};
+      for (int k = 0; k < 2; ++k) {
+        const double rho = 1.0 / (2.0 * theta[k] / delta[k] - rho_prev[k]);
+        c1[k] = T(rho * rho_prev[k]);
+        c2[k] = T(2.0 * rho / delta[k]);
+        rho_prev[k] = rho;
+      }
+      level_apply<T>(l, nullptr, w.dir[1], EPI_CHEB_FIRST, b, nullptr, w.x[1], c1, c2, c0);
+      xi = 1;
+      di = 1;
+      j0 = 2;
+    } else if (x_in_idx < 0) {
       xi = 0;
       hipLaunchKernelGGL((k_cheb_first<T>), dim3(grid_for(3 * nl)), dim3(256), 0, s, w.x[0], w.dir[0], b, w.dinv,
                          nl, T(1.0 / theta[0]), T(1.0 / theta[1]));
@@ -550,7 +569,7 @@ struct pff_ctx {
       level_apply<T>(l, w.x[xi], w.dir[0], EPI_CHEB, b, nullptr, w.x[1 - xi], c1, c2);
       xi = 1 - xi;
     }
-    for (int j = 1; j < degree; ++j) {
+    for (int j = j0; j < degree; ++j) {
       for (int k = 0; k < 2; ++k) {
         const double rho = 1.0 / (2.0 * theta[k] / delta[k] - rho_prev[k]);
         c1[k] = T(rho * rho_prev[k]);

@@ -38,7 +38,10 @@ enum Mode : int {
   MODE_MASS,       // lumped phase-field mass (row sums)
 };
 
-enum Epi : int { EPI_PLAIN = 0, EPI_RESID = 1, EPI_CHEB = 2 };
+// EPI_CHEB_FIRST: the first two Chebyshev updates from x = 0 in one pass: the
+// operand x = d_0 = c0 D^-1 b is formed while staging (never stored), then the
+// EPI_CHEB update with d_old = d_0.
+enum Epi : int { EPI_PLAIN = 0, EPI_RESID = 1, EPI_CHEB = 2, EPI_CHEB_FIRST = 3 };
 
 template <typename T>
 struct TileArgs {
@@ -76,6 +79,7 @@ struct TileArgs {
   const T* dinv;     // inverse diagonal
   T* xnew;
   T c1[2], c2[2];    // Chebyshev coefficients per block (u, phi)
+  T c0[2];           // EPI_CHEB_FIRST: coefficient of the first update d_0 = c0 D^-1 b
 };
 
 template <int MODE>
@@ -117,13 +121,19 @@ __device__ __forceinline__ void node_epilogue(const TileArgs<T>& a, int c, int64
     } else {
       const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
       const int blk = c < 2 ? 0 : 1;
-      const T x = a.src[i];
+      T x, dp;
+      if constexpr (EPI == EPI_CHEB_FIRST) {
+        x = a.c0[blk] * a.dinv[i] * a.b[i];
+        dp = x;
+      } else {
+        x = a.src[i];
+        dp = a.dold ? a.dold[i] : T(0);
+      }
       if (fixed) {
         a.dst[i] = T(0);
         a.xnew[i] = x;
       } else {
         const T r = a.b[i] - v;
-        const T dp = a.dold ? a.dold[i] : T(0);
         const T dn = a.c1[blk] * dp + a.c2[blk] * a.dinv[i] * r;
         a.dst[i] = dn;
         a.xnew[i] = x + dn;
@@ -330,8 +340,9 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   // and residual, b, D^-1 and the previous update, requested here with the
   // node loads so that the epilogue issues no dependent load. The Jacobian
   // modes otherwise write their identity rows while staging.
-  constexpr bool LPRE = MODE == MODE_LEVEL && (EPI == EPI_CHEB || EPI == EPI_RESID);
-  constexpr bool CHEB = MODE == MODE_LEVEL && EPI == EPI_CHEB;
+  constexpr bool FIRST = MODE == MODE_LEVEL && EPI == EPI_CHEB_FIRST;
+  constexpr bool CHEB = MODE == MODE_LEVEL && (EPI == EPI_CHEB || FIRST);
+  constexpr bool LPRE = CHEB || (MODE == MODE_LEVEL && EPI == EPI_RESID);
   constexpr int NPRE = (JMODE || LPRE) ? SP : 1;
   const bool keep_raw = (JMODE || LPRE) && no <= SP * bs;
   T raw[NPRE][3], pb[LPRE ? SP : 1][3], pdi[CHEB ? SP : 1][3], pdo[CHEB ? SP : 1][3];
@@ -344,7 +355,8 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         pb[k][c] = a.b[c * n + g];
         if constexpr (CHEB) {
           pdi[k][c] = a.dinv[c * n + g];
-          pdo[k][c] = a.dold ? a.dold[c * n + g] : T(0);
+          if constexpr (FIRST) pdo[k][c] = a.c0[c < 2 ? 0 : 1] * pdi[k][c] * pb[k][c];
+          else pdo[k][c] = a.dold ? a.dold[c * n + g] : T(0);
         }
       }
     }
@@ -377,7 +389,10 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       const int64_t g = min(int64_t(o0) + min(l, max(no - 1, 0)), n - 1);
       fp_[k] = a.flags[g];
       if constexpr (NF > 0) {
-        if constexpr (TR::n_src > 0) {
+        if constexpr (FIRST) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) vp[k][c] = a.c0[c < 2 ? 0 : 1] * a.dinv[c * n + g] * a.b[c * n + g];
+        } else if constexpr (TR::n_src > 0) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) vp[k][c] = a.src[c * n + g];
         }
@@ -390,7 +405,10 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       const int64_t g = gsh[k] >= 0 ? gsh[k] : int64_t(0);
       fsh[k] = a.flags[g];
       if constexpr (NF > 0) {
-        if constexpr (TR::n_src > 0) {
+        if constexpr (FIRST) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) vsh[k][c] = a.c0[c < 2 ? 0 : 1] * a.dinv[c * n + g] * a.b[c * n + g];
+        } else if constexpr (TR::n_src > 0) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) vsh[k][c] = a.src[c * n + g];
         }
