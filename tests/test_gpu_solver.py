@@ -512,3 +512,30 @@ def test_tcv_of_params_autograd(p):
     fd = (vals[0] - vals[1]) / (2 * h)
     print(f"dTCV/dp adjoint {g[2]:.8e} central difference {fd:.8e} TCV/p {T / th0[2]:.8e}", flush=True)
     assert abs(fd - g[2]) <= 1e-4 * abs(g[2])
+
+
+@pytest.mark.parametrize("p", (1, 2))
+def test_gmres_restarts_match_oracle(p):
+    """GMRES(4) (Sec. 3.2 with a short restart, so that the solve passes
+    through several restarts): the solution matches a direct solve, and the
+    iteration count that of the oracle's GMRES(4) with the same V-cycle."""
+    from oracle.krylov import gmres
+    from paper_2404_03265_amd import SolverParams
+    m = MESHES["tiny"]
+    print(f"[case] GMRES(4) tiny p={p}", flush=True)
+    c = Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], mask="bernoulli", u_std=1e-2,
+             solver_params=SolverParams(gmres_restart=4), phit="shifted")
+    c.load_state(setup_mg=True)
+    lam_max, lam_min0 = c.g.get_eigen()
+    vc = VCycle(Hierarchy(c.om), c.prm, MGParams(), c.U_o, c.phit_o, c.active_o,
+                eigen=([lam_max[l] for l in range(c.g.n_levels)], lam_min0))
+    J = c.lp.masked_operator(c.U_o, c.phit_o, c.active_o)
+    b = inputs.random_vector(c.X, c.Y, 63) * c.to_g(c.lp.free_mask(c.active_o)).astype(float)
+    tol = 1e-11 * np.linalg.norm(b)
+    x, info, rc = c.g.gmres(c.dev(b), tol=tol)
+    assert info["converged"] == 1 and info["iterations"] > 8, info
+    xd = c.to_g(spla.spsolve(J.tocsc(), c.to_o(b)))
+    assert np.linalg.norm(x.cpu().numpy() - xd) <= 1e-8 * np.linalg.norm(xd)
+    _, oinfo = gmres(lambda v: J @ v, vc.apply, c.to_o(b), tol, restart=4, maxit=300)
+    assert oinfo.converged
+    assert abs(info["iterations"] - oinfo.iterations) <= 2, (info["iterations"], oinfo.iterations)
