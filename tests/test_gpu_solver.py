@@ -112,6 +112,19 @@ def test_vcycle_degree4_and_short_coarse(name, p):
     assert rel_err(got, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("cheb", (1, 2))
+@pytest.mark.parametrize("p", (1, 2))
+def test_vcycle_low_chebyshev_degrees(p, cheb):
+    """Chebyshev degree 1 (the first update alone, no operator application
+    from x = 0) and 2 (the first two updates in one level pass and nothing
+    after): the FP64 V-cycle against the oracle's at 1e-12."""
+    c = mg_case("tiny", p, cheb=cheb)
+    src = inputs.random_vector(c.X, c.Y, 9)
+    got = c.g.vcycle(c.dev(src)).cpu().numpy()
+    ref = c.to_g(c.vc.apply(c.to_o(src)))
+    assert rel_err(got, ref) <= 1e-12
+
+
 @pytest.mark.parametrize("name,p", CASES)
 def test_vcycle_coarse_cg(name, p):
     """Coarse solve by fixed-step Jacobi-CG (Chebyshev degree 4 smoothing, the
