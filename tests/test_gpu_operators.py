@@ -174,3 +174,27 @@ def test_tcv_and_parameter_derivatives(name, p):
         r = zo @ (d[k] * free)
         scale = np.abs(zo).sum() * np.abs(d[k]).max()
         assert abs(out[i] - r) <= 1e-13 * scale, (k, out[i], r)
+
+
+@pytest.mark.parametrize("p", (1, 2))
+def test_vector_utilities_match_oracle(p):
+    """The small entry points around the operators: hanging entries set from
+    their masters (pff_distribute) and constrained rows zeroed
+    (pff_mask_constrained) as the oracle's constraint matrix and free mask
+    give them, and the deterministic dot product (pff_dot): bitwise
+    repeatable and equal to a plain FP64 sum to rounding."""
+    c = case("tiny", p)
+    n = c.n
+    v = inputs.random_vector(c.X, c.Y, 64)
+    got = c.g.distribute(c.dev(v), 3).cpu().numpy()
+    assert rel_err(got, c.to_g(c.lp.distribute(c.to_o(v)))) <= 1e-15
+    got = c.g.mask_constrained(c.dev(v)).cpu().numpy()
+    assert np.array_equal(got, v * c.to_g(c.lp.free_mask(c.active_o)).astype(float))
+    w = inputs.random_vector(c.X, c.Y, 65)
+    d1 = c.g.dot(c.dev(v), c.dev(w))
+    d2 = c.g.dot(c.dev(v), c.dev(w))
+    assert d1 == d2
+    assert abs(d1 - float(np.dot(v, w))) <= 1e-13 * float(np.dot(np.abs(v), np.abs(w)))
+    nt, nrec, mx = c.g.tile_stats()
+    assert nt > 0 and nrec >= 1 and 0 < mx <= 256
+    assert 3 * n == v.size
