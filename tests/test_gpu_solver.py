@@ -61,6 +61,10 @@ def test_level_active_sets_and_inverse_diagonals(name, p):
         ref = c.vc.ops[l].Dinv
         ref_g = np.concatenate([ref[k * nl:(k + 1) * nl][mp] for k in range(3)])
         assert rel_err(got, ref_g) <= 1e-12, l
+        # the FP32 copy of the mixed form: the FP64 diagonal to FP32 rounding
+        # (entries of the FP32 level operator, summed in FP32)
+        got32 = c.g.inverse_diagonal(l, fp32=True).cpu().numpy().astype(np.float64)
+        assert rel_err(got32, ref_g) <= 1e-5, l
 
 
 @pytest.mark.parametrize("name,p", CASES)
