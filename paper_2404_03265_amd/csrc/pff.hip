@@ -998,15 +998,26 @@ struct pff_ctx {
         // classical Gram-Schmidt, twice: h1 = V^T vn; vn -= V h1 fused with
         // h2 = V^T vn; vn -= V h2 fused with |vn|^2
         const int k = j + 1;
-        mdot(V, k, vn, N, h1.data());
-        HIPCHK(hipMemcpyAsync(hdev, h1.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-        launch_k<McombMdotL>(k, (const double*)V, vn, (const double*)hdev, k, N, red_part);
-        reduce_to_host(k, h2.data());
-        HIPCHK(hipMemcpyAsync(hdev, h2.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_mcombine_sq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, vn, hdev, k, N,
+        // the coefficients stay on the device between the passes (h1 in
+        // red_out[0, k), h2 in red_out[64, 64 + k), |vn|^2 in red_out[128]);
+        // the host receives all three with one wait
+        double* d_h1 = red_out;
+        double* d_h2 = red_out + 64;
+        double* d_hn = red_out + 128;
+        launch_k<MdotL>(k, (const double*)V, (const double*)vn, k, N, red_part);
+        hipLaunchKernelGGL(k_reduce_final, dim3(k), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, k, d_h1);
+        launch_k<McombMdotL>(k, (const double*)V, vn, (const double*)d_h1, k, N, red_part);
+        hipLaunchKernelGGL(k_reduce_final, dim3(k), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, k, d_h2);
+        hipLaunchKernelGGL(k_mcombine_sq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, vn, d_h2, k, N,
                            red_part);
-        double hn2 = 0.0;
-        reduce_to_host(1, &hn2);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, 1, d_hn);
+        HIPCHK(hipMemcpyAsync(host_red, red_out, sizeof(double) * 129, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int i = 0; i < k; ++i) {
+          h1[i] = host_red[i];
+          h2[i] = host_red[64 + i];
+        }
+        const double hn2 = host_red[128];
         double hn = std::sqrt(hn2);
         std::vector<double> h(j + 2);
         for (int i = 0; i <= j; ++i) h[i] = h1[i] + h2[i];
