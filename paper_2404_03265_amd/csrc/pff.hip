@@ -242,6 +242,7 @@ struct pff_ctx {
   double* eig_al = nullptr;
   double* eig_be = nullptr;
   double* host_red = nullptr;   // pinned
+  double* eig_host = nullptr;   // pinned: per level 2 EIG_SC + 4 EIG_MAX_ITS doubles of estimate output
   double* V = nullptr;          // GMRES basis
   double* ccg_s = nullptr;      // coarse CG scalars
   // level-0 cells for the one-kernel coarse solve: node ids sorted by colour
@@ -795,7 +796,12 @@ struct pff_ctx {
   // Lanczos tridiagonal of its coefficients. The level operator is block
   // diagonal, so both blocks run at once (one operator application per step);
   // their scalars stay on the device and are read back once at the end.
-  void eig_estimate(int l, int its) {
+  // Eigenvalue estimate of level l, enqueued without a host wait: the CG
+  // runs `its` steps (the device scalars stop a block earlier), and its
+  // scalars and Lanczos coefficients are copied to the pinned area `out`
+  // (2 EIG_SC + 4 EIG_MAX_ITS doubles). eig_finish turns them into the
+  // extreme Ritz values once the stream has been synchronised.
+  void eig_launch(int l, int its, double* out) {
     DevLevel& L = lv[l];
     LevelWork<double>& w = w64of(L);
     const int64_t nl = L.n;
@@ -813,24 +819,9 @@ struct pff_ctx {
       dot2_async(r + off[b], r + off[b], len[b], sc + EIG_SC * b + EIG_PQ);   // n_free (scratch slot)
       dot2_async(r + off[b], z + off[b], len[b], sc + EIG_SC * b + EIG_RZ);
     }
-    double h[2 * EIG_SC];
-    HIPCHK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    // at most `its` steps and never more than the number of free unknowns;
-    // stop once r.z has dropped by 1e-24
-    int max_it = 0;
-    for (int b = 0; b < 2; ++b) {
-      double* c = h + EIG_SC * b;
-      const double n_free = c[EIG_PQ];
-      c[EIG_RZ0] = c[EIG_RZ];
-      c[EIG_MAX] = std::min<double>(its, n_free);
-      c[EIG_ACTIVE] = (c[EIG_MAX] >= 1.0 && c[EIG_RZ] > 0.0) ? 1.0 : 0.0;
-      c[EIG_STEPS] = 0.0;
-      max_it = std::max(max_it, int(c[EIG_MAX]));
-    }
-    HIPCHK(hipMemcpyAsync(sc, h, sizeof(h), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_eig_init, dim3(1), dim3(64), 0, s, sc, its);
     const int stride = EIG_MAX_ITS;
-    max_it = std::min(max_it, stride);
+    const int max_it = std::min(its, stride);
     // per step: operator, p.q partials, alpha, update fused with the r.z
     // partials, beta, direction update (both blocks in every launch)
     const int nb = std::min(RED_BLOCKS, grid_for(3 * nl));
@@ -843,19 +834,23 @@ struct pff_ctx {
       hipLaunchKernelGGL(k_eig_beta_reduce, dim3(1), dim3(RED_THREADS), 0, s, red_part, nb, sc, eig_be, stride, it);
       hipLaunchKernelGGL(k_eig_waxpy, dim3(grid_for(3 * nl)), dim3(256), 0, s, pv, z, sc, nl);
     }
-    std::vector<double> al(2 * stride), be(2 * stride);
-    HIPCHK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
-    if (max_it > 0) {
-      HIPCHK(hipMemcpyAsync(al.data(), eig_al, sizeof(double) * 2 * stride, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(be.data(), eig_be, sizeof(double) * 2 * stride, hipMemcpyDeviceToHost, s));
-    }
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpyAsync(out, sc, sizeof(double) * 2 * EIG_SC, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(out + 2 * EIG_SC, eig_al, sizeof(double) * 2 * stride, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(out + 2 * EIG_SC + 2 * stride, eig_be, sizeof(double) * 2 * stride,
+                          hipMemcpyDeviceToHost, s));
+  }
+  void eig_finish(int l, const double* in) {
+    DevLevel& L = lv[l];
+    const int stride = EIG_MAX_ITS;
+    const double* h = in;
+    const double* al = in + 2 * EIG_SC;
+    const double* be = in + 2 * EIG_SC + 2 * stride;
     for (int b = 0; b < 2; ++b) {
       const int m = int(h[EIG_SC * b + EIG_STEPS]);
       double lo = 1.0, hi = 1.0;
       if (m > 0) {
-        const double* A = al.data() + b * stride;
-        const double* B = be.data() + b * stride;
+        const double* A = al + b * stride;
+        const double* B = be + b * stride;
         std::vector<double> dg(m), of(m > 1 ? m - 1 : 0);
         for (int j = 0; j < m; ++j) dg[j] = 1.0 / A[j] + (j > 0 ? B[j - 1] / A[j - 1] : 0.0);
         for (int j = 0; j + 1 < m; ++j) of[j] = std::sqrt(B[j]) / A[j];
@@ -864,6 +859,14 @@ struct pff_ctx {
       L.lam_max[b] = hi;
       L.lam_min[b] = lo;
     }
+  }
+  // every level's estimate with one host wait
+  void eig_estimate_all() {
+    const size_t per = size_t(2 * EIG_SC + 4 * EIG_MAX_ITS);
+    for (int l = 0; l < int(lv.size()); ++l)
+      eig_launch(l, l == 0 ? prm.coarse_eig_its : prm.eig_cg_its, eig_host + per * size_t(l));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int l = 0; l < int(lv.size()); ++l) eig_finish(l, eig_host + per * size_t(l));
   }
 
   // Smallest and largest eigenvalue of a symmetric tridiagonal matrix by
@@ -931,7 +934,7 @@ struct pff_ctx {
     level_active_sets();
     setup_levels<double>();
     if (!eig_fixed)
-      for (int l = 0; l < int(lv.size()); ++l) eig_estimate(l, l == 0 ? prm.coarse_eig_its : prm.eig_cg_its);
+      eig_estimate_all();
     if (prm.vcycle_fp32) setup_fp32();
     mg_ready = true;
   }
@@ -1182,6 +1185,9 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
     c->eig_be = dalloc<double>(2 * EIG_MAX_ITS);
     c->ccg_s = dalloc<double>(8);
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->host_red), 256 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->eig_host),
+                         size_t(COPY_MAX_LEVELS) * size_t(2 * EIG_SC + 4 * EIG_MAX_ITS) * sizeof(double),
+                         hipHostMallocDefault));
     (void)n;
   } catch (const std::bad_alloc&) {
     return PFF_E_NOMEM;
@@ -1219,6 +1225,7 @@ int pff_destroy(pff_ctx* c) {
   }
   f(c->red_part); f(c->red_out); f(c->ccg_s); f(c->coarse_nodes); f(c->eig_sc); f(c->eig_al); f(c->eig_be);
   if (c->host_red) hipHostFree(c->host_red);
+  if (c->eig_host) hipHostFree(c->eig_host);
   delete c;
   return PFF_OK;
 }
