@@ -2,8 +2,13 @@
 
 Thin Python layer over the C ABI of include/pff.h: it only marshals torch
 device tensors (memory and streams) into the library, which does all of the
-arithmetic in HIP kernels. There is no CPU fallback: without the built
-library (libpff.so next to this file) every call raises.
+arithmetic in HIP kernels. The library's work buffers live in one torch uint8
+tensor bound to the context (pff_bind_workspace), so torch owns the device
+memory. There is no CPU fallback: without the built library (libpff.so next
+to this file) every call raises.
+
+The drivers above one Newton step (load step, quasi-static load path, adjoint
+gradient, torch.autograd forms) are in paper_2404_03265_amd.autograd.
 """
 from __future__ import annotations
 
