@@ -620,3 +620,177 @@ def test_coarse_cg_closed_forms():
         xe = spla.spsolve(op.A[idx][:, idx].tocsc(), b[idx])
         assert np.linalg.norm(xn[idx] - xe) <= 1e-8 * np.linalg.norm(xe)
         assert np.all(xn[blk & ~op.free] == 0.0)
+
+
+# ------------------------------------- energy term at a deformed state ---
+def _poly_integral(expr, H, x, y):
+    """Exact integral over [0, H]^2 of a polynomial in (x, y), monomial by
+    monomial with rational arithmetic."""
+    import sympy as s
+    P = s.Poly(s.expand(expr), x, y)
+    tot = s.Integer(0)
+    for (i, j), c in P.terms():
+        tot += c * H ** (i + 1) / (i + 1) * H ** (j + 1) / (j + 1)
+    return tot
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_single_cell_deformed_state_exact_integrals(p):
+    """Residual (Problem 2) and Jacobian (Sec. 3.1) on one cell at a state with
+    u != 0, so that sigma(u):e(u) != 0 and the degradation-energy terms
+    (1-kappa) phi sigma(u):e(u) and their derivatives carry weight; kappa != 0
+    and phi~ != 1. The fields are chosen so that p+1 Gauss points integrate
+    every term exactly: u affine (constant strain), phi bilinear, phi~
+    bilinear in the residual and constant in the u-block of the Jacobian. The
+    reference is the weak form integrated exactly in rational arithmetic,
+    written from the paper's formulas in terms of the fields themselves (no
+    quadrature, no shape-function tables)."""
+    import sympy as s
+    R_ = s.Rational
+    x, y = s.symbols("x y")
+    H = R_(7, 10)
+    E, nu, Gc, pr, kap, ell = R_(5, 2), R_(3, 10), R_(17, 10), R_(2, 5), R_(1, 20), R_(7, 20)
+    mu = E / (2 * (1 + nu))
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    ux = R_(3, 10) + R_(1, 5) * x - R_(1, 2) * y
+    uy = -R_(1, 10) + R_(2, 5) * x + R_(1, 4) * y
+    phi = R_(3, 5) + R_(1, 5) * x - R_(3, 10) * y + R_(1, 2) * x * y
+    phit_res = R_(4, 5) + R_(1, 10) * x + R_(1, 5) * y - R_(3, 10) * x * y
+    phit_jac = R_(4, 5)
+
+    def strain(vx, vy):
+        return s.diff(vx, x), s.diff(vy, y), (s.diff(vx, y) + s.diff(vy, x)) / 2
+
+    def stress(e):
+        exx, eyy, exy = e
+        return 2 * mu * exx + lam * (exx + eyy), 2 * mu * eyy + lam * (exx + eyy), 2 * mu * exy
+
+    def ddot(sg, e):
+        return sg[0] * e[0] + sg[1] * e[1] + 2 * sg[2] * e[2]
+
+    eu = strain(ux, uy)
+    su = stress(eu)
+    Sval = ddot(su, eu)
+    divu = eu[0] + eu[1]
+    # shape functions on [0, H]^2, node (a, b) at (a H / p, b H / p), index a + (p+1) b
+    pts = [R_(k, p) * H for k in range(p + 1)]
+
+    def l1(k, t):
+        e = s.Integer(1)
+        for m_ in range(p + 1):
+            if m_ != k:
+                e *= (t - pts[m_]) / (pts[k] - pts[m_])
+        return e
+    N = [l1(a, x) * l1(b, y) for b in range(p + 1) for a in range(p + 1)]
+    nl = len(N)
+    integ = lambda e: float(_poly_integral(e, H, x, y))   # noqa: E731
+
+    # exact residual
+    g_res = (1 - kap) * phit_res ** 2 + kap
+    Rx = np.zeros(3 * nl)
+    for k, Nk in enumerate(N):
+        ex_ = strain(Nk, 0)
+        ey_ = strain(0, Nk)
+        Rx[k] = integ(g_res * ddot(su, ex_) + pr * phit_res ** 2 * s.diff(Nk, x))
+        Rx[nl + k] = integ(g_res * ddot(su, ey_) + pr * phit_res ** 2 * s.diff(Nk, y))
+        Rx[2 * nl + k] = integ((1 - kap) * phi * Sval * Nk + 2 * pr * phi * divu * Nk
+                               - Gc / ell * (1 - phi) * Nk
+                               + Gc * ell * (s.diff(phi, x) * s.diff(Nk, x) + s.diff(phi, y) * s.diff(Nk, y)))
+    # exact Jacobian: u-block at constant phi~, full phi rows
+    g_jac = (1 - kap) * phit_jac ** 2 + kap
+    Kx = np.zeros((3 * nl, 3 * nl))
+    trials = [(Nm, 0) for Nm in N] + [(0, Nm) for Nm in N]
+    for col, (dx_, dy_) in enumerate(trials):
+        ed = strain(dx_, dy_)
+        sd = stress(ed)
+        for k, Nk in enumerate(N):
+            Kx[k, col] = integ(g_jac * ddot(sd, strain(Nk, 0)))
+            Kx[nl + k, col] = integ(g_jac * ddot(sd, strain(0, Nk)))
+            Kx[2 * nl + k, col] = integ((1 - kap) * 2 * phi * ddot(sd, eu) * Nk
+                                        + 2 * pr * phi * (ed[0] + ed[1]) * Nk)
+    for m_, Nm in enumerate(N):
+        for k, Nk in enumerate(N):
+            Kx[2 * nl + k, 2 * nl + m_] = integ(
+                (1 - kap) * Nm * Sval * Nk + 2 * pr * Nm * divu * Nk + Gc / ell * Nm * Nk
+                + Gc * ell * (s.diff(Nm, x) * s.diff(Nk, x) + s.diff(Nm, y) * s.diff(Nk, y)))
+
+    from oracle.assemble import element_residual
+    prm = Params(E=2.5, nu=0.3, Gc=1.7, pressure=0.4, kappa=0.05, ell=0.35)
+    el = Element(p)
+    cs = CellSet(el, np.array([0.7]), np.arange(nl)[None, :])
+
+    def nodal(f):
+        return np.array([[float(f.subs({x: pts[a], y: pts[b]})) for b in range(p + 1)
+                          for a in range(p + 1)]])
+    vux, vuy, vph = nodal(ux), nodal(uy), nodal(phi)
+    Rloc = element_residual(cs, prm, vux, vuy, vph, nodal(phit_res)).reshape(-1)
+    Kloc = element_jacobian(cs, prm, vux, vuy, vph, nodal(s.Integer(1) * phit_jac))[0]
+    # the energy term is a substantial part of the phase-field rows here
+    e_part = np.array([integ((1 - kap) * phi * Sval * Nk) for Nk in N])
+    assert np.abs(e_part).max() > 0.05 * np.abs(Rx[2 * nl:]).max()
+    assert np.allclose(Rloc, Rx, rtol=1e-13, atol=1e-13 * np.abs(Rx).max())
+    assert np.allclose(Kloc, Kx, rtol=1e-13, atol=1e-13 * np.abs(Kx).max())
+
+
+# ------------------------------------------------ level active sets ---
+def _level_sets(hier, mesh, active_xy):
+    act = np.zeros(mesh.n_nodes, bool)
+    for X, Y in active_xy:
+        act[mesh.node_at(X, Y)] = True
+    acts = hier.level_active(act)
+    return [{(int(lv.NX[i]), int(lv.NY[i])) for i in np.flatnonzero(a)}
+            for lv, a in zip(hier.levels, acts)]
+
+
+def test_level_active_sets_by_hand_q1():
+    """Sec. 3.2, last paragraph: a level unknown of the phase field is frozen
+    if any finer unknown it interacts with is active. Mesh: 8 x 8 base cells
+    (level 1, edge 2 lattice units; level 0 has edge 4) with the central 2 x 2
+    block refined once (level 2, edge 1, lattice square [6, 10]^2). The bilinear
+    prolongation couples a fine node to the 1, 2 or 4 vertices of its parent
+    cell (coinciding node, edge midpoint, cell centre). A level node stays
+    free where a leaf cell of that level owns it (its home, reading R19).
+    The expected sets below are listed by hand from those stencils."""
+    mesh = Mesh(8, 1, 1, coarse=4, band=(3.0, 3.0))
+    hier = Hierarchy(mesh)
+    assert [lv.S for lv in hier.levels] == [4, 2, 1]
+    # (7, 7): interior fine node, home level 2. On level 1 it is the centre of
+    # the refined cell [6, 8]^2, whose vertices (6, 6), (8, 6), (6, 8) are nodes
+    # of unrefined level-1 leaf cells (home, keep their own inactive flag), and
+    # (8, 8), which belongs to refined cells only and is frozen; on level 0 the
+    # frozen (8, 8) is a coarse vertex and freezes only itself.
+    sets = _level_sets(hier, mesh, [(7, 7)])
+    assert sets == [{(8, 8)}, {(8, 8)}, {(7, 7)}]
+    # (8, 7): fine edge midpoint between (8, 6) and (8, 8) on level 1; (8, 6)
+    # is home on level 1 (cell [6, 8] x [4, 6] is a leaf), (8, 8) is frozen.
+    sets = _level_sets(hier, mesh, [(8, 7)])
+    assert sets == [{(8, 8)}, {(8, 8)}, {(8, 7)}]
+    # (6, 4): a leaf node of the unrefined region, home level 1 (keeps its flag
+    # there); it is the midpoint of the level-0 edge from (4, 4) to (8, 4).
+    sets = _level_sets(hier, mesh, [(6, 4)])
+    assert sets == [{(4, 4), (8, 4)}, {(6, 4)}, set()]
+    # (10, 10): corner of the refined square, on level 2 but on its refinement
+    # edge; home level 1 (leaf cells there). Level 2 has no finer level and
+    # takes the leaf flag at the position; level 0 gets the coarse cell centre
+    # stencil of the level-1 node (10, 10) inside [8, 12]^2: the node lies at
+    # (1/2, 1/2) of that cell, so all four vertices.
+    sets = _level_sets(hier, mesh, [(10, 10)])
+    assert sets == [{(8, 8), (12, 8), (8, 12), (12, 12)}, {(10, 10)}, {(10, 10)}]
+
+
+def test_level_active_sets_by_hand_q2():
+    """The same rule for Q2 (lattice doubled: level edges 8, 4, 2; refined
+    square [12, 20]^2). A fine node at a quarter point of its parent cell has
+    non-zero 1-D Lagrange weights 3/8, 3/4, -1/8 at all three parent nodes, so
+    it couples to all nine."""
+    mesh = Mesh(8, 1, 2, coarse=4, band=(3.0, 3.0))
+    hier = Hierarchy(mesh)
+    assert [lv.S for lv in hier.levels] == [8, 4, 2]
+    sets = _level_sets(hier, mesh, [(13, 13)])
+    # level 1: the nine nodes of the refined cell [12, 16]^2, minus those on
+    # x = 12 or y = 12, which belong to unrefined level-1 leaf cells (home)
+    lvl1 = {(14, 14), (16, 14), (14, 16), (16, 16)}
+    # level 0: (14, 14) sits at (3/4, 3/4) of [8, 16]^2 and couples to all nine
+    # of its nodes; (16, 14), (14, 16), (16, 16) couple to subsets of them
+    lvl0 = {(a, b) for a in (8, 12, 16) for b in (8, 12, 16)}
+    assert sets == [lvl0, lvl1, {(13, 13)}]
