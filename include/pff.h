@@ -209,6 +209,23 @@ int pff_get_active(pff_ctx* ctx, uint8_t* active, void* stream);
  * condensation, constrained columns removed and identity on constrained rows
  * (3n doubles each; dst and src must not overlap). */
 int pff_vmult(pff_ctx* ctx, double* dst, const double* src, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * dst = J~ src as pff_vmult, with the same kernels and bitwise the same
+ * result, but the partial sums of shared nodes go to a static device array
+ * of PFF_NOALLOC_SCRATCH_BYTES bytes (one per GPU, held until the process
+ * ends) instead of the context's work buffers. The call itself allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); the
+ * context, its state (pff_set_state) and the caller's dst and src must exist
+ * beforehand. Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, two contexts or two threads at once) race
+ * and must be serialised by the caller; the array keeps the last call's
+ * contents, and nothing in it needs to start at zero (every slot is written
+ * before it is read within a call). Errors: PFF_E_ARG (null or overlapping
+ * vectors, or a mesh whose 3 x n_slots partial sums exceed the array, with
+ * the sizes in pff_last_error), PFF_E_STATE (no state). */
+#define PFF_NOALLOC_SCRATCH_BYTES (16u * 1024u * 1024u)
+int pff_vmult_noalloc(pff_ctx* ctx, double* dst, const double* src, void* stream);
 /* dst = J~^T src for `batch` vectors stored one after another (3n each). */
 int pff_vmult_T(pff_ctx* ctx, double* dst, const double* src, int32_t batch, void* stream);
 

@@ -175,6 +175,13 @@ class PhaseFieldSolver:
         self._check(self.lib.pff_vmult(self.h, _ptr(out), _ptr(src), _stream()))
         return out
 
+    def vmult_noalloc(self, src, out):
+        """pff_vmult_noalloc: dst = J~ src with the partial sums in the
+        library's static device array (out must be given: nothing is
+        allocated)."""
+        self._check(self.lib.pff_vmult_noalloc(self.h, _ptr(out), _ptr(src), _stream()))
+        return out
+
     def vmult_T(self, src, batch: int = 1, out=None):
         import torch
         out = torch.empty_like(src) if out is None else out

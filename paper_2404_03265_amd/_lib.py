@@ -60,6 +60,7 @@ _SIGS = {
     "pff_extrapolate_phi": (C.c_int, [VP, VP, VP, C.c_double, VP, VP]),
     "pff_vmult": (C.c_int, [VP, VP, VP, VP]),
     "pff_vmult_T": (C.c_int, [VP, VP, VP, C.c_int32, VP]),
+    "pff_vmult_noalloc": (C.c_int, [VP, VP, VP, VP]),
     "pff_inverse_diagonal": (C.c_int, [VP, C.c_int32, VP, C.c_int32, VP]),
     "pff_vcycle": (C.c_int, [VP, VP, VP, C.c_int32, VP]),
     "pff_get_eigen": (C.c_int, [VP, VP, VP]),

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <type_traits>
@@ -218,6 +219,35 @@ inline int grid_for(int64_t n, int threads = 256) {
   return int(std::max<int64_t>(1, std::min<int64_t>(b, 65536)));
 }
 
+// Partial sums of shared nodes for pff_vmult_noalloc: a file-scope device
+// array, one copy per GPU, held until the process ends. Host code never
+// passes `scratch` itself to a kernel (in host code the name is a host-side
+// stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns on each device, resolved once per device with
+// that device current (pff_create).
+__device__ __align__(256) double scratch[PFF_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (resolved on first use)
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 struct pff_ctx {
@@ -252,6 +282,7 @@ struct pff_ctx {
   bool coarse_fusable = false;
   void* part = nullptr;         // partial sums of shared nodes (largest tile set)
   size_t part_bytes = 0;
+  void* scratch_dev = nullptr;  // device address of `scratch` on this context's GPU
   int V_cap = 0;
   // caller-bound workspace (pff_bind_workspace): the work vectors, level
   // vectors and GMRES basis are carved from it instead of allocated
@@ -279,8 +310,15 @@ struct pff_ctx {
   }
 
   // ---------------------------------------------------------------- tiles --
+  // part_buf / part_cap: partial-sum buffer and its size in bytes (nullptr:
+  // the context's own)
   template <typename T, int MODE, int EPI>
-  void launch_tile(const DevTiles& t, const uint8_t* fl, int64_t nn, TileArgs<T>& a) {
+  void launch_tile(const DevTiles& t, const uint8_t* fl, int64_t nn, TileArgs<T>& a, void* part_buf = nullptr,
+                   size_t part_cap = 0) {
+    if (!part_buf) {
+      part_buf = part;
+      part_cap = part_bytes;
+    }
     a.tile_info = t.info;
     a.shared = t.shared;
     a.cell_loc = t.loc;
@@ -292,7 +330,7 @@ struct pff_ctx {
     a.flags = fl;
     a.n = nn;
     a.max_local = t.max_local;
-    a.part = reinterpret_cast<T*>(part);
+    a.part = reinterpret_cast<T*>(part_buf);
     a.n_slots = t.n_slots;
     a.n_private = t.n_private;
     a.n_shared = t.n_shared;
@@ -308,7 +346,7 @@ struct pff_ctx {
     // one thread per cell of the largest tile
     const int threads = std::max(64, ((t.max_cells + 63) / 64) * 64);
     if (threads > 256) throw std::runtime_error("a tile holds at most 256 cells");
-    if (size_t(3 * t.n_slots) * sizeof(T) > part_bytes) throw std::runtime_error("partial-sum buffer too small");
+    if (size_t(3 * t.n_slots) * sizeof(T) > part_cap) throw std::runtime_error("partial-sum buffer too small");
     if (lds > size_t(160 * 1024)) throw std::runtime_error("tile needs more LDS than a CU has; use smaller tiles");
     // hanging nodes are handled on the tile's nodes; only the inverse
     // diagonal runs the per-cell constraint form
@@ -1188,6 +1226,7 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->eig_host),
                          size_t(COPY_MAX_LEVELS) * size_t(2 * EIG_SC + 4 * EIG_MAX_ITS) * sizeof(double),
                          hipHostMallocDefault));
+    HIPCHK(scratch_address(&c->scratch_dev));
     (void)n;
   } catch (const std::bad_alloc&) {
     return PFF_E_NOMEM;
@@ -1382,6 +1421,30 @@ int pff_vmult(pff_ctx* c, double* dst, const double* src, void* stream) {
   GUARD_BEGIN
   c->s = static_cast<hipStream_t>(stream);
   c->apply_A(dst, src, false);
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_vmult_noalloc(pff_ctx* c, double* dst, const double* src, void* stream) {
+  if (!c || !dst || !src || dst == src) return PFF_E_ARG;
+  const size_t need = size_t(3 * std::max<int64_t>(c->tiles.n_slots, 1)) * sizeof(double);
+  if (need > size_t(PFF_NOALLOC_SCRATCH_BYTES)) {
+    c->err = "vmult_noalloc: the mesh needs " + std::to_string(need) + " bytes of partial sums, above the " +
+             std::to_string(size_t(PFF_NOALLOC_SCRATCH_BYTES)) + "-byte static scratch; use pff_vmult";
+    return PFF_E_ARG;
+  }
+  if (!c->has_state) { c->err = "vmult_noalloc needs a state"; return PFF_E_STATE; }
+  if (!c->scratch_dev) { c->err = "vmult_noalloc: scratch address not resolved"; return PFF_E_STATE; }
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  const double* st[4];
+  c->leaf_state4(st);
+  TileArgs<double> a{};
+  a.src = src;
+  a.dst = dst;
+  for (int i = 0; i < 4; ++i) a.st[i] = st[i];
+  c->launch_tile<double, MODE_J, EPI_PLAIN>(c->tiles, c->flags, c->n, a, c->scratch_dev,
+                                            size_t(PFF_NOALLOC_SCRATCH_BYTES));
   return PFF_OK;
   GUARD_END(c)
 }
