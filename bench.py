@@ -44,6 +44,20 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+def load_traffic(workload: str, path: str = TRAFFIC_FILE):
+    """HBM bytes per vmult from the committed counter summary, or None when
+    there is none for the workload or the kernel sources have changed since
+    the counters were taken (their hash differs)."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tr = json.load(fh)
+    w = tr.get("workloads", {}).get(workload)
+    if tr.get("kernel_hash") != kernel_hash() or w is None:
+        return None
+    return w.get("bytes_per_launch")
+
+
 def algorithmic_bytes(n_nodes: int, n_cells: int, degree: int) -> int:
     """Bytes one vmult must move: src and dst (3 comps, 8 B each), the state
     (u_x, u_y, phi, phit: 4 x 8 B per node) and an int32 dof map per cell."""
@@ -215,15 +229,7 @@ def main():
     algo = algorithmic_bytes(g.n, n_cells_leaf, spec.degree)
     achieved = algo / (ms_vmult * 1e-3) / 1e9
     log(f"vmult {ms_vmult * 1e3:.1f} us -> {gdofs:.2f} GDoF/s, {achieved:.0f} GB/s algorithmic")
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        # HBM bytes per vmult from the committed counter summary, valid only
-        # while the kernel sources are the ones profiled
-        w = tr.get("workloads", {}).get(spec.name)
-        if tr.get("kernel_hash") == kernel_hash() and w is not None:
-            traffic = w.get("bytes_per_launch")
+    traffic = load_traffic(spec.name)
 
     # ---- load-step solves (Alg. 2 loop), FP64 and mixed precision ----------
     extra = {}

@@ -31,7 +31,9 @@
  *    there (dst_i = src_i).
  *  - Return value: 0 on success; negative on error (PFF_E_*), with text from
  *    pff_last_error; positive PFF_W_* when an iteration did not converge
- *    (results are still written).
+ *    (results are still written). Iterations check their norms and
+ *    Gram-Schmidt coefficients: a NaN or infinity (e.g. from a non-finite
+ *    input) stops them with PFF_E_NONFINITE.
  *  - Device memory of a context: its mesh, tile and transfer tables and a few
  *    KB of scalars are allocated by pff_create; its work buffers live in a
  *    caller-owned workspace (pff_bind_workspace) or, without one, are
@@ -54,6 +56,7 @@ extern "C" {
 #define PFF_E_HIP (-3)      /* HIP runtime error */
 #define PFF_E_MESH (-4)     /* mesh construction failed */
 #define PFF_E_NOMEM (-5)    /* device allocation failed */
+#define PFF_E_NONFINITE (-6) /* a norm or reduction of an iteration came out NaN or infinite */
 #define PFF_W_NOCONV 1      /* GMRES reached its iteration limit */
 #define PFF_W_LINESEARCH 2  /* no line-search trial decreased the residual */
 
@@ -139,8 +142,11 @@ int pff_default_params(pff_params* p);
 /* Build the mesh, tile tables and multigrid levels on the host and upload
  * them to the current HIP device. The context owns those device tables; its
  * work vectors come from a bound workspace (pff_bind_workspace) or are
- * allocated on first use. Errors:
- * PFF_E_ARG, PFF_E_MESH, PFF_E_NOMEM, PFF_E_HIP. */
+ * allocated on first use. Errors: PFF_E_ARG (invalid parameters: see
+ * pff_params; also gmres_max_its < 1, ls_max < 1, ls_omega outside (0, 1]),
+ * PFF_E_MESH, PFF_E_NOMEM, PFF_E_HIP; *out stays NULL, whatever was already
+ * uploaded is freed, and pff_last_error(NULL) returns the reason (text of the
+ * last failed pff_create on the calling thread). */
 int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** out);
 int pff_destroy(pff_ctx* ctx);
 /* Replace material/solver parameters (takes effect at the next set_state). */
@@ -202,6 +208,12 @@ int pff_set_state(pff_ctx* ctx, const double* U, const double* phi_old, const do
  * finite). */
 int pff_extrapolate_phi(pff_ctx* ctx, const double* phi_prev, const double* phi_prev2, double theta,
                         double* out, void* stream);
+/* The same extrapolation from the load parameters of the two solved steps
+ * and the next one (t_prev2 < t_prev <= t_next, e.g. pressures): theta =
+ * (t_next - t_prev) / (t_prev - t_prev2). Errors: PFF_E_ARG if the
+ * parameters do not increase. */
+int pff_extrapolate_phi_load(pff_ctx* ctx, const double* phi_prev, const double* phi_prev2, double t_prev2,
+                             double t_prev, double t_next, double* out, void* stream);
 /* Copy the current active set (device n bytes, 1 = active). */
 int pff_get_active(pff_ctx* ctx, uint8_t* active, void* stream);
 
@@ -226,7 +238,10 @@ int pff_vmult(pff_ctx* ctx, double* dst, const double* src, void* stream);
  * the sizes in pff_last_error), PFF_E_STATE (no state). */
 #define PFF_NOALLOC_SCRATCH_BYTES (16u * 1024u * 1024u)
 int pff_vmult_noalloc(pff_ctx* ctx, double* dst, const double* src, void* stream);
-/* dst = J~^T src for `batch` vectors stored one after another (3n each). */
+/* dst = J~^T src for `batch` vectors stored one after another (3n each):
+ * the transpose of the operator of pff_vmult (the Jacobian of Sec. 3.1 with
+ * its coupling block moved to the displacement rows), used by the adjoint
+ * of the crack-volume functional (Sec. 4). Identity on constrained rows. */
 int pff_vmult_T(pff_ctx* ctx, double* dst, const double* src, int32_t batch, void* stream);
 
 /* Inverse diagonal of the leaf operator (level = -1: 1/diag on free rows, 1 on
@@ -270,8 +285,21 @@ int pff_residual(pff_ctx* ctx, double* R, const double* U, int32_t masked, void*
  * condensed). Synchronises. */
 int pff_tcv(pff_ctx* ctx, const double* U, double* tcv, double* dTCVdU, void* stream);
 /* out[0..2] = z^T dF~/d(Gc, E, p) at the loaded state, constrained rows of z
- * ignored (host out). Synchronises. */
+ * ignored (host out): the residual of Problem 2 differentiated in the
+ * material parameters of Table 1 (sigma is linear in E at fixed nu; Gc and
+ * p enter linearly), with l, kappa and the active set held fixed.
+ * Synchronises. */
 int pff_param_grad(pff_ctx* ctx, const double* z, double* out, void* stream);
+/* Adjoint gradient of the crack volume TCV = int u . grad phi (Sec. 4) with
+ * respect to theta = (Gc, E, p) at the loaded state U (3n; pass the U of
+ * pff_set_state, which must have run with setup_mg) with the active set held
+ * fixed: solves J~^T z = dTCV/dU (constrained rows zero) by transposed GMRES
+ * (tolerance: tol_override if > 0, else max(gmres_atol, gmres_rtol |rhs|))
+ * and returns grad[0..2] = dTCV/dtheta = -z^T dF~/dtheta (host), *tcv
+ * (host, nullable) and z (device 3n, nullable). info: host, nullable.
+ * Synchronises. Returns PFF_W_NOCONV if GMRES stopped at its limit. */
+int pff_adjoint_tcv(pff_ctx* ctx, const double* U, double* tcv, double* grad, double* z, double tol_override,
+                    pff_gmres_info* info, void* stream);
 /* Set hanging entries of a nodal vector with ncomp blocked components from
  * their masters. */
 int pff_distribute(pff_ctx* ctx, double* v, int32_t ncomp, void* stream);

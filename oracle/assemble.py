@@ -268,28 +268,49 @@ class LeafProblem:
         Jc = self.C3.T @ J @ self.C3
         return (Mf @ Jc @ Mf + sp.diags(1.0 - f)).tocsr()
 
-    def masked_rows(self, rows, src, U, phit, active):
-        """Selected rows of J~ src (blocked dof indices), assembling only the
-        cells that touch those rows (directly or through a hanging node whose
-        masters include the row's node). For spot checks on large meshes."""
+    def _cells_for_rows(self, rows):
+        """Cells whose element arrays reach the given blocked rows of a
+        condensed (C^T ... C) operator: cells with the row's node or with a
+        hanging node that has the row's node among its masters."""
         n = self.n
         mesh = self.mesh
-        rows = np.asarray(rows)
-        nodes = np.unique(rows % n)
+        nodes = np.unique(np.asarray(rows) % n)
         need = set(int(k) for k in nodes)
         for h, lst in mesh.hanging_constraints.items():
             if any(m in need for m, _ in lst):
                 need.add(int(h))
         need = np.array(sorted(need))
         sel = np.isin(mesh.cell_nodes, need).any(axis=1)
-        cs = CellSet(self.el, self.cells.H[sel], self.cells.nodes[sel])
+        return CellSet(self.el, self.cells.H[sel], self.cells.nodes[sel])
+
+    def masked_rows(self, rows, src, U, phit, active, transpose=False):
+        """Selected rows of J~ src (or of J~^T src), assembling only the cells
+        that touch those rows. For spot checks on large meshes: the
+        row of J~^T at node k needs column k of J, which only cells holding k
+        (or a hanging node mastered by k) reach, the same cells as row k."""
+        n = self.n
+        rows = np.asarray(rows)
+        cs = self._cells_for_rows(rows)
         g = cs.gather
         Ke = element_jacobian(cs, self.prm, g(U[:n]), g(U[n:2 * n]), g(U[2 * n:]), g(phit))
         J = assemble_matrix(cs.nodes, n, Ke)
+        if transpose:
+            J = J.T.tocsr()
         f = self.free_mask(active)
         x = self.C3 @ (src * f)
         y = (self.C3.T @ (J @ x))[rows]
         return np.where(f[rows], y, src[rows])
+
+    def residual_rows(self, rows, U, phit):
+        """Selected rows of R = -C^T F(U), assembling only the cells that
+        touch those rows."""
+        n = self.n
+        rows = np.asarray(rows)
+        cs = self._cells_for_rows(rows)
+        g = cs.gather
+        loc = element_residual(cs, self.prm, g(U[:n]), g(U[n:2 * n]), g(U[2 * n:]), g(phit))
+        raw = assemble_vector(cs.nodes, n, loc)
+        return -(self.C3.T @ raw)[rows]
 
     # crack volume (Sec. 4) and its derivative
     def tcv(self, U):

@@ -87,7 +87,8 @@ class PhaseFieldSolver:
         h = C.c_void_p()
         rc = self.lib.pff_create(C.byref(spec), C.byref(self.params.to_c()), C.byref(h))
         if rc != 0:
-            raise RuntimeError(f"pff_create failed ({rc})")
+            msg = self.lib.pff_last_error(None)
+            raise RuntimeError(f"pff_create failed ({rc}): {msg.decode() if msg else ''}")
         self.h = h
         n = C.c_int64()
         nl = C.c_int32()
@@ -161,6 +162,13 @@ class PhaseFieldSolver:
         out = torch.empty_like(phi_prev) if out is None else out
         self._check(self.lib.pff_extrapolate_phi(self.h, _ptr(phi_prev), _ptr(phi_prev2), float(theta), _ptr(out),
                                                  _stream()))
+        return out
+
+    def extrapolate_phi_load(self, phi_prev, phi_prev2, t_prev2: float, t_prev: float, t_next: float, out=None):
+        import torch
+        out = torch.empty_like(phi_prev) if out is None else out
+        self._check(self.lib.pff_extrapolate_phi_load(self.h, _ptr(phi_prev), _ptr(phi_prev2), float(t_prev2),
+                                                      float(t_prev), float(t_next), _ptr(out), _stream()))
         return out
 
     def active(self):
@@ -249,6 +257,18 @@ class PhaseFieldSolver:
         out = np.zeros(3)
         self._check(self.lib.pff_param_grad(self.h, _ptr(z), out.ctypes.data_as(C.c_void_p), _stream()))
         return out
+
+    def adjoint_tcv(self, U, tol: float = 0.0):
+        """pff_adjoint_tcv at the loaded state: (TCV, dTCV/d(Gc, E, p) as a
+        numpy array, adjoint solution z, GMRES info, return code)."""
+        import torch
+        v = C.c_double()
+        grad = np.zeros(3)
+        z = torch.empty_like(U)
+        info = _lib.GmresInfo()
+        rc = self._check(self.lib.pff_adjoint_tcv(self.h, _ptr(U), C.byref(v), grad.ctypes.data_as(C.c_void_p),
+                                                  _ptr(z), float(tol), C.byref(info), _stream()))
+        return v.value, grad, z, {k: getattr(info, k) for k, _ in info._fields_}, rc
 
     def distribute(self, v, ncomp: int):
         self._check(self.lib.pff_distribute(self.h, _ptr(v), ncomp, _stream()))

@@ -58,6 +58,7 @@ _SIGS = {
     "pff_set_state": (C.c_int, [VP, VP, VP, VP, VP, C.c_int32, VP]),
     "pff_get_active": (C.c_int, [VP, VP, VP]),
     "pff_extrapolate_phi": (C.c_int, [VP, VP, VP, C.c_double, VP, VP]),
+    "pff_extrapolate_phi_load": (C.c_int, [VP, VP, VP, C.c_double, C.c_double, C.c_double, VP, VP]),
     "pff_vmult": (C.c_int, [VP, VP, VP, VP]),
     "pff_vmult_T": (C.c_int, [VP, VP, VP, C.c_int32, VP]),
     "pff_vmult_noalloc": (C.c_int, [VP, VP, VP, VP]),
@@ -70,6 +71,7 @@ _SIGS = {
     "pff_residual": (C.c_int, [VP, VP, VP, C.c_int32, VP]),
     "pff_tcv": (C.c_int, [VP, VP, C.POINTER(C.c_double), VP, VP]),
     "pff_param_grad": (C.c_int, [VP, VP, VP, VP]),
+    "pff_adjoint_tcv": (C.c_int, [VP, VP, C.POINTER(C.c_double), VP, VP, C.c_double, C.POINTER(GmresInfo), VP]),
     "pff_distribute": (C.c_int, [VP, VP, C.c_int32, VP]),
     "pff_mask_constrained": (C.c_int, [VP, VP, VP]),
     "pff_dot": (C.c_int, [VP, VP, VP, C.c_int64, C.POINTER(C.c_double), VP]),

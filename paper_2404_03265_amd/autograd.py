@@ -26,21 +26,40 @@ class JacobianApply(torch.autograd.Function):
         return ctx.solver.vmult_T(grad.contiguous()), None
 
 
-def solve_load_step(solver, U, phi_old, phi_tilde, active=None, tol=1e-7, max_steps=30, progress=None):
+class LoadStepNotConverged(RuntimeError):
+    """A load step ended without meeting the Newton tolerance (Alg. 2)."""
+
+
+def solve_load_step(solver, U, phi_old, phi_tilde, active=None, tol=1e-7, max_steps=30, progress=None,
+                    strict=False):
     """Alg. 2 loop until the active set repeats and |R~| <= tol. U is updated
-    in place; returns (active, list of per-step info dicts). progress, if
-    given, is called as progress(step_count, info) after every step."""
+    in place; returns (active, list of per-step info dicts). Each info dict
+    carries the step's return code under "rc" (PFF_W_NOCONV = 1: GMRES hit
+    its iteration limit; PFF_W_LINESEARCH = 2: no trial decreased |R~|), and
+    the last one "converged" (tolerance met with an unchanged active set).
+    With strict=True a load step that stops at max_steps unconverged raises
+    LoadStepNotConverged. progress, if given, is called as
+    progress(step_count, info) after every step."""
     if active is None:
         active = torch.zeros(solver.n, dtype=torch.uint8, device=U.device)
     infos = []
+    converged = False
     for _ in range(max_steps):
         prev = active.clone()
         info, rc = solver.newton_step(U, phi_old, phi_tilde, active)
+        info["rc"] = rc
         infos.append(info)
         if progress is not None:
             progress(len(infos), info)
         if torch.equal(prev, active) and info["residual_before"] <= tol:
+            converged = True
             break
+    if infos:
+        infos[-1]["converged"] = converged
+    if strict and not converged:
+        codes = sorted({i["rc"] for i in infos if i["rc"]})
+        raise LoadStepNotConverged(f"load step not converged in {len(infos)} Newton steps "
+                                   f"(last |R~| {infos[-1]['residual_before']:.3e}, warning codes {codes})")
     return active, infos
 
 
@@ -64,8 +83,7 @@ def solve_load_path(solver, U, phi0, pressures, extrapolate=False, tol=1e-7, max
     for k, p in enumerate(pressures):
         solver.set_params(replace(solver.params, pressure=float(p)))
         if extrapolate and phi_prev2 is not None:
-            theta = (float(p) - float(pressures[k - 1])) / (float(pressures[k - 1]) - float(pressures[k - 2]))
-            phi_tilde = solver.extrapolate_phi(phi_old, phi_prev2, theta)
+            phi_tilde = solver.extrapolate_phi_load(phi_old, phi_prev2, pressures[k - 2], pressures[k - 1], p)
         else:
             phi_tilde = phi_old
         cb = None if progress is None else (lambda j, info, k=k: progress(k, j, info))
@@ -81,13 +99,13 @@ def solve_load_path(solver, U, phi0, pressures, extrapolate=False, tol=1e-7, max
 
 
 def adjoint_tcv_gradient(solver, U, phi_old, phi_tilde, active, tol=0.0):
-    """(TCV, dTCV/d(Gc, E, p)) at U with the active set frozen."""
+    """(TCV, dTCV/d(Gc, E, p), adjoint solution z, GMRES info) at U with the
+    active set frozen (pff_adjoint_tcv: transposed GMRES and the parameter
+    derivatives, sign included, in the library)."""
     solver.set_state(U, phi_old, phi_tilde, active, setup_mg=True)
-    tcv, g = solver.tcv(U, grad=True)
-    solver.mask_constrained(g)
-    z, info, rc = solver.gmres(g, transpose=True, tol=tol)
-    dF = solver.param_grad(z)
-    return tcv, -torch.as_tensor(dF, dtype=torch.float64), z, info
+    tcv, grad, z, info, rc = solver.adjoint_tcv(U, tol=tol)
+    info["rc"] = rc
+    return tcv, torch.as_tensor(grad, dtype=torch.float64), z, info
 
 
 class TcvOfParams(torch.autograd.Function):

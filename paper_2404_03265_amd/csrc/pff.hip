@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -17,12 +18,18 @@
 #include "../../include/pff.h"
 #include "mesh.hpp"
 #include "tile_kernel.hpp"
+#include "tile_pipe.hpp"
 #include "util_kernels.hpp"
 #include "coarse_kernel.hpp"
 
 using namespace pff;
 
 namespace {
+
+// a reduction or norm that came out NaN or infinite (reported as PFF_E_NONFINITE)
+struct nonfinite_error : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
 
 #define HIPCHK(expr)                                                            \
   do {                                                                          \
@@ -46,6 +53,14 @@ struct DevTiles {
   uint8_t* hang_col = nullptr;
   int n_tiles = 0, max_local = 0, max_cells = 0;
   int64_t n_rec = 0, n_private = 0, n_shared = 0, n_slots = 0;
+  int n_hang_rec = 0;
+  // the persistent double-buffered kernel (tile_pipe_kernel) applies: Q2,
+  // one-wave tiles within its LDS slots; pipe_par_ok[b]: every tile's private
+  // range fits its 256 slots when the field's element parity is b
+  bool pipe_shape_ok = false;
+  bool pipe_par_ok[2] = {false, false};
+  int32_t* runless = nullptr;   // tiles whose shared list is not in header runs
+  int n_runless = 0;
 };
 
 template <typename T>
@@ -167,6 +182,27 @@ DevTiles upload_tiles(const TileSet& t) {
   d.n_private = t.n_private;
   d.n_shared = t.n_shared;
   d.n_slots = t.n_slots;
+  d.n_hang_rec = int(t.hang_col.size());
+  bool shape = t.p == 2 && t.n_tiles > 0 && t.max_cells <= PIPE_CELLS && t.n_shared > 0;
+  bool par0 = true, par1 = true;
+  for (int k = 0; shape && k < t.n_tiles; ++k) {
+    const int32_t* ti = t.tile_info.data() + size_t(TILE_STRIDE) * size_t(k);
+    const int o0 = ti[TILE_OWNED0], no = ti[TILE_NOWNED], ns = ti[TILE_NSHARED];
+    shape = no >= 2 && no <= PIPE_PRIV && ns >= 1 && ns <= PIPE_SH && ti[TILE_NHANG] <= 64 &&
+            ti[TILE_NCELL] >= 1;
+    par0 = par0 && no + (o0 & 1) <= PIPE_PRIV;
+    par1 = par1 && no + ((o0 + 1) & 1) <= PIPE_PRIV;
+  }
+  d.pipe_shape_ok = shape;
+  d.pipe_par_ok[0] = shape && par0;
+  d.pipe_par_ok[1] = shape && par1;
+  if (shape) {
+    std::vector<int32_t> rl;
+    for (int k = 0; k < t.n_tiles; ++k)
+      if (t.tile_info[size_t(TILE_STRIDE) * size_t(k) + TILE_NRUN] == 0) rl.push_back(k);
+    d.n_runless = int(rl.size());
+    d.runless = upload(rl);
+  }
   return d;
 }
 
@@ -283,6 +319,8 @@ struct pff_ctx {
   void* part = nullptr;         // partial sums of shared nodes (largest tile set)
   size_t part_bytes = 0;
   void* scratch_dev = nullptr;  // device address of `scratch` on this context's GPU
+  int n_cu = 0;                 // compute units of the context's GPU
+  bool pipe_enabled = true;     // leaf Jacobian / transpose through tile_pipe_kernel where it applies
   int V_cap = 0;
   // caller-bound workspace (pff_bind_workspace): the work vectors, level
   // vectors and GMRES basis are carved from it instead of allocated
@@ -312,6 +350,24 @@ struct pff_ctx {
   // ---------------------------------------------------------------- tiles --
   // part_buf / part_cap: partial-sum buffer and its size in bytes (nullptr:
   // the context's own)
+  // whether the pipelined kernel can run the leaf operator with these
+  // operand and state pointers: every field's private ranges must fit the
+  // 256 LDS slots at the pointer's element parity, and an operand at an odd
+  // element address would make the first tile's 16-byte loads start before
+  // the array
+  bool pipe_applies(const DevTiles& t, const TileArgs<double>& a) const {
+    if (!pipe_enabled || !t.pipe_shape_ok || n_cu <= 0) return false;
+    if ((reinterpret_cast<uintptr_t>(a.src) & 15u) != 0) return false;
+    for (int f = 0; f < PIPE_NF; ++f) {
+      const double* ep = f < 3 ? a.src + f * a.n : a.st[f - 3];
+      if (!ep) return false;
+      const int par = int((reinterpret_cast<uintptr_t>(ep) >> 3) & 1u);
+      if (f >= 3 && par) return false;
+      if (!t.pipe_par_ok[par]) return false;
+    }
+    return true;
+  }
+
   template <typename T, int MODE, int EPI>
   void launch_tile(const DevTiles& t, const uint8_t* fl, int64_t nn, TileArgs<T>& a, void* part_buf = nullptr,
                    size_t part_cap = 0) {
@@ -356,6 +412,26 @@ struct pff_ctx {
     if (lds > size_t(64 * 1024))
       HIPCHK(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     a.tile_base = 0;
+    if constexpr ((MODE == MODE_J || MODE == MODE_JT) && std::is_same<T, double>::value) {
+      if (p == 2 && pipe_applies(t, a)) {
+        // four one-wave workgroups per CU (LDS: two buffers of 7 fields each)
+        const int nwg = std::min(t.n_tiles, 4 * n_cu);
+        hipLaunchKernelGGL((tile_pipe_kernel<MODE>), dim3(nwg), dim3(64), 0, s, a, a.tile_info, a.shared, a.cell_loc,
+                           a.cell_info, a.flags, a.hang_rec, a.hang_w, a.hang_col, a.dst, a.part, t.n_tiles,
+                           t.n_hang_rec);
+        if (t.n_runless > 0) {
+          // the tiles the pipelined kernel skipped (shared list not in runs)
+          TileArgs<T> b = a;
+          b.tile_list = t.runless;
+          const int threads = std::max(64, ((t.max_cells + 63) / 64) * 64);
+          hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI, false>), dim3(t.n_runless), dim3(threads), lds, s, b);
+        }
+        if (t.n_shared > 0)
+          hipLaunchKernelGGL((shared_fixup<T, MODE, EPI>), dim3(grid_for(t.n_shared)), dim3(256), 0, s, a);
+        HIPCHK(hipGetLastError());
+        return;
+      }
+    }
     if (t.n_tiles > 0) {
       if (p == 1)
         hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI, HANG>), dim3(t.n_tiles), dim3(threads), lds, s, a);
@@ -1017,6 +1093,7 @@ struct pff_ctx {
     HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
     apply_Minv(V, b, fp32);
     double beta = norm(V, N);
+    if (!std::isfinite(beta)) throw nonfinite_error("GMRES: |P^-1 b| is not finite");
     pff_gmres_info inf{};
     inf.initial_residual = beta;
     inf.final_residual = beta;
@@ -1062,6 +1139,9 @@ struct pff_ctx {
         double hn = std::sqrt(hn2);
         std::vector<double> h(j + 2);
         for (int i = 0; i <= j; ++i) h[i] = h1[i] + h2[i];
+        bool finite = std::isfinite(hn);
+        for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(h[i]);
+        if (!finite) throw nonfinite_error("GMRES: a Gram-Schmidt coefficient or norm is not finite");
         for (int i = 0; i < j; ++i) {
           const double tt = cs[i] * h[i] + sn[i] * h[i + 1];
           h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
@@ -1096,6 +1176,7 @@ struct pff_ctx {
       hipLaunchKernelGGL(k_sub, dim3(grid_for(N)), dim3(256), 0, s, w, b, t, N);
       apply_Minv(V, w, fp32);
       beta = norm(V, N);
+      if (!std::isfinite(beta)) throw nonfinite_error("GMRES: restart residual is not finite");
       inf.final_residual = beta;
       if (beta <= tol) { conv = true; break; }
     }
@@ -1116,6 +1197,10 @@ LevelWork<float>& pff_ctx::work<float>(DevLevel& L) { return L.w32; }
 #define GUARD_BEGIN try {
 #define GUARD_END(ctx)                                      \
   }                                                         \
+  catch (const nonfinite_error& e) {                        \
+    if (ctx) (ctx)->err = e.what();                         \
+    return PFF_E_NONFINITE;                                 \
+  }                                                         \
   catch (const std::bad_alloc&) {                           \
     if (ctx) (ctx)->err = "device allocation failed";       \
     return PFF_E_NOMEM;                                     \
@@ -1127,6 +1212,7 @@ LevelWork<float>& pff_ctx::work<float>(DevLevel& L) { return L.w32; }
 
 static bool params_valid(const pff_params& p) {
   return p.cheb_degree >= 1 && p.coarse_its >= 1 && p.gmres_restart >= 1 && p.gmres_restart <= 60 &&
+         p.gmres_max_its >= 1 && p.ls_max >= 1 && p.ls_omega > 0.0 && p.ls_omega <= 1.0 &&
          p.coarse_mode >= 0 && p.coarse_mode <= 1 && p.eig_cg_its >= 1 && p.eig_cg_its <= EIG_MAX_ITS &&
          p.coarse_eig_its >= 1 && p.coarse_eig_its <= EIG_MAX_ITS && std::isfinite(p.pdas_c) && p.pdas_c >= 0.0;
 }
@@ -1160,8 +1246,17 @@ int pff_default_params(pff_params* p) {
   return PFF_OK;
 }
 
+// text of the last failed pff_create on this thread (pff_last_error(NULL))
+static thread_local std::string g_create_err = "null context";
+
+static int create_failed(pff_ctx* c, int rc, const std::string& why) {
+  g_create_err = why;
+  if (c) pff_destroy(c);   // frees whatever was uploaded before the failure
+  return rc;
+}
+
 int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** out) {
-  if (!spec || !params || !out) return PFF_E_ARG;
+  if (!spec || !params || !out) return create_failed(nullptr, PFF_E_ARG, "pff_create: null argument");
   *out = nullptr;
   std::unique_ptr<pff_ctx> c(new pff_ctx());
   MeshSpec ms;
@@ -1173,7 +1268,7 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
   ms.band_y = spec->band_y;
   ms.tile_x = spec->tile_x;
   ms.tile_y = spec->tile_y;
-  if (!params_valid(*params)) return PFF_E_ARG;
+  if (!params_valid(*params)) return create_failed(nullptr, PFF_E_ARG, "pff_create: invalid parameters");
   try {
     bool built = false;
     try {
@@ -1181,15 +1276,13 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
     } catch (const std::runtime_error& e) {
       c->mesh.error = e.what();
     }
-    if (!built) {
-      static thread_local std::string msg;
-      msg = c->mesh.error;
-      return PFF_E_MESH;
-    }
-    if (c->mesh.n_levels > COPY_MAX_LEVELS) return PFF_E_ARG;
-    for (const Level& L : c->mesh.levels)
-      if (L.tiles.max_local > 65535) return PFF_E_MESH;
-    if (c->mesh.tiles.max_local > 65535) return PFF_E_MESH;
+    if (!built) return create_failed(nullptr, PFF_E_MESH, "pff_create: mesh: " + c->mesh.error);
+    if (c->mesh.n_levels > COPY_MAX_LEVELS)
+      return create_failed(nullptr, PFF_E_ARG, "pff_create: more multigrid levels than the library holds (" +
+                                                   std::to_string(COPY_MAX_LEVELS) + ")");
+    bool too_big = c->mesh.tiles.max_local > 65535;
+    for (const Level& L : c->mesh.levels) too_big = too_big || L.tiles.max_local > 65535;
+    if (too_big) return create_failed(nullptr, PFF_E_MESH, "pff_create: a tile has more than 65535 local nodes");
     c->prm = *params;
     c->p = ms.degree;
     c->n = c->mesh.n_nodes;
@@ -1227,11 +1320,18 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
                          size_t(COPY_MAX_LEVELS) * size_t(2 * EIG_SC + 4 * EIG_MAX_ITS) * sizeof(double),
                          hipHostMallocDefault));
     HIPCHK(scratch_address(&c->scratch_dev));
+    {
+      int dev = 0;
+      HIPCHK(hipGetDevice(&dev));
+      HIPCHK(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+      const char* e = std::getenv("PFF_PIPELINE");
+      c->pipe_enabled = e && e[0] == '1';
+    }
     (void)n;
   } catch (const std::bad_alloc&) {
-    return PFF_E_NOMEM;
-  } catch (const std::exception&) {
-    return PFF_E_HIP;
+    return create_failed(c.release(), PFF_E_NOMEM, "pff_create: device allocation failed");
+  } catch (const std::exception& e) {
+    return create_failed(c.release(), PFF_E_HIP, std::string("pff_create: ") + e.what());
   }
   *out = c.release();
   return PFF_OK;
@@ -1242,7 +1342,7 @@ int pff_destroy(pff_ctx* c) {
   auto f = [](void* p) { if (p) hipFree(p); };
   auto ft = [&](DevTiles& t) {
     f(t.info); f(t.shared); f(t.sh_tab); f(t.loc); f(t.loc_sub); f(t.cinfo);
-    f(t.hang_rec); f(t.hang_w); f(t.hang_col);
+    f(t.hang_rec); f(t.hang_w); f(t.hang_col); f(t.runless);
   };
   ft(c->tiles);
   f(c->flags);
@@ -1571,6 +1671,7 @@ int pff_newton_step(pff_ctx* c, double* U, const double* phi_old, const double* 
   hipLaunchKernelGGL(k_mask_leaf, dim3(grid_for(N)), dim3(256), 0, c->s, R, c->flags, n);
   const double base = c->norm(R, N);
   inf.residual_before = base;
+  if (!std::isfinite(base)) throw nonfinite_error("newton_step: |R~(U)| is not finite");
   // U_c and the right-hand side R~(U_c)
   HIPCHK(hipMemcpyAsync(Uc, c->U, sizeof(double) * N, hipMemcpyDeviceToDevice, c->s));
   hipLaunchKernelGGL(k_apply_active, dim3(grid_for(n)), dim3(256), 0, c->s, Uc, c->phio, c->flags, n);
@@ -1658,6 +1759,48 @@ int pff_param_grad(pff_ctx* c, const double* z, double* out, void* stream) {
   GUARD_END(c)
 }
 
+int pff_adjoint_tcv(pff_ctx* c, const double* U, double* tcv, double* grad, double* z, double tol_override,
+                    pff_gmres_info* info, void* stream) {
+  if (!c || !U || !grad) return PFF_E_ARG;
+  if (!c->has_state || !c->mg_ready) { c->err = "adjoint_tcv needs set_state with setup_mg"; return PFF_E_STATE; }
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  const int64_t N = 3 * c->n;
+  double* g = c->wv[2];
+  double* zz = z ? z : c->wv[3];
+  // dTCV/dU (condensed) with constrained rows zeroed: the right-hand side
+  // of the transposed system J~^T z = dTCV/dU
+  c->leaf_op<MODE_TCVGRAD>(g, U, nullptr);
+  const double t = c->dot(g + 2 * c->n, U + 2 * c->n, c->n);
+  hipLaunchKernelGGL(k_mask_leaf, dim3(grid_for(N)), dim3(256), 0, c->s, g, c->flags, c->n);
+  const double gn = c->norm(g, N);
+  if (!std::isfinite(gn) || !std::isfinite(t)) throw nonfinite_error("adjoint_tcv: TCV or its gradient is not finite");
+  const double tol = tol_override > 0.0 ? tol_override : std::max(c->prm.gmres_atol, c->prm.gmres_rtol * gn);
+  pff_gmres_info gi{};
+  const int grc = c->gmres(zz, g, true, tol, &gi, c->prm.vcycle_fp32 != 0);
+  // dTCV/dtheta = -z^T dF~/dtheta (the state depends on theta through F~(U, theta) = 0)
+  double dF[3];
+  const int rc = pff_param_grad(c, zz, dF, stream);
+  if (rc) return rc;
+  for (int k = 0; k < 3; ++k) grad[k] = -dF[k];
+  if (tcv) *tcv = t;
+  if (info) *info = gi;
+  return grc;
+  GUARD_END(c)
+}
+
+int pff_extrapolate_phi_load(pff_ctx* c, const double* phi_prev, const double* phi_prev2, double t_prev2,
+                             double t_prev, double t_next, double* out, void* stream) {
+  if (!c) return PFF_E_ARG;
+  const double den = t_prev - t_prev2;
+  const double theta = (t_next - t_prev) / den;
+  if (!std::isfinite(theta) || den == 0.0 || theta < 0.0) {
+    c->err = "extrapolate_phi_load: the load parameters must increase (t_prev2 < t_prev <= t_next)";
+    return PFF_E_ARG;
+  }
+  return pff_extrapolate_phi(c, phi_prev, phi_prev2, theta, out, stream);
+}
+
 int pff_distribute(pff_ctx* c, double* v, int32_t ncomp, void* stream) {
   if (!c || !v || ncomp < 1 || ncomp > 3) return PFF_E_ARG;
   GUARD_BEGIN
@@ -1689,6 +1832,6 @@ int pff_dot(pff_ctx* c, const double* a, const double* b, int64_t len, double* o
   GUARD_END(c)
 }
 
-const char* pff_last_error(const pff_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* pff_last_error(const pff_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 }  // extern "C"

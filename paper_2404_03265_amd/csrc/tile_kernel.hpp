@@ -46,6 +46,7 @@ enum Epi : int { EPI_PLAIN = 0, EPI_RESID = 1, EPI_CHEB = 2, EPI_CHEB_FIRST = 3 
 template <typename T>
 struct TileArgs {
   int tile_base;               // this launch handles tiles tile_base + [0, gridDim.x)
+  const int32_t* tile_list;    // nullable: the launch handles tile_list[tile_base + [0, gridDim.x)]
   const int32_t* tile_info;
   const int32_t* shared;       // global ids of the tiles' shared local nodes
   const uint16_t* cell_loc;       // own nodes per cell (hanging nodes included)
@@ -248,6 +249,203 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
   }
 }
 
+
+// One cell of an operator mode: gather(f, u) fetches the cell's nodal values
+// of staged field f, out receives the cell's contributions to its (p+1)^2
+// nodes (per component). H: the cell edge; hang: the per-cell constraint form
+// of the inverse diagonal.
+template <int P, typename T, int MODE, class Gather>
+__device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool hang, unsigned info, Gather&& gather,
+                                             T (&out)[3][(P + 1) * (P + 1)]) {
+  constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
+  using TR = ModeTraits<MODE>;
+  const Material& m = a.mat;
+  const T kap = T(m.kappa), pr = T(m.pressure), Gc = T(m.Gc), ell = T(m.ell);
+  const T mu = T(m.mu), lam = T(m.lam);
+  (void)info;
+  (void)hang;
+  T wq[NQ];
+#pragma unroll
+  for (int qy = 0; qy < N1; ++qy)
+#pragma unroll
+    for (int qx = 0; qx < N1; ++qx) wq[qy * N1 + qx] = a.B.w[qx] * a.B.w[qy];
+  const T invH = T(1) / H;
+
+  if constexpr (MODE == MODE_J || MODE == MODE_LEVEL) {
+    jacobian_cell<P, T, MODE == MODE_J>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
+  } else if constexpr (MODE == MODE_JT || MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
+    // state-derived coefficients at the Gauss points:
+    //   g = (1-k) phit^2 + k, c1 = (1-k) S + 2 p tr e(u) + Gc/l,
+    //   B = 2 (1-k) phi sigma(u) + 2 p phi I (coupling, leaf only)
+    constexpr int SU = TR::n_src;
+    T cg[NQ], cc1[NQ], bxx[NQ], byy[NQ], bxy[NQ];
+    {
+      T u[NL], gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pq[NQ], tq[NQ];
+      gather(SU + 0, u);
+      interp_g<P, T>(a.B, u, gx1, gy1);
+      gather(SU + 1, u);
+      interp_g<P, T>(a.B, u, gx2, gy2);
+      if constexpr (TR::leaf) {
+        gather(SU + 2, u);
+        interp_v<P, T>(a.B, u, pq);
+        gather(SU + 3, u);
+        interp_v<P, T>(a.B, u, tq);
+      } else {
+        gather(SU + 2, u);
+        interp_v<P, T>(a.B, u, tq);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
+        const T tr = exx + eyy;
+        const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+        const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
+        cg[q] = (T(1) - kap) * tq[q] * tq[q] + kap;
+        cc1[q] = (T(1) - kap) * S + T(2) * pr * tr + Gc / ell;
+        if constexpr (TR::leaf) {
+          const T ph = pq[q];
+          bxx[q] = T(2) * (T(1) - kap) * ph * sxx + T(2) * pr * ph;
+          byy[q] = T(2) * (T(1) - kap) * ph * syy + T(2) * pr * ph;
+          bxy[q] = T(2) * (T(1) - kap) * ph * sxy;
+        } else {
+          bxx[q] = byy[q] = bxy[q] = T(0);
+        }
+      }
+    }
+    if constexpr (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
+      // diagonal of the block-diagonal part for each local master dof:
+      // interpolate the (hanging-mapped) unit vector and evaluate the forms
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        T u[NL], vq[NQ], gxq[NQ], gyq[NQ];
+#pragma unroll
+        for (int j = 0; j < NL; ++j) u[j] = (j == k) ? T(1) : T(0);
+        if (hang) hang_apply<P, T>(a.B, u, info);
+        interp_vg<P, T>(a.B, u, vq, gxq, gyq);
+        T dux = T(0), duy = T(0), dph = T(0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const T gx = gxq[q] * invH, gy = gyq[q] * invH, JxW = H * H * wq[q];
+          dux += JxW * cg[q] * ((T(2) * mu + lam) * gx * gx + mu * gy * gy);
+          duy += JxW * cg[q] * (mu * gx * gx + (T(2) * mu + lam) * gy * gy);
+          dph += JxW * (cc1[q] * vq[q] * vq[q] + Gc * ell * (gx * gx + gy * gy));
+        }
+        out[0][k] = dux;
+        out[1][k] = duy;
+        out[2][k] = dph;
+      }
+    } else {
+      // transpose of the Jacobian: the coupling moves to the u rows,
+      //   u rows: g sigma(s_u) : grad psi + s_phi B : grad psi
+      T gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pv[NQ], px[NQ], py[NQ];
+      {
+        T u[NL];
+        gather(0, u);
+        interp_g<P, T>(a.B, u, gx1, gy1);
+        gather(1, u);
+        interp_g<P, T>(a.B, u, gx2, gy2);
+        gather(2, u);
+        interp_vg<P, T>(a.B, u, pv, px, py);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
+        const T tr = exx + eyy;
+        const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+        const T wg = H * wq[q];
+        const T gq = cg[q];
+        gx1[q] = wg * (gq * sxx + pv[q] * bxx[q]);
+        gy1[q] = wg * (gq * sxy + pv[q] * bxy[q]);
+        gx2[q] = wg * (gq * sxy + pv[q] * bxy[q]);
+        gy2[q] = wg * (gq * syy + pv[q] * byy[q]);
+        pv[q] = H * H * wq[q] * cc1[q] * pv[q];
+        px[q] = wq[q] * Gc * ell * px[q];
+        py[q] = wq[q] * Gc * ell * py[q];
+      }
+      integrate_g<P, T>(a.B, gx1, gy1, out[0]);
+      integrate_g<P, T>(a.B, gx2, gy2, out[1]);
+      integrate<P, T>(a.B, pv, px, py, out[2]);
+    }
+  } else if constexpr (MODE == MODE_RESID || MODE == MODE_DGC || MODE == MODE_DE || MODE == MODE_DP) {
+    // residual F(U) of Problem 2 (phi~ in degradation and u-pressure):
+    //   u rows:   g(phit) sigma(u) : e(psi) + p phit^2 div psi
+    //   phi rows: (1-k) phi S + 2 p phi tr e(u) - (Gc/l)(1 - phi), Gc l grad phi
+    // the parameter derivatives keep the terms linear in Gc, E or p.
+    T gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pv[NQ], px[NQ], py[NQ], tq[NQ];
+    {
+      T u[NL];
+      gather(0, u);
+      interp_g<P, T>(a.B, u, gx1, gy1);
+      gather(1, u);
+      interp_g<P, T>(a.B, u, gx2, gy2);
+      gather(2, u);
+      interp_vg<P, T>(a.B, u, pv, px, py);
+      gather(3, u);
+      interp_v<P, T>(a.B, u, tq);
+    }
+    constexpr T sig = (MODE == MODE_RESID || MODE == MODE_DE) ? T(1) : T(0);
+    const T spr = (MODE == MODE_RESID) ? pr : (MODE == MODE_DP ? T(1) : T(0));
+    const T sgc = (MODE == MODE_RESID) ? Gc : (MODE == MODE_DGC ? T(1) : T(0));
+    const T invE = (MODE == MODE_DE) ? T(1.0 / m.E) : T(1);   // sigma is linear in E at fixed nu
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
+      const T tr = exx + eyy;
+      const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+      const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
+      const T g = (T(1) - kap) * tq[q] * tq[q] + kap;
+      const T ph = pv[q];
+      const T wg = H * wq[q], wv = H * H * wq[q];
+      const T pt2 = spr * tq[q] * tq[q];
+      gx1[q] = wg * (sig * invE * g * sxx + pt2);
+      gy1[q] = wg * (sig * invE * g * sxy);
+      gx2[q] = wg * (sig * invE * g * sxy);
+      gy2[q] = wg * (sig * invE * g * syy + pt2);
+      pv[q] = wv * (sig * invE * (T(1) - kap) * ph * S + spr * T(2) * ph * tr - sgc / ell * (T(1) - ph));
+      px[q] = wq[q] * sgc * ell * px[q];
+      py[q] = wq[q] * sgc * ell * py[q];
+    }
+    integrate_g<P, T>(a.B, gx1, gy1, out[0]);
+    integrate_g<P, T>(a.B, gx2, gy2, out[1]);
+    integrate<P, T>(a.B, pv, px, py, out[2]);
+  } else if constexpr (MODE == MODE_TCVGRAD) {
+    // TCV = int u . grad phi; derivative: (v . grad phi) for u, (u . grad psi) for phi
+    T vx[NQ], vy[NQ], px[NQ], py[NQ], zero[NQ];
+    {
+      T u[NL], d1[NQ], d2[NQ];
+      gather(0, u);
+      interp_v<P, T>(a.B, u, vx);
+      gather(1, u);
+      interp_v<P, T>(a.B, u, vy);
+      gather(2, u);
+      interp_g<P, T>(a.B, u, px, py);
+      (void)d1;
+      (void)d2;
+    }
+    T f0[NQ], f1[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      zero[q] = T(0);
+      const T wv = H * H * wq[q], wg = H * wq[q];
+      f0[q] = wv * px[q] * invH;
+      f1[q] = wv * py[q] * invH;
+      px[q] = wg * vx[q];
+      py[q] = wg * vy[q];
+    }
+    integrate<P, T>(a.B, f0, zero, zero, out[0]);
+    integrate<P, T>(a.B, f1, zero, zero, out[1]);
+    integrate<P, T>(a.B, zero, px, py, out[2]);
+  } else if constexpr (MODE == MODE_MASS) {
+    T f[NQ], zero[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      f[q] = H * H * wq[q];
+      zero[q] = T(0);
+    }
+    integrate<P, T>(a.B, f, zero, zero, out[2]);
+  }
+}
+
 template <int P, typename T, int MODE, int EPI, bool HANG>
 __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
@@ -269,7 +467,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   const int nb = int(gridDim.x), bid = int(blockIdx.x);
   const int xq = nb >> 3, xr = nb & 7, xcd = bid & 7;
   const int order_idx = xcd * xq + (xcd < xr ? xcd : xr) + (bid >> 3);
-  const int tile = a.tile_base + order_idx;
+  const int tile = a.tile_list ? a.tile_list[a.tile_base + order_idx] : a.tile_base + order_idx;
   // the whole tile header goes into scalar registers in one batch of loads;
   // reading it field by field under the branches below would serialise a
   // scalar-load round trip per run
@@ -498,186 +696,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         for (int k = 0; k < NL; ++k) u[k] = T(lds[field * ML + loc[k]]);
         if (hang) hang_apply<P, T>(a.B, u, info);
       };
-      T wq[NQ];
-#pragma unroll
-      for (int qy = 0; qy < N1; ++qy)
-#pragma unroll
-        for (int qx = 0; qx < N1; ++qx) wq[qy * N1 + qx] = a.B.w[qx] * a.B.w[qy];
-      const T invH = T(1) / H;
-
-      if constexpr (MODE == MODE_J || MODE == MODE_LEVEL) {
-        jacobian_cell<P, T, MODE == MODE_J>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
-      } else if constexpr (MODE == MODE_JT || MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
-        // state-derived coefficients at the Gauss points:
-        //   g = (1-k) phit^2 + k, c1 = (1-k) S + 2 p tr e(u) + Gc/l,
-        //   B = 2 (1-k) phi sigma(u) + 2 p phi I (coupling, leaf only)
-        constexpr int SU = TR::n_src;
-        T cg[NQ], cc1[NQ], bxx[NQ], byy[NQ], bxy[NQ];
-        {
-          T u[NL], gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pq[NQ], tq[NQ];
-          gather(SU + 0, u);
-          interp_g<P, T>(a.B, u, gx1, gy1);
-          gather(SU + 1, u);
-          interp_g<P, T>(a.B, u, gx2, gy2);
-          if constexpr (TR::leaf) {
-            gather(SU + 2, u);
-            interp_v<P, T>(a.B, u, pq);
-            gather(SU + 3, u);
-            interp_v<P, T>(a.B, u, tq);
-          } else {
-            gather(SU + 2, u);
-            interp_v<P, T>(a.B, u, tq);
-          }
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
-            const T tr = exx + eyy;
-            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
-            const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
-            cg[q] = (T(1) - kap) * tq[q] * tq[q] + kap;
-            cc1[q] = (T(1) - kap) * S + T(2) * pr * tr + Gc / ell;
-            if constexpr (TR::leaf) {
-              const T ph = pq[q];
-              bxx[q] = T(2) * (T(1) - kap) * ph * sxx + T(2) * pr * ph;
-              byy[q] = T(2) * (T(1) - kap) * ph * syy + T(2) * pr * ph;
-              bxy[q] = T(2) * (T(1) - kap) * ph * sxy;
-            } else {
-              bxx[q] = byy[q] = bxy[q] = T(0);
-            }
-          }
-        }
-        if constexpr (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
-          // diagonal of the block-diagonal part for each local master dof:
-          // interpolate the (hanging-mapped) unit vector and evaluate the forms
-#pragma unroll
-          for (int k = 0; k < NL; ++k) {
-            T u[NL], vq[NQ], gxq[NQ], gyq[NQ];
-#pragma unroll
-            for (int j = 0; j < NL; ++j) u[j] = (j == k) ? T(1) : T(0);
-            if (hang) hang_apply<P, T>(a.B, u, info);
-            interp_vg<P, T>(a.B, u, vq, gxq, gyq);
-            T dux = T(0), duy = T(0), dph = T(0);
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-              const T gx = gxq[q] * invH, gy = gyq[q] * invH, JxW = H * H * wq[q];
-              dux += JxW * cg[q] * ((T(2) * mu + lam) * gx * gx + mu * gy * gy);
-              duy += JxW * cg[q] * (mu * gx * gx + (T(2) * mu + lam) * gy * gy);
-              dph += JxW * (cc1[q] * vq[q] * vq[q] + Gc * ell * (gx * gx + gy * gy));
-            }
-            out[0][k] = dux;
-            out[1][k] = duy;
-            out[2][k] = dph;
-          }
-        } else {
-          // transpose of the Jacobian: the coupling moves to the u rows,
-          //   u rows: g sigma(s_u) : grad psi + s_phi B : grad psi
-          T gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pv[NQ], px[NQ], py[NQ];
-          {
-            T u[NL];
-            gather(0, u);
-            interp_g<P, T>(a.B, u, gx1, gy1);
-            gather(1, u);
-            interp_g<P, T>(a.B, u, gx2, gy2);
-            gather(2, u);
-            interp_vg<P, T>(a.B, u, pv, px, py);
-          }
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
-            const T tr = exx + eyy;
-            const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
-            const T wg = H * wq[q];
-            const T gq = cg[q];
-            gx1[q] = wg * (gq * sxx + pv[q] * bxx[q]);
-            gy1[q] = wg * (gq * sxy + pv[q] * bxy[q]);
-            gx2[q] = wg * (gq * sxy + pv[q] * bxy[q]);
-            gy2[q] = wg * (gq * syy + pv[q] * byy[q]);
-            pv[q] = H * H * wq[q] * cc1[q] * pv[q];
-            px[q] = wq[q] * Gc * ell * px[q];
-            py[q] = wq[q] * Gc * ell * py[q];
-          }
-          integrate_g<P, T>(a.B, gx1, gy1, out[0]);
-          integrate_g<P, T>(a.B, gx2, gy2, out[1]);
-          integrate<P, T>(a.B, pv, px, py, out[2]);
-        }
-      } else if constexpr (MODE == MODE_RESID || MODE == MODE_DGC || MODE == MODE_DE || MODE == MODE_DP) {
-        // residual F(U) of Problem 2 (phi~ in degradation and u-pressure):
-        //   u rows:   g(phit) sigma(u) : e(psi) + p phit^2 div psi
-        //   phi rows: (1-k) phi S + 2 p phi tr e(u) - (Gc/l)(1 - phi), Gc l grad phi
-        // the parameter derivatives keep the terms linear in Gc, E or p.
-        T gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pv[NQ], px[NQ], py[NQ], tq[NQ];
-        {
-          T u[NL];
-          gather(0, u);
-          interp_g<P, T>(a.B, u, gx1, gy1);
-          gather(1, u);
-          interp_g<P, T>(a.B, u, gx2, gy2);
-          gather(2, u);
-          interp_vg<P, T>(a.B, u, pv, px, py);
-          gather(3, u);
-          interp_v<P, T>(a.B, u, tq);
-        }
-        constexpr T sig = (MODE == MODE_RESID || MODE == MODE_DE) ? T(1) : T(0);
-        const T spr = (MODE == MODE_RESID) ? pr : (MODE == MODE_DP ? T(1) : T(0));
-        const T sgc = (MODE == MODE_RESID) ? Gc : (MODE == MODE_DGC ? T(1) : T(0));
-        const T invE = (MODE == MODE_DE) ? T(1.0 / m.E) : T(1);   // sigma is linear in E at fixed nu
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
-          const T tr = exx + eyy;
-          const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
-          const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
-          const T g = (T(1) - kap) * tq[q] * tq[q] + kap;
-          const T ph = pv[q];
-          const T wg = H * wq[q], wv = H * H * wq[q];
-          const T pt2 = spr * tq[q] * tq[q];
-          gx1[q] = wg * (sig * invE * g * sxx + pt2);
-          gy1[q] = wg * (sig * invE * g * sxy);
-          gx2[q] = wg * (sig * invE * g * sxy);
-          gy2[q] = wg * (sig * invE * g * syy + pt2);
-          pv[q] = wv * (sig * invE * (T(1) - kap) * ph * S + spr * T(2) * ph * tr - sgc / ell * (T(1) - ph));
-          px[q] = wq[q] * sgc * ell * px[q];
-          py[q] = wq[q] * sgc * ell * py[q];
-        }
-        integrate_g<P, T>(a.B, gx1, gy1, out[0]);
-        integrate_g<P, T>(a.B, gx2, gy2, out[1]);
-        integrate<P, T>(a.B, pv, px, py, out[2]);
-      } else if constexpr (MODE == MODE_TCVGRAD) {
-        // TCV = int u . grad phi; derivative: (v . grad phi) for u, (u . grad psi) for phi
-        T vx[NQ], vy[NQ], px[NQ], py[NQ], zero[NQ];
-        {
-          T u[NL], d1[NQ], d2[NQ];
-          gather(0, u);
-          interp_v<P, T>(a.B, u, vx);
-          gather(1, u);
-          interp_v<P, T>(a.B, u, vy);
-          gather(2, u);
-          interp_g<P, T>(a.B, u, px, py);
-          (void)d1;
-          (void)d2;
-        }
-        T f0[NQ], f1[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          zero[q] = T(0);
-          const T wv = H * H * wq[q], wg = H * wq[q];
-          f0[q] = wv * px[q] * invH;
-          f1[q] = wv * py[q] * invH;
-          px[q] = wg * vx[q];
-          py[q] = wg * vy[q];
-        }
-        integrate<P, T>(a.B, f0, zero, zero, out[0]);
-        integrate<P, T>(a.B, f1, zero, zero, out[1]);
-        integrate<P, T>(a.B, zero, px, py, out[2]);
-      } else if constexpr (MODE == MODE_MASS) {
-        T f[NQ], zero[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          f[q] = H * H * wq[q];
-          zero[q] = T(0);
-        }
-        integrate<P, T>(a.B, f, zero, zero, out[2]);
-      }
+      compute_cell<P, T, MODE>(a, H, hang, info, gather, out);
     }
     // every gather is done: the accumulators take over the field arrays
     __syncthreads();

@@ -61,6 +61,19 @@ def test_host_only_calls():
     spec = _lib.MeshSpec(30, 1, 1, 16, 2.0, 0.5, 0, 0)      # 30 is not 16 * 2^k
     h = C.c_void_p()
     assert lib.pff_mesh_build(C.byref(spec), C.byref(h)) < 0
+    # a failed pff_create leaves its reason for pff_last_error(NULL) (the mesh
+    # is built on the host before any device work)
+    good = _lib.Params()
+    lib.pff_default_params(C.byref(good))
+    assert lib.pff_create(C.byref(spec), C.byref(good), C.byref(ctx)) == -4
+    assert not ctx.value
+    assert "mesh" in lib.pff_last_error(None).decode()
+    for field, value in (("ls_max", 0), ("gmres_max_its", 0), ("ls_omega", 0.0), ("ls_omega", 1.5)):
+        bad = _lib.Params()
+        lib.pff_default_params(C.byref(bad))
+        setattr(bad, field, value)
+        assert lib.pff_create(C.byref(mspec), C.byref(bad), C.byref(ctx)) == -1, field
+        assert "invalid parameters" in lib.pff_last_error(None).decode()
     spec = _lib.MeshSpec(32, 1, 3, 16, 2.0, 0.5, 0, 0)      # degree 3 is not offered
     assert lib.pff_mesh_build(C.byref(spec), C.byref(h)) < 0
     spec = _lib.MeshSpec(32, 1, 2, 16, 2.0, 0.5, 0, 0)

@@ -313,14 +313,17 @@ def test_mixed_precision_load_step(p):
 
 def test_full_size_vmult_sampled_rows():
     """The benchmark workload (1024 x 1024 base cells + 3 local levels, Q2,
-    20.5 M unknowns) in the benchmark's launch configuration: 600 sampled rows
-    (every class of node included) against the oracle row by row."""
+    20.5 M unknowns) in the benchmark's launch configuration: about 600
+    sampled nodes (every class of node included) against the oracle row by
+    row, for the vmult, its transpose and the residual R = -F(U)."""
     import time
     t0 = time.time()
     c = Case(1024, 3, 2, mask="bernoulli", u_std=1e-4, build_oracle=False, phit="shifted")
     c.load_state()
     src = inputs.random_vector(c.X, c.Y, 1)
     dst = c.g.vmult(c.dev(src)).cpu().numpy()
+    dstT = c.g.vmult_T(c.dev(src)).cpu().numpy()
+    res = c.g.residual(c.dev(c.U_raw)).cpu().numpy()
     print(f"[full] library side done {time.time() - t0:.1f}s", flush=True)
     c.build_oracle(1024, 3, 2, 16, (2.0, 0.5))
     print(f"[full] oracle mesh built {time.time() - t0:.1f}s", flush=True)
@@ -339,10 +342,17 @@ def test_full_size_vmult_sampled_rows():
     rows_g = np.concatenate([pick + k * n for k in range(3)])
     rows_o = np.concatenate([c.g2o[pick] + k * n for k in range(3)])
     ref = c.lp.masked_rows(rows_o, c.to_o(src), c.U_o, c.phit_o, c.active_o)
-    got = dst[rows_g]
+    refT = c.lp.masked_rows(rows_o, c.to_o(src), c.U_o, c.phit_o, c.active_o, transpose=True)
+    refR = c.lp.residual_rows(rows_o, c.U_o, c.phit_o)
     print(f"[full] oracle rows done {time.time() - t0:.1f}s", flush=True)
-    scale = np.abs(dst).max()
-    assert np.abs(got - ref).max() <= 1e-12 * scale
+    assert np.abs(dst[rows_g] - ref).max() <= 1e-12 * np.abs(dst).max()
+    assert np.abs(dstT[rows_g] - refT).max() <= 1e-12 * np.abs(dstT).max()
+    # the residual per block: the u rows carry the pressure term, the phase-
+    # field rows the much larger Gc / l term
+    for b in range(3):
+        sel = slice(b * pick.size, (b + 1) * pick.size)
+        scale = np.abs(res[b * n:(b + 1) * n]).max()
+        assert np.abs(res[rows_g[sel]] - refR[sel]).max() <= 1e-12 * scale, b
 
 
 def test_full_size_vcycle_properties():

@@ -27,8 +27,9 @@ class _Solver:
     def set_params(self, p):
         self.params = p
 
-    def extrapolate_phi(self, a, b, theta):
-        self.calls.append(("extrapolate", float(a[0]), float(b[0]), theta))
+    def extrapolate_phi_load(self, a, b, t_prev2, t_prev, t_next):
+        self.calls.append(("extrapolate", float(a[0]), float(b[0]), (t_prev2, t_prev, t_next)))
+        theta = (t_next - t_prev) / (t_prev - t_prev2)
         return a + theta * (a - b)
 
     def newton_step(self, U, phi_old, phi_tilde, active):
@@ -50,10 +51,11 @@ def test_load_path_phase_fields_and_extrapolation():
     assert [c[1] for c in newton] == pressures
     # phi_old: phi0, then the previous increment's phase field
     assert [c[2] for c in newton] == [1.0, -1.0, -2.0, -4.0]
-    # phi~: phi_old for the first two increments, then extrapolated with
-    # theta = (p_k - p_{k-1}) / (p_{k-1} - p_{k-2})
+    # phi~: phi_old for the first two increments, then extrapolated from the
+    # last two solved steps with the load parameters (p_{k-2}, p_{k-1}, p_k)
+    # (the library forms theta = (p_k - p_{k-1}) / (p_{k-1} - p_{k-2}))
     assert [c[3] for c in newton[:2]] == [1.0, -1.0]
-    assert extra == [("extrapolate", -2.0, -1.0, 2.0), ("extrapolate", -4.0, -2.0, 0.5)]
+    assert extra == [("extrapolate", -2.0, -1.0, (1.0, 2.0, 4.0)), ("extrapolate", -4.0, -2.0, (2.0, 4.0, 5.0))]
     assert [c[3] for c in newton[2:]] == [-4.0, -5.0]
     assert [float(o[2][0]) for o in out] == [1.0, -1.0, -2.0, -4.0]
     assert float(U[2 * n]) == -5.0
@@ -72,3 +74,26 @@ def test_load_path_without_extrapolation_and_step_stop():
     g2 = _Solver(n)
     act, infos = solve_load_step(g2, torch.zeros(3 * n, dtype=torch.float64), phi0, phi0, max_steps=7)
     assert len(infos) == 1 and act.dtype == torch.uint8
+
+
+class _StuckSolver(_Solver):
+    """Newton steps that never meet the tolerance and report that GMRES hit
+    its iteration limit (return code 1)."""
+
+    def newton_step(self, U, phi_old, phi_tilde, active):
+        return {"residual_before": 1.0, "gmres_iterations": 300}, 1
+
+
+def test_load_step_surfaces_return_codes():
+    import pytest
+    from paper_2404_03265_amd.autograd import LoadStepNotConverged
+    n = 2
+    phi0 = torch.zeros(n, dtype=torch.float64)
+    act, infos = solve_load_step(_StuckSolver(n), torch.zeros(3 * n, dtype=torch.float64), phi0, phi0, max_steps=3)
+    assert len(infos) == 3 and all(i["rc"] == 1 for i in infos)
+    assert infos[-1]["converged"] is False
+    with pytest.raises(LoadStepNotConverged, match="warning codes \\[1\\]"):
+        solve_load_step(_StuckSolver(n), torch.zeros(3 * n, dtype=torch.float64), phi0, phi0, max_steps=3,
+                        strict=True)
+    act, infos = solve_load_step(_Solver(n), torch.zeros(3 * n, dtype=torch.float64), phi0, phi0, strict=True)
+    assert infos[-1]["converged"] is True and infos[-1]["rc"] == 0

@@ -794,3 +794,27 @@ def test_level_active_sets_by_hand_q2():
     # of its nodes; (16, 14), (14, 16), (16, 16) couple to subsets of them
     lvl0 = {(a, b) for a in (8, 12, 16) for b in (8, 12, 16)}
     assert sets == [lvl0, lvl1, {(13, 13)}]
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_row_sampled_operators_equal_full_assembly(p, tiny_mesh_factory):
+    """The row-sampled forms used for spot checks at sizes the full assembly
+    cannot reach (rows of J~ src, of J~^T src and of R) equal the same rows
+    of the fully assembled definitions, for rows of every node class (free,
+    Dirichlet, hanging, active, masters of hanging nodes)."""
+    m = tiny_mesh_factory(p)
+    lp = LeafProblem(m, Params(ell=0.3, kappa=1e-3, pressure=0.3))
+    U, phit = _state(m, lp)
+    act = inputs.bernoulli_mask(m.NX, m.NY, 2, 0.2) & ~m.hanging
+    n = m.n_nodes
+    src = inputs.random_vector(m.NX, m.NY, 5)
+    masters = sorted({mm for lst in m.hanging_constraints.values() for mm, _ in lst})
+    nodes = np.unique(np.concatenate([np.flatnonzero(m.hanging)[:6], np.flatnonzero(m.dirichlet)[:6],
+                                      np.flatnonzero(act)[:6], masters[:6], np.arange(0, n, max(1, n // 25))]))
+    rows = np.concatenate([nodes + k * n for k in range(3)])
+    Jt = lp.masked_operator(U, phit, act)
+    assert np.abs(lp.masked_rows(rows, src, U, phit, act) - (Jt @ src)[rows]).max() <= 1e-13 * np.abs(Jt @ src).max()
+    JT = Jt.T.tocsr() @ src
+    assert np.abs(lp.masked_rows(rows, src, U, phit, act, transpose=True) - JT[rows]).max() <= 1e-13 * np.abs(JT).max()
+    R = lp.residual(U, phit)
+    assert np.abs(lp.residual_rows(rows, U, phit) - R[rows]).max() <= 1e-13 * np.abs(R).max()
