@@ -6,7 +6,6 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -18,7 +17,6 @@
 #include "../../include/pff.h"
 #include "mesh.hpp"
 #include "tile_kernel.hpp"
-#include "tile_pipe.hpp"
 #include "util_kernels.hpp"
 #include "coarse_kernel.hpp"
 
@@ -53,14 +51,6 @@ struct DevTiles {
   uint8_t* hang_col = nullptr;
   int n_tiles = 0, max_local = 0, max_cells = 0;
   int64_t n_rec = 0, n_private = 0, n_shared = 0, n_slots = 0;
-  int n_hang_rec = 0;
-  // the persistent double-buffered kernel (tile_pipe_kernel) applies: Q2,
-  // one-wave tiles within its LDS slots; pipe_par_ok[b]: every tile's private
-  // range fits its 256 slots when the field's element parity is b
-  bool pipe_shape_ok = false;
-  bool pipe_par_ok[2] = {false, false};
-  int32_t* runless = nullptr;   // tiles whose shared list is not in header runs
-  int n_runless = 0;
 };
 
 template <typename T>
@@ -182,27 +172,6 @@ DevTiles upload_tiles(const TileSet& t) {
   d.n_private = t.n_private;
   d.n_shared = t.n_shared;
   d.n_slots = t.n_slots;
-  d.n_hang_rec = int(t.hang_col.size());
-  bool shape = t.p == 2 && t.n_tiles > 0 && t.max_cells <= PIPE_CELLS && t.n_shared > 0;
-  bool par0 = true, par1 = true;
-  for (int k = 0; shape && k < t.n_tiles; ++k) {
-    const int32_t* ti = t.tile_info.data() + size_t(TILE_STRIDE) * size_t(k);
-    const int o0 = ti[TILE_OWNED0], no = ti[TILE_NOWNED], ns = ti[TILE_NSHARED];
-    shape = no >= 2 && no <= PIPE_PRIV && ns >= 1 && ns <= PIPE_SH && ti[TILE_NHANG] <= 64 &&
-            ti[TILE_NCELL] >= 1;
-    par0 = par0 && no + (o0 & 1) <= PIPE_PRIV;
-    par1 = par1 && no + ((o0 + 1) & 1) <= PIPE_PRIV;
-  }
-  d.pipe_shape_ok = shape;
-  d.pipe_par_ok[0] = shape && par0;
-  d.pipe_par_ok[1] = shape && par1;
-  if (shape) {
-    std::vector<int32_t> rl;
-    for (int k = 0; k < t.n_tiles; ++k)
-      if (t.tile_info[size_t(TILE_STRIDE) * size_t(k) + TILE_NRUN] == 0) rl.push_back(k);
-    d.n_runless = int(rl.size());
-    d.runless = upload(rl);
-  }
   return d;
 }
 
@@ -319,8 +288,6 @@ struct pff_ctx {
   void* part = nullptr;         // partial sums of shared nodes (largest tile set)
   size_t part_bytes = 0;
   void* scratch_dev = nullptr;  // device address of `scratch` on this context's GPU
-  int n_cu = 0;                 // compute units of the context's GPU
-  bool pipe_enabled = true;     // leaf Jacobian / transpose through tile_pipe_kernel where it applies
   int V_cap = 0;
   // caller-bound workspace (pff_bind_workspace): the work vectors, level
   // vectors and GMRES basis are carved from it instead of allocated
@@ -350,23 +317,6 @@ struct pff_ctx {
   // ---------------------------------------------------------------- tiles --
   // part_buf / part_cap: partial-sum buffer and its size in bytes (nullptr:
   // the context's own)
-  // whether the pipelined kernel can run the leaf operator with these
-  // operand and state pointers: every field's private ranges must fit the
-  // 256 LDS slots at the pointer's element parity, and an operand at an odd
-  // element address would make the first tile's 16-byte loads start before
-  // the array
-  bool pipe_applies(const DevTiles& t, const TileArgs<double>& a) const {
-    if (!pipe_enabled || !t.pipe_shape_ok || n_cu <= 0) return false;
-    if ((reinterpret_cast<uintptr_t>(a.src) & 15u) != 0) return false;
-    for (int f = 0; f < PIPE_NF; ++f) {
-      const double* ep = f < 3 ? a.src + f * a.n : a.st[f - 3];
-      if (!ep) return false;
-      const int par = int((reinterpret_cast<uintptr_t>(ep) >> 3) & 1u);
-      if (f >= 3 && par) return false;
-      if (!t.pipe_par_ok[par]) return false;
-    }
-    return true;
-  }
 
   template <typename T, int MODE, int EPI>
   void launch_tile(const DevTiles& t, const uint8_t* fl, int64_t nn, TileArgs<T>& a, void* part_buf = nullptr,
@@ -412,26 +362,6 @@ struct pff_ctx {
     if (lds > size_t(64 * 1024))
       HIPCHK(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     a.tile_base = 0;
-    if constexpr ((MODE == MODE_J || MODE == MODE_JT) && std::is_same<T, double>::value) {
-      if (p == 2 && pipe_applies(t, a)) {
-        // four one-wave workgroups per CU (LDS: two buffers of 7 fields each)
-        const int nwg = std::min(t.n_tiles, 4 * n_cu);
-        hipLaunchKernelGGL((tile_pipe_kernel<MODE>), dim3(nwg), dim3(64), 0, s, a, a.tile_info, a.shared, a.cell_loc,
-                           a.cell_info, a.flags, a.hang_rec, a.hang_w, a.hang_col, a.dst, a.part, t.n_tiles,
-                           t.n_hang_rec);
-        if (t.n_runless > 0) {
-          // the tiles the pipelined kernel skipped (shared list not in runs)
-          TileArgs<T> b = a;
-          b.tile_list = t.runless;
-          const int threads = std::max(64, ((t.max_cells + 63) / 64) * 64);
-          hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI, false>), dim3(t.n_runless), dim3(threads), lds, s, b);
-        }
-        if (t.n_shared > 0)
-          hipLaunchKernelGGL((shared_fixup<T, MODE, EPI>), dim3(grid_for(t.n_shared)), dim3(256), 0, s, a);
-        HIPCHK(hipGetLastError());
-        return;
-      }
-    }
     if (t.n_tiles > 0) {
       if (p == 1)
         hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI, HANG>), dim3(t.n_tiles), dim3(threads), lds, s, a);
@@ -1320,13 +1250,6 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
                          size_t(COPY_MAX_LEVELS) * size_t(2 * EIG_SC + 4 * EIG_MAX_ITS) * sizeof(double),
                          hipHostMallocDefault));
     HIPCHK(scratch_address(&c->scratch_dev));
-    {
-      int dev = 0;
-      HIPCHK(hipGetDevice(&dev));
-      HIPCHK(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-      const char* e = std::getenv("PFF_PIPELINE");
-      c->pipe_enabled = e && e[0] == '1';
-    }
     (void)n;
   } catch (const std::bad_alloc&) {
     return create_failed(c.release(), PFF_E_NOMEM, "pff_create: device allocation failed");
@@ -1342,7 +1265,7 @@ int pff_destroy(pff_ctx* c) {
   auto f = [](void* p) { if (p) hipFree(p); };
   auto ft = [&](DevTiles& t) {
     f(t.info); f(t.shared); f(t.sh_tab); f(t.loc); f(t.loc_sub); f(t.cinfo);
-    f(t.hang_rec); f(t.hang_w); f(t.hang_col); f(t.runless);
+    f(t.hang_rec); f(t.hang_w); f(t.hang_col);
   };
   ft(c->tiles);
   f(c->flags);

@@ -46,7 +46,6 @@ enum Epi : int { EPI_PLAIN = 0, EPI_RESID = 1, EPI_CHEB = 2, EPI_CHEB_FIRST = 3 
 template <typename T>
 struct TileArgs {
   int tile_base;               // this launch handles tiles tile_base + [0, gridDim.x)
-  const int32_t* tile_list;    // nullable: the launch handles tile_list[tile_base + [0, gridDim.x)]
   const int32_t* tile_info;
   const int32_t* shared;       // global ids of the tiles' shared local nodes
   const uint16_t* cell_loc;       // own nodes per cell (hanging nodes included)
@@ -467,7 +466,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   const int nb = int(gridDim.x), bid = int(blockIdx.x);
   const int xq = nb >> 3, xr = nb & 7, xcd = bid & 7;
   const int order_idx = xcd * xq + (xcd < xr ? xcd : xr) + (bid >> 3);
-  const int tile = a.tile_list ? a.tile_list[a.tile_base + order_idx] : a.tile_base + order_idx;
+  const int tile = a.tile_base + order_idx;
   // the whole tile header goes into scalar registers in one batch of loads;
   // reading it field by field under the branches below would serialise a
   // scalar-load round trip per run
