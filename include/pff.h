@@ -67,11 +67,16 @@ typedef struct pff_ctx pff_ctx;
  * passes refining every cell whose centre lies strictly inside
  * |x| < band_x, |y| < band_y, then 2:1 face balancing. degree = 1 (Q1) or
  * 2 (Q2). tile_x, tile_y: cells per tile along x and y, at most 256 cells
- * per tile (0 = default: 16 x 16 for Q1, 8 x 8 for Q2). */
+ * per tile (0 = default: 16 x 16 for Q1, 8 x 8 for Q2). mg_global != 0 also
+ * builds the levels of global-coarsening multigrid (each level the quadtree
+ * cut off at one depth, a complete mesh with its own hanging nodes; the
+ * uniform levels up to the base mesh are shared with local smoothing, the
+ * finest is the leaf mesh), which pff_params.mg_kind = 1 selects. */
 typedef struct {
   int32_t n_base, n_local, degree, coarse;
   double band_x, band_y;
   int32_t tile_x, tile_y;
+  int32_t mg_global;
 } pff_mesh_spec;
 
 /* Material and solver parameters.
@@ -98,7 +103,15 @@ typedef struct {
  *  lambda + c (phi - phi_old) > 0). 0 (default) takes the per-unknown choice
  *  c_i = 2 |lambda_i / (phi_i - phi_old_i)| (Sec. 2, with c_i * 0 := 0); a
  *  positive value is used as one constant for every unknown (the paper notes
- *  c may be chosen freely). Negative or non-finite: PFF_E_ARG. */
+ *  c may be chosen freely). Negative or non-finite: PFF_E_ARG.
+ *  mg_kind: the multigrid of the block preconditioner. 0 (default): local
+ *  smoothing (Sec. 3.2: level l holds the cells of refinement level l, the
+ *  refinement edge fixed during smoothing). 1: global coarsening (every level
+ *  a complete mesh, the quadtree cut at one depth, smoothed over all its
+ *  unknowns with its own hanging-node constraints; transfers interpolate the
+ *  coarse finite-element function; a coarse phase-field unknown is active if
+ *  any finer unknown its interpolation reaches is). 1 needs a context created
+ *  with pff_mesh_spec.mg_global != 0, else PFF_E_ARG. */
 typedef struct {
   double E, nu, Gc, pressure, kappa, ell;
   int32_t cheb_degree;
@@ -113,6 +126,7 @@ typedef struct {
   int32_t ls_max;
   int32_t vcycle_fp32;
   double pdas_c;
+  int32_t mg_kind;
 } pff_params;
 
 typedef struct {

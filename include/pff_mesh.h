@@ -62,6 +62,19 @@ int pff_mesh_tile_tables(const pff_mesh* m, int32_t level, int64_t* sizes, int32
                          int32_t* shared_ptr, int32_t* shared_slot, uint16_t* cell_loc, uint16_t* cell_loc_sub,
                          uint16_t* cell_info, int32_t* order, uint16_t* hang_rec, double* hang_w, uint8_t* hang_col);
 
+/* Global-coarsening levels (spec.mg_global != 0; PFF_E_ARG otherwise), level
+ * 0 .. n_levels - 1, the last one being the leaf mesh: node count, lattice
+ * coordinates (2 n int32), flags (n bytes: 1 Dirichlet, 2 hanging), leaf node
+ * at each node's position (n int32), and the interpolation from level - 1
+ * (level >= 1; CSR over this level's nodes: ptr n + 1, col and val nnz; NULL
+ * arrays query nnz). */
+int pff_mesh_gc_nodes(const pff_mesh* m, int32_t level, int64_t* n);
+int pff_mesh_gc_coords(const pff_mesh* m, int32_t level, int32_t* xy);
+int pff_mesh_gc_flags(const pff_mesh* m, int32_t level, uint8_t* flags);
+int pff_mesh_gc_leaf_index(const pff_mesh* m, int32_t level, int32_t* idx);
+int pff_mesh_gc_interpolation(const pff_mesh* m, int32_t level, int64_t* nnz, int64_t* ptr, int32_t* col,
+                              double* val);
+
 #ifdef __cplusplus
 }
 #endif

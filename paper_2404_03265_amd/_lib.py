@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(_HERE, "libpff.so")
 class MeshSpec(C.Structure):
     _fields_ = [("n_base", C.c_int32), ("n_local", C.c_int32), ("degree", C.c_int32),
                 ("coarse", C.c_int32), ("band_x", C.c_double), ("band_y", C.c_double),
-                ("tile_x", C.c_int32), ("tile_y", C.c_int32)]
+                ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("mg_global", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -23,7 +23,7 @@ class Params(C.Structure):
                 ("coarse_eig_its", C.c_int32), ("gmres_restart", C.c_int32),
                 ("gmres_max_its", C.c_int32), ("gmres_rtol", C.c_double),
                 ("gmres_atol", C.c_double), ("ls_omega", C.c_double), ("ls_max", C.c_int32),
-                ("vcycle_fp32", C.c_int32), ("pdas_c", C.c_double)]
+                ("vcycle_fp32", C.c_int32), ("pdas_c", C.c_double), ("mg_kind", C.c_int32)]
 
 
 class GmresInfo(C.Structure):
@@ -90,6 +90,11 @@ _SIGS = {
     "pff_mesh_tile_stats": (C.c_int, [VP, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]),
     "pff_mesh_tile_tables": (C.c_int, [VP, C.c_int32, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
+    "pff_mesh_gc_nodes": (C.c_int, [VP, C.c_int32, C.POINTER(C.c_int64)]),
+    "pff_mesh_gc_coords": (C.c_int, [VP, C.c_int32, VP]),
+    "pff_mesh_gc_flags": (C.c_int, [VP, C.c_int32, VP]),
+    "pff_mesh_gc_leaf_index": (C.c_int, [VP, C.c_int32, VP]),
+    "pff_mesh_gc_interpolation": (C.c_int, [VP, C.c_int32, C.POINTER(C.c_int64), VP, VP, VP]),
 }
 
 _lib = None

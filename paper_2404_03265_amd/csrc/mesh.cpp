@@ -282,6 +282,168 @@ void build_tiles(int p, int n_tiles, const std::vector<int32_t>& fp, const std::
   }
 }
 
+// Nodes, hanging-node constraints and tiles of the mesh made of `cells`
+// (2:1-balanced quadtree leaves covering the domain): the leaf mesh, and the
+// cut meshes of global-coarsening multigrid.
+struct Part {
+  int64_t n = 0;
+  int64_t n_cells = 0;
+  std::vector<int32_t> NX, NY;     // by final node id
+  std::vector<uint8_t> flags;      // NODE_DIRICHLET | NODE_HANGING
+  std::vector<Hanging> hanging;    // final ids
+  TileSet tiles;
+  PosIndex pos;                    // temporary ids by position
+  std::vector<int32_t> new_id;     // temporary -> final id
+  int32_t at(int64_t X, int64_t Y) const {
+    int64_t t = pos.find(X, Y);
+    return t < 0 ? -1 : new_id[t];
+  }
+};
+
+bool build_part(int p, int lmax, int64_t coarse, int64_t M, int TX, int TY, std::vector<Cell> cells, Part& out,
+                std::string& error) {
+  auto S = [&](int l) { return int64_t(p) << (lmax - l); };
+  auto ncell = [&](int l) { return int64_t(coarse) << l; };
+  std::unordered_set<uint64_t> leaves;
+  leaves.reserve(cells.size() * 2);
+  for (const Cell& c : cells) leaves.insert(ckey(c.l, c.i, c.j));
+  auto is_leaf = [&](int l, int64_t i, int64_t j) { return leaves.count(ckey(l, i, j)) > 0; };
+  static const int DI[4] = {-1, 1, 0, 0}, DJ[4] = {0, 0, -1, 1};
+  std::sort(cells.begin(), cells.end(), [](const Cell& a, const Cell& c) {
+    if (a.l != c.l) return a.l < c.l;
+    if (a.j != c.j) return a.j < c.j;
+    return a.i < c.i;
+  });
+  out.n_cells = int64_t(cells.size());
+  const int NL = (p + 1) * (p + 1);
+
+  // ---- nodes (temporary numbering by position) ----------------------------
+  const uint64_t W = uint64_t(M) + 1;
+  {
+    std::vector<uint64_t> k;
+    k.reserve(cells.size() * NL);
+    for (const Cell& c : cells) {
+      int64_t Sl = S(c.l), h = Sl / p;
+      for (int bb = 0; bb <= p; ++bb)
+        for (int a = 0; a <= p; ++a) k.push_back(uint64_t(c.j * Sl + bb * h) * W + uint64_t(c.i * Sl + a * h));
+    }
+    out.pos.build(std::move(k), W);
+  }
+  const int64_t nn = out.pos.size();
+  std::vector<int32_t> NXt(nn), NYt(nn);
+  for (int64_t n = 0; n < nn; ++n) { NXt[n] = int32_t(out.pos.X(n)); NYt[n] = int32_t(out.pos.Y(n)); }
+
+  // footprints with hanging substitution
+  std::vector<int32_t> fp(cells.size() * NL), fp_raw(cells.size() * NL);
+  std::vector<uint16_t> info(cells.size());
+  std::unordered_map<int64_t, Hanging> hang_tmp;
+  for (size_t c = 0; c < cells.size(); ++c) {
+    const Cell& C = cells[c];
+    const int64_t Sl = S(C.l), h = Sl / p;
+    uint16_t inf = uint16_t(C.l << CELL_LEVEL_SHIFT);
+    if (C.i & 1) inf |= CELL_CX;
+    if (C.j & 1) inf |= CELL_CY;
+    for (int bb = 0; bb <= p; ++bb)
+      for (int a = 0; a <= p; ++a) fp[c * NL + bb * (p + 1) + a] = int32_t(out.pos.find(C.i * Sl + a * h, C.j * Sl + bb * h));
+    for (int k = 0; k < NL; ++k) fp_raw[c * NL + k] = fp[c * NL + k];
+    for (int d = 0; d < 4; ++d) {
+      int64_t ni = C.i + DI[d], nj = C.j + DJ[d];
+      if (ni < 0 || nj < 0 || ni >= ncell(C.l) || nj >= ncell(C.l)) continue;
+      if (is_leaf(C.l, ni, nj) || C.l == 0 || !is_leaf(C.l - 1, ni >> 1, nj >> 1)) continue;
+      // coarse neighbour: this face is half of the coarse face
+      const int64_t Sc = 2 * Sl, hc = Sc / p;
+      const int sub = (d < 2) ? (C.j & 1) : (C.i & 1);
+      int32_t mast[3];
+      int slot[3];
+      for (int k = 0; k <= p; ++k) {
+        int64_t X, Y;
+        if (d < 2) {  // vertical face
+          X = (C.i + (d == 1 ? 1 : 0)) * Sl;
+          Y = (nj >> 1) * Sc + k * hc;
+          slot[k] = k * (p + 1) + (d == 1 ? p : 0);
+        } else {
+          X = (ni >> 1) * Sc + k * hc;
+          Y = (C.j + (d == 3 ? 1 : 0)) * Sl;
+          slot[k] = (d == 3 ? p : 0) * (p + 1) + k;
+        }
+        mast[k] = int32_t(out.pos.find(X, Y));
+        if (mast[k] < 0) { error = "coarse face node missing"; return false; }
+      }
+      inf |= uint16_t(1u << d);
+      // fine nodes of the face not on a coarse node are hanging
+      for (int t = 0; t <= p; ++t) {
+        int32_t node = fp[c * NL + slot[t]];
+        int num = sub * p + t;  // position along the coarse face in units of S/p ... over 2p
+        if (num % 2 == 0) continue;
+        double sfr = double(num) / double(2 * p);
+        Hanging hg{};
+        hg.node = node;
+        for (int k = 0; k < 3; ++k) { hg.master[k] = -1; hg.weight[k] = 0.0; }
+        for (int k = 0; k <= p; ++k) { hg.master[k] = mast[k]; hg.weight[k] = lagrange(p, k, sfr); }
+        hang_tmp[node] = hg;
+      }
+      for (int k = 0; k <= p; ++k) fp[c * NL + slot[k]] = mast[k];
+    }
+    info[c] = inf;
+  }
+  std::vector<uint8_t> flags_t(nn, 0);
+  for (int64_t n = 0; n < nn; ++n)
+    if (NXt[n] == 0 || NXt[n] == M || NYt[n] == 0 || NYt[n] == M) flags_t[n] |= NODE_DIRICHLET;
+  for (auto& kv : hang_tmp) {
+    flags_t[kv.first] |= NODE_HANGING;
+    for (int k = 0; k <= p; ++k)
+      if (hang_tmp.count(kv.second.master[k])) { error = "chained hanging constraint"; return false; }
+  }
+
+  // ---- tiles -------------------------------------------------------------
+  std::unordered_map<uint64_t, int32_t> tile_of;
+  std::vector<int32_t> cell_tile(cells.size());
+  {
+    std::vector<uint64_t> tkeys;
+    for (const Cell& C : cells) tkeys.push_back(ckey(C.l, C.j / TY, C.i / TX));  // (level, by, bx)
+    std::vector<uint64_t> u = tkeys;
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    for (size_t t = 0; t < u.size(); ++t) tile_of[u[t]] = int32_t(t);
+    for (size_t c = 0; c < cells.size(); ++c) cell_tile[c] = tile_of[tkeys[c]];
+  }
+  const int n_leaf_tiles = int(tile_of.size());
+  std::unordered_map<uint64_t, int32_t> leaf_cell_id;
+  leaf_cell_id.reserve(cells.size() * 2);
+  for (size_t c = 0; c < cells.size(); ++c) leaf_cell_id[ckey(cells[c].l, cells[c].i, cells[c].j)] = int32_t(c);
+  std::vector<int32_t> node_tile(nn, -1);
+  for (int64_t n = 0; n < nn; ++n) {
+    // leaf cell whose half-open box holds the node
+    for (int l = lmax; l >= 0; --l) {
+      int64_t ci = std::min<int64_t>(NXt[n] / S(l), ncell(l) - 1);
+      int64_t cj = std::min<int64_t>(NYt[n] / S(l), ncell(l) - 1);
+      auto it = leaf_cell_id.find(ckey(l, ci, cj));
+      if (it != leaf_cell_id.end()) { node_tile[n] = cell_tile[it->second]; break; }
+    }
+    if (node_tile[n] < 0) { error = "node without owner cell"; return false; }
+  }
+  std::vector<int32_t>& new_id = out.new_id;
+  build_tiles(p, n_leaf_tiles, fp, fp_raw, hang_tmp, info, cell_tile, node_tile, NXt, NYt, out.tiles, new_id);
+  out.n = nn;
+  out.NX.assign(nn, 0);
+  out.NY.assign(nn, 0);
+  out.flags.assign(nn, 0);
+  for (int64_t n = 0; n < nn; ++n) {
+    out.NX[new_id[n]] = NXt[n];
+    out.NY[new_id[n]] = NYt[n];
+    out.flags[new_id[n]] = flags_t[n];
+  }
+  out.hanging.clear();
+  for (auto& kv : hang_tmp) {
+    Hanging hg = kv.second;
+    hg.node = new_id[hg.node];
+    for (int k = 0; k <= p; ++k) hg.master[k] = new_id[hg.master[k]];
+    out.hanging.push_back(hg);
+  }
+  std::sort(out.hanging.begin(), out.hanging.end(), [](const Hanging& a, const Hanging& c) { return a.node < c.node; });
+  return true;
+}
+
 }  // namespace
 
 bool Mesh::build(const MeshSpec& s) {
@@ -364,143 +526,18 @@ bool Mesh::build(const MeshSpec& s) {
   cells.reserve(leaves.size());
   for (uint64_t key : leaves)
     cells.push_back({int(key >> 58), int32_t((key >> 29) & ((1u << 29) - 1)), int32_t(key & ((1u << 29) - 1))});
-  std::sort(cells.begin(), cells.end(), [](const Cell& a, const Cell& c) {
-    if (a.l != c.l) return a.l < c.l;
-    if (a.j != c.j) return a.j < c.j;
-    return a.i < c.i;
-  });
-  n_leaf_cells = int64_t(cells.size());
+  Part leaf;
+  if (!build_part(p, lmax, s.coarse, M, TX, TY, cells, leaf, error)) return false;
+  n_leaf_cells = leaf.n_cells;
+  n_nodes = leaf.n;
+  NX = leaf.NX;
+  NY = leaf.NY;
+  flags = leaf.flags;
+  hanging = leaf.hanging;
+  tiles = std::move(leaf.tiles);
   const int NL = (p + 1) * (p + 1);
-
-  // ---- leaf nodes (temporary numbering by position) -----------------------
   const uint64_t W = uint64_t(M) + 1;
-  PosIndex pos;
-  {
-    std::vector<uint64_t> k;
-    k.reserve(cells.size() * NL);
-    for (const Cell& c : cells) {
-      int64_t Sl = S(c.l), h = Sl / p;
-      for (int bb = 0; bb <= p; ++bb)
-        for (int a = 0; a <= p; ++a) k.push_back(uint64_t(c.j * Sl + bb * h) * W + uint64_t(c.i * Sl + a * h));
-    }
-    pos.build(std::move(k), W);
-  }
-  const int64_t nn = pos.size();
-  std::vector<int32_t> NXt(nn), NYt(nn);
-  for (int64_t n = 0; n < nn; ++n) { NXt[n] = int32_t(pos.X(n)); NYt[n] = int32_t(pos.Y(n)); }
-
-  // footprints with hanging substitution
-  std::vector<int32_t> fp(cells.size() * NL), fp_raw(cells.size() * NL);
-  std::vector<uint16_t> info(cells.size());
-  std::unordered_map<int64_t, Hanging> hang_tmp;
-  for (size_t c = 0; c < cells.size(); ++c) {
-    const Cell& C = cells[c];
-    const int64_t Sl = S(C.l), h = Sl / p;
-    uint16_t inf = uint16_t(C.l << CELL_LEVEL_SHIFT);
-    if (C.i & 1) inf |= CELL_CX;
-    if (C.j & 1) inf |= CELL_CY;
-    for (int bb = 0; bb <= p; ++bb)
-      for (int a = 0; a <= p; ++a) fp[c * NL + bb * (p + 1) + a] = int32_t(pos.find(C.i * Sl + a * h, C.j * Sl + bb * h));
-    for (int k = 0; k < NL; ++k) fp_raw[c * NL + k] = fp[c * NL + k];
-    for (int d = 0; d < 4; ++d) {
-      int64_t ni = C.i + DI[d], nj = C.j + DJ[d];
-      if (ni < 0 || nj < 0 || ni >= ncell(C.l) || nj >= ncell(C.l)) continue;
-      if (is_leaf(C.l, ni, nj) || C.l == 0 || !is_leaf(C.l - 1, ni >> 1, nj >> 1)) continue;
-      // coarse neighbour: this face is half of the coarse face
-      const int64_t Sc = 2 * Sl, hc = Sc / p;
-      const int sub = (d < 2) ? (C.j & 1) : (C.i & 1);
-      int32_t mast[3];
-      int slot[3];
-      for (int k = 0; k <= p; ++k) {
-        int64_t X, Y;
-        if (d < 2) {  // vertical face
-          X = (C.i + (d == 1 ? 1 : 0)) * Sl;
-          Y = (nj >> 1) * Sc + k * hc;
-          slot[k] = k * (p + 1) + (d == 1 ? p : 0);
-        } else {
-          X = (ni >> 1) * Sc + k * hc;
-          Y = (C.j + (d == 3 ? 1 : 0)) * Sl;
-          slot[k] = (d == 3 ? p : 0) * (p + 1) + k;
-        }
-        mast[k] = int32_t(pos.find(X, Y));
-        if (mast[k] < 0) { error = "coarse face node missing"; return false; }
-      }
-      inf |= uint16_t(1u << d);
-      // fine nodes of the face not on a coarse node are hanging
-      for (int t = 0; t <= p; ++t) {
-        int32_t node = fp[c * NL + slot[t]];
-        int num = sub * p + t;  // position along the coarse face in units of S/p ... over 2p
-        if (num % 2 == 0) continue;
-        double sfr = double(num) / double(2 * p);
-        Hanging hg{};
-        hg.node = node;
-        for (int k = 0; k < 3; ++k) { hg.master[k] = -1; hg.weight[k] = 0.0; }
-        for (int k = 0; k <= p; ++k) { hg.master[k] = mast[k]; hg.weight[k] = lagrange(p, k, sfr); }
-        hang_tmp[node] = hg;
-      }
-      for (int k = 0; k <= p; ++k) fp[c * NL + slot[k]] = mast[k];
-    }
-    info[c] = inf;
-  }
-  std::vector<uint8_t> flags_t(nn, 0);
-  for (int64_t n = 0; n < nn; ++n)
-    if (NXt[n] == 0 || NXt[n] == M || NYt[n] == 0 || NYt[n] == M) flags_t[n] |= NODE_DIRICHLET;
-  for (auto& kv : hang_tmp) {
-    flags_t[kv.first] |= NODE_HANGING;
-    for (int k = 0; k <= p; ++k)
-      if (hang_tmp.count(kv.second.master[k])) { error = "chained hanging constraint"; return false; }
-  }
-
-  // ---- leaf tiles --------------------------------------------------------
-  std::unordered_map<uint64_t, int32_t> tile_of;
-  std::vector<int32_t> cell_tile(cells.size());
-  {
-    std::vector<uint64_t> tkeys;
-    for (const Cell& C : cells) tkeys.push_back(ckey(C.l, C.j / TY, C.i / TX));  // (level, by, bx)
-    std::vector<uint64_t> u = tkeys;
-    std::sort(u.begin(), u.end());
-    u.erase(std::unique(u.begin(), u.end()), u.end());
-    for (size_t t = 0; t < u.size(); ++t) tile_of[u[t]] = int32_t(t);
-    for (size_t c = 0; c < cells.size(); ++c) cell_tile[c] = tile_of[tkeys[c]];
-  }
-  const int n_leaf_tiles = int(tile_of.size());
-  std::unordered_map<uint64_t, int32_t> leaf_cell_id;
-  leaf_cell_id.reserve(cells.size() * 2);
-  for (size_t c = 0; c < cells.size(); ++c) leaf_cell_id[ckey(cells[c].l, cells[c].i, cells[c].j)] = int32_t(c);
-  std::vector<int32_t> node_tile(nn, -1);
-  for (int64_t n = 0; n < nn; ++n) {
-    // leaf cell whose half-open box holds the node
-    for (int l = lmax; l >= 0; --l) {
-      int64_t ci = std::min<int64_t>(NXt[n] / S(l), ncell(l) - 1);
-      int64_t cj = std::min<int64_t>(NYt[n] / S(l), ncell(l) - 1);
-      auto it = leaf_cell_id.find(ckey(l, ci, cj));
-      if (it != leaf_cell_id.end()) { node_tile[n] = cell_tile[it->second]; break; }
-    }
-    if (node_tile[n] < 0) { error = "node without owner cell"; return false; }
-  }
-  std::vector<int32_t> new_id;
-  build_tiles(p, n_leaf_tiles, fp, fp_raw, hang_tmp, info, cell_tile, node_tile, NXt, NYt, tiles, new_id);
-  n_nodes = nn;
-  NX.assign(nn, 0);
-  NY.assign(nn, 0);
-  flags.assign(nn, 0);
-  for (int64_t n = 0; n < nn; ++n) {
-    NX[new_id[n]] = NXt[n];
-    NY[new_id[n]] = NYt[n];
-    flags[new_id[n]] = flags_t[n];
-  }
-  hanging.clear();
-  for (auto& kv : hang_tmp) {
-    Hanging hg = kv.second;
-    hg.node = new_id[hg.node];
-    for (int k = 0; k <= p; ++k) hg.master[k] = new_id[hg.master[k]];
-    hanging.push_back(hg);
-  }
-  std::sort(hanging.begin(), hanging.end(), [](const Hanging& a, const Hanging& c) { return a.node < c.node; });
-  auto leaf_node_at = [&](int64_t X, int64_t Y) -> int32_t {
-    int64_t t = pos.find(X, Y);
-    return t < 0 ? -1 : new_id[t];
-  };
+  auto leaf_node_at = [&](int64_t X, int64_t Y) -> int32_t { return leaf.at(X, Y); };
 
   // ---- levels ------------------------------------------------------------
   levels.assign(n_levels, Level());
@@ -647,6 +684,120 @@ bool Mesh::build(const MeshSpec& s) {
         int64_t q = fill[L.P.col[e]]++;
         L.PT.col[q] = int32_t(r);
         L.PT.val[q] = L.P.val[e];
+      }
+  }
+  if (!s.mg_global) return true;
+
+  // ---- global-coarsening levels ------------------------------------------
+  // level k: the leaves cut off at depth k; k <= b: the uniform level-k mesh
+  // (shared with the local-smoothing level), k = lmax: the leaf mesh
+  gc.assign(n_levels, GcLevel());
+  std::vector<Part> parts(n_levels);
+  std::vector<std::unordered_set<uint64_t>> cut(n_levels);
+  for (int k = 0; k < n_levels; ++k) {
+    GcLevel& G = gc[k];
+    G.level = k;
+    if (k == lmax) {
+      G.n = n_nodes;
+      continue;
+    }
+    if (k <= b) {
+      G.n = levels[k].n;
+      continue;
+    }
+    for (const Cell& C : cells) {
+      const int l = std::min(C.l, k);
+      cut[k].insert(ckey(l, C.i >> (C.l - l), C.j >> (C.l - l)));
+    }
+    std::vector<Cell> ck;
+    ck.reserve(cut[k].size());
+    for (uint64_t key : cut[k])
+      ck.push_back({int(key >> 58), int32_t((key >> 29) & ((1u << 29) - 1)), int32_t(key & ((1u << 29) - 1))});
+    if (!build_part(p, lmax, s.coarse, M, TX, TY, ck, parts[k], error)) return false;
+    Part& P = parts[k];
+    G.own = true;
+    G.n = P.n;
+    G.NX = P.NX;
+    G.NY = P.NY;
+    G.flags = P.flags;
+    G.tiles = std::move(P.tiles);
+    G.leaf_index.assign(P.n, -1);
+    for (int64_t g = 0; g < P.n; ++g) {
+      G.leaf_index[g] = leaf_node_at(P.NX[g], P.NY[g]);
+      if (G.leaf_index[g] < 0) { error = "global-coarsening node is not a leaf position"; return false; }
+    }
+  }
+  // interpolation k-1 -> k for the levels above the base mesh and for the
+  // leaf level (the uniform levels below use levels[k].P)
+  for (int k = std::min(b + 1, lmax); k < n_levels; ++k) {
+    if (k == 0) continue;
+    GcLevel& G = gc[k];
+    const int kc = k - 1;
+    // coarse level: cell set and node id by position
+    auto coarse_has = [&](int l, int64_t i, int64_t j) {
+      if (i < 0 || j < 0 || i >= ncell(l) || j >= ncell(l)) return false;
+      if (kc <= b) return l == kc;
+      return cut[kc].count(ckey(l, i, j)) > 0;
+    };
+    auto coarse_node = [&](int64_t X, int64_t Y) -> int32_t {
+      if (kc <= b) {
+        const int64_t t = lev_pos[kc].find(X, Y);
+        return t < 0 ? -1 : lev_new[kc][t];
+      }
+      return parts[kc].at(X, Y);
+    };
+    const std::vector<int32_t>& FX = k == lmax ? NX : G.NX;
+    const std::vector<int32_t>& FY = k == lmax ? NY : G.NY;
+    G.P.rows = G.n;
+    G.P.ptr.assign(G.n + 1, 0);
+    G.P.col.clear();
+    G.P.val.clear();
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t g = 0; g < G.n; ++g) {
+      const int64_t X = FX[g], Y = FY[g];
+      int cl = -1;
+      int64_t ci = 0, cj = 0;
+      for (int l = kc; l >= 0 && cl < 0; --l) {
+        const int64_t Sl = S(l);
+        int64_t is[2], js[2];
+        int ni = 0, nj = 0;
+        is[ni++] = X / Sl;
+        if (X % Sl == 0) is[ni++] = X / Sl - 1;
+        js[nj++] = Y / Sl;
+        if (Y % Sl == 0) js[nj++] = Y / Sl - 1;
+        for (int a = 0; a < ni && cl < 0; ++a)
+          for (int c2 = 0; c2 < nj && cl < 0; ++c2)
+            if (coarse_has(l, is[a], js[c2])) { cl = l; ci = is[a]; cj = js[c2]; }
+      }
+      if (cl < 0) { error = "global-coarsening node outside the coarse level"; return false; }
+      const int64_t Sc = S(cl), hc = Sc / p;
+      row.clear();
+      for (int cb = 0; cb <= p; ++cb)
+        for (int ca = 0; ca <= p; ++ca) {
+          const double w = lagrange(p, ca, double(X - ci * Sc) / double(Sc)) *
+                           lagrange(p, cb, double(Y - cj * Sc) / double(Sc));
+          if (w == 0.0) continue;
+          const int32_t cn = coarse_node(ci * Sc + ca * hc, cj * Sc + cb * hc);
+          if (cn < 0) { error = "global-coarsening coarse node missing"; return false; }
+          row.push_back({cn, w});
+        }
+      std::sort(row.begin(), row.end());
+      G.P.ptr[g + 1] = G.P.ptr[g] + int64_t(row.size());
+      for (auto& e : row) { G.P.col.push_back(e.first); G.P.val.push_back(e.second); }
+    }
+    const int64_t nc = gc[kc].n;
+    G.PT.rows = nc;
+    G.PT.ptr.assign(nc + 1, 0);
+    for (int32_t cidx : G.P.col) G.PT.ptr[cidx + 1]++;
+    for (int64_t r = 0; r < nc; ++r) G.PT.ptr[r + 1] += G.PT.ptr[r];
+    G.PT.col.assign(G.P.col.size(), 0);
+    G.PT.val.assign(G.P.col.size(), 0.0);
+    std::vector<int64_t> fill(G.PT.ptr.begin(), G.PT.ptr.end() - 1);
+    for (int64_t r = 0; r < G.n; ++r)
+      for (int64_t e = G.P.ptr[r]; e < G.P.ptr[r + 1]; ++e) {
+        int64_t q = fill[G.P.col[e]]++;
+        G.PT.col[q] = int32_t(r);
+        G.PT.val[q] = G.P.val[e];
       }
   }
   return true;

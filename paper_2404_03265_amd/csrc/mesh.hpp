@@ -108,6 +108,25 @@ struct Level {
   Csr PT;   // its transpose (rows: level-1 nodes)
 };
 
+// A level of global-coarsening multigrid: the quadtree cut off at depth
+// `level` (leaves finer than that replaced by their ancestor), a complete
+// mesh of the domain with its own hanging nodes. Levels up to the base mesh
+// are uniform and identical to the local-smoothing levels (own = false: the
+// tables of Mesh::levels serve both); the last level is the leaf mesh itself
+// (own = false as well). P interpolates the previous level's finite-element
+// function at this level's nodes (rows: this level's nodes); PT is its
+// transpose.
+struct GcLevel {
+  int level = 0;
+  bool own = false;
+  int64_t n = 0;
+  std::vector<int32_t> NX, NY;
+  std::vector<uint8_t> flags;       // NODE_DIRICHLET | NODE_HANGING
+  std::vector<int32_t> leaf_index;  // leaf node at the same position
+  TileSet tiles;
+  Csr P, PT;
+};
+
 struct Hanging {
   int32_t node;
   int32_t master[3];
@@ -123,6 +142,7 @@ struct MeshSpec {
   double band_y = 0.5;
   int tile_x = 0;  // cells per tile in x (0 = default for the degree)
   int tile_y = 0;
+  bool mg_global = false;  // also build the global-coarsening levels
 };
 
 struct Mesh {
@@ -137,6 +157,7 @@ struct Mesh {
   std::vector<double> level_H;   // physical cell edge per level
   TileSet tiles;                 // leaf operator tiles
   std::vector<Level> levels;
+  std::vector<GcLevel> gc;       // global-coarsening levels (spec.mg_global)
   std::string error;
 
   bool build(const MeshSpec& s);

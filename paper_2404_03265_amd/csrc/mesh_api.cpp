@@ -19,7 +19,21 @@ pff::MeshSpec to_spec(const pff_mesh_spec* s) {
   ms.band_y = s->band_y;
   ms.tile_x = s->tile_x;
   ms.tile_y = s->tile_y;
+  ms.mg_global = s->mg_global != 0;
   return ms;
+}
+bool bad_gc(const pff_mesh* m, int32_t level) {
+  return !m || m->m.gc.empty() || level < 0 || level >= int32_t(m->m.gc.size());
+}
+// coordinates, flags and leaf positions of a global-coarsening level: its own
+// tables, the shared local-smoothing level, or the leaf mesh
+const std::vector<int32_t>& gc_x(const pff::Mesh& M, int k) {
+  const pff::GcLevel& G = M.gc[k];
+  return G.own ? G.NX : (k == M.lmax ? M.NX : M.levels[k].NX);
+}
+const std::vector<int32_t>& gc_y(const pff::Mesh& M, int k) {
+  const pff::GcLevel& G = M.gc[k];
+  return G.own ? G.NY : (k == M.lmax ? M.NY : M.levels[k].NY);
 }
 bool bad_level(const pff_mesh* m, int32_t level) {
   return !m || level < -1 || level >= int32_t(m->m.levels.size());
@@ -151,6 +165,57 @@ int pff_mesh_tile_tables(const pff_mesh* m, int32_t level, int64_t* sizes, int32
   put(hang_rec, t.hang_rec);
   put(hang_w, t.hang_w);
   put(hang_col, t.hang_col);
+  return PFF_OK;
+}
+
+int pff_mesh_gc_nodes(const pff_mesh* m, int32_t level, int64_t* n) {
+  if (bad_gc(m, level) || !n) return PFF_E_ARG;
+  *n = m->m.gc[level].n;
+  return PFF_OK;
+}
+
+int pff_mesh_gc_coords(const pff_mesh* m, int32_t level, int32_t* xy) {
+  if (bad_gc(m, level) || !xy) return PFF_E_ARG;
+  const auto& X = gc_x(m->m, level);
+  const auto& Y = gc_y(m->m, level);
+  std::memcpy(xy, X.data(), X.size() * sizeof(int32_t));
+  std::memcpy(xy + X.size(), Y.data(), Y.size() * sizeof(int32_t));
+  return PFF_OK;
+}
+
+int pff_mesh_gc_flags(const pff_mesh* m, int32_t level, uint8_t* flags) {
+  if (bad_gc(m, level) || !flags) return PFF_E_ARG;
+  const pff::Mesh& M = m->m;
+  const pff::GcLevel& G = M.gc[level];
+  const int64_t n = G.n;
+  for (int64_t i = 0; i < n; ++i) {
+    uint8_t f;
+    if (G.own) f = G.flags[i];
+    else if (level == M.lmax) f = M.flags[i];
+    else f = M.levels[level].flags[i];
+    flags[i] = uint8_t(f & (pff::NODE_DIRICHLET | pff::NODE_HANGING));
+  }
+  return PFF_OK;
+}
+
+int pff_mesh_gc_leaf_index(const pff_mesh* m, int32_t level, int32_t* idx) {
+  if (bad_gc(m, level) || !idx) return PFF_E_ARG;
+  const pff::Mesh& M = m->m;
+  const pff::GcLevel& G = M.gc[level];
+  for (int64_t i = 0; i < G.n; ++i)
+    idx[i] = G.own ? G.leaf_index[i] : (level == M.lmax ? int32_t(i) : M.levels[level].leaf_index[i]);
+  return PFF_OK;
+}
+
+int pff_mesh_gc_interpolation(const pff_mesh* m, int32_t level, int64_t* nnz, int64_t* ptr, int32_t* col,
+                              double* val) {
+  if (bad_gc(m, level) || level < 1 || !nnz) return PFF_E_ARG;
+  const pff::Mesh& M = m->m;
+  const pff::Csr& P = (level <= M.b && level < M.lmax) ? M.levels[level].P : M.gc[level].P;
+  *nnz = int64_t(P.col.size());
+  if (ptr) std::memcpy(ptr, P.ptr.data(), P.ptr.size() * sizeof(int64_t));
+  if (col) std::memcpy(col, P.col.data(), P.col.size() * sizeof(int32_t));
+  if (val) std::memcpy(val, P.val.data(), P.val.size() * sizeof(double));
   return PFF_OK;
 }
 

@@ -13,9 +13,9 @@ def _np(a):
 
 
 class HostMesh:
-    def __init__(self, n_base, n_local, degree, coarse=16, band=(2.0, 0.5), tile=(0, 0)):
+    def __init__(self, n_base, n_local, degree, coarse=16, band=(2.0, 0.5), tile=(0, 0), mg_global=False):
         self.lib = _lib.load()
-        spec = _lib.MeshSpec(n_base, n_local, degree, coarse, band[0], band[1], tile[0], tile[1])
+        spec = _lib.MeshSpec(n_base, n_local, degree, coarse, band[0], band[1], tile[0], tile[1], int(mg_global))
         h = C.c_void_p()
         rc = self.lib.pff_mesh_build(C.byref(spec), C.byref(h))
         if rc != 0:
@@ -104,3 +104,35 @@ class HostMesh:
                 "order", "hang_rec", "hang_w", "hang_col")
         assert self.lib.pff_mesh_tile_tables(self.h, level, _np(sz), *[_np(t[k]) for k in keys]) == 0
         return t
+
+    # ---- global-coarsening levels (mg_global=True) -----------------------
+    def gc_nodes(self, level):
+        n = C.c_int64()
+        assert self.lib.pff_mesh_gc_nodes(self.h, level, C.byref(n)) == 0
+        return n.value
+
+    def gc_coords(self, level):
+        xy = np.zeros(2 * self.gc_nodes(level), dtype=np.int32)
+        assert self.lib.pff_mesh_gc_coords(self.h, level, _np(xy)) == 0
+        return xy.reshape(2, -1)
+
+    def gc_flags(self, level):
+        f = np.zeros(self.gc_nodes(level), dtype=np.uint8)
+        assert self.lib.pff_mesh_gc_flags(self.h, level, _np(f)) == 0
+        return f
+
+    def gc_leaf_index(self, level):
+        idx = np.zeros(self.gc_nodes(level), dtype=np.int32)
+        assert self.lib.pff_mesh_gc_leaf_index(self.h, level, _np(idx)) == 0
+        return idx
+
+    def gc_interpolation(self, level):
+        """CSR (ptr, col, val) of the interpolation from level - 1."""
+        nnz = C.c_int64()
+        assert self.lib.pff_mesh_gc_interpolation(self.h, level, C.byref(nnz), None, None, None) == 0
+        n = self.gc_nodes(level)
+        ptr = np.zeros(n + 1, dtype=np.int64)
+        col = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(nnz.value, dtype=np.float64)
+        assert self.lib.pff_mesh_gc_interpolation(self.h, level, C.byref(nnz), _np(ptr), _np(col), _np(val)) == 0
+        return ptr, col, val

@@ -113,3 +113,45 @@ def test_every_free_leaf_node_copied_once(pair):
         np.add.at(hits, li[(f & 32) != 0], 1)
     hang = (hm.flags() & 2) != 0
     assert np.all(hits[~hang] == 1) and np.all(hits[hang] == 0)
+
+
+# ---- global-coarsening levels ---------------------------------------------
+GC_CASES = [CASES[0], CASES[2], CASES[3], CASES[4]]
+
+
+@pytest.mark.parametrize("ci", range(len(GC_CASES)))
+@pytest.mark.parametrize("p", (1, 2))
+def test_global_coarsening_levels_match_oracle(ci, p):
+    """Every global-coarsening level of the library (node positions, Dirichlet
+    and hanging flags, leaf position of each node, interpolation from the
+    level below) against the oracle's cut meshes, matched by lattice
+    coordinates; the interpolation weights are exact dyadic values."""
+    import scipy.sparse as sp
+    from oracle.gc import GlobalHierarchy
+    c = GC_CASES[ci]
+    om = Mesh(c["n_base"], c["n_local"], p, coarse=c["coarse"], band=c["band"])
+    gh = GlobalHierarchy(om)
+    hm = lib_mod.HostMesh(c["n_base"], c["n_local"], p, coarse=c["coarse"], band=c["band"], mg_global=True)
+    assert len(gh.meshes) == hm.n_levels
+    maps = []
+    for k, m in enumerate(gh.meshes):
+        X, Y = hm.gc_coords(k)
+        assert X.size == m.n_nodes
+        kh = _key(X, Y, hm.M)
+        ko = _key(m.NX, m.NY, m.M)
+        pos = {int(v): i for i, v in enumerate(ko)}
+        h2o = np.array([pos[int(v)] for v in kh])
+        maps.append(h2o)
+        f = hm.gc_flags(k)
+        assert np.array_equal((f & 1) != 0, m.dirichlet[h2o])
+        assert np.array_equal((f & 2) != 0, m.hanging[h2o])
+        li = hm.gc_leaf_index(k)
+        lX, lY = hm.coords()
+        assert np.array_equal(lX[li], X) and np.array_equal(lY[li], Y)
+    for k in range(1, len(gh.meshes)):
+        ptr, col, val = hm.gc_interpolation(k)
+        n_f, n_c = maps[k].size, maps[k - 1].size
+        Ph = sp.csr_matrix((val, col, ptr), shape=(n_f, n_c))
+        # oracle interpolation in library numbering
+        Po = gh.I[k][maps[k]][:, maps[k - 1]]
+        assert abs(Ph - Po).max() == 0.0, k
