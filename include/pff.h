@@ -185,7 +185,11 @@ int pff_workspace_bytes(const pff_ctx* ctx, size_t* bytes);
 int pff_bind_workspace(pff_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Sizes: leaf nodes n (vectors have 3n entries), number of multigrid levels,
- * and (if level_nodes != NULL, host, n_levels entries) nodes per level. */
+ * and (if level_nodes != NULL, host, n_levels entries) nodes per level.
+ * Every call that takes a level index (sizes, coords, flags, tile stats,
+ * inverse diagonal, eigenvalues) addresses the hierarchy that the current
+ * pff_params.mg_kind selects; for global coarsening the last level is the
+ * leaf mesh. */
 int pff_sizes(const pff_ctx* ctx, int64_t* n_nodes, int32_t* n_levels, int64_t* level_nodes);
 /* Lattice size M: a node at integer (X, Y) sits at x = -10 + 20 X / M. */
 int pff_lattice(const pff_ctx* ctx, int64_t* M);
@@ -260,14 +264,19 @@ int pff_vmult_T(pff_ctx* ctx, double* dst, const double* src, int32_t batch, voi
 
 /* Inverse diagonal of the leaf operator (level = -1: 1/diag on free rows, 1 on
  * constrained rows) or of a level block operator (1/diag on free rows, 0 on
- * fixed rows: Dirichlet, level-active, refinement edge), as used by the
+ * fixed rows: Dirichlet, level-active, refinement edge, hanging; the level
+ * operators of global coarsening carry the hanging-node constraints of their
+ * mesh, C^T A C), as used by the
  * Chebyshev-Jacobi smoother (Sec. 1, Sec. 3.2). fp32 selects float output for
  * levels. Needs set_state (and setup_mg for levels). */
 int pff_inverse_diagonal(pff_ctx* ctx, int32_t level, void* dst, int32_t fp32, void* stream);
 
 /* dst = P^{-1} src: one V-cycle per diagonal block (Sec. 3.2) with local
- * smoothing. src, dst: 3n doubles (the V-cycle runs in FP32 inside when
- * fp32 != 0). Identity on constrained leaf rows. */
+ * smoothing (mg_kind 0) or global coarsening (mg_kind 1: smoothing on every
+ * level over all its free unknowns, restriction the transpose of the
+ * interpolation, leaf rows enter and leave on the finest level). src, dst: 3n
+ * doubles (the V-cycle runs in FP32 inside when fp32 != 0). Identity on
+ * constrained leaf rows. */
 int pff_vcycle(pff_ctx* ctx, double* dst, const double* src, int32_t fp32, void* stream);
 /* Eigenvalue estimates per level and block (host arrays): lam_max[2 * l + b]
  * for level l and block b (0 = u, 1 = phi), lam_min0[b] on level 0. get

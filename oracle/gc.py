@@ -13,7 +13,8 @@ unknowns with that level's hanging-node constraints.
 Per level (all assembled here, plainly):
   A_k   the block-diagonal operator diag(G_uu, G_phiphi) of Sec. 3.2 on the
         cells of level k with the injected state (u_x, u_y, phi~ at the same
-        lattice point of the leaf mesh), condensed with the level's hanging
+        lattice point of the leaf mesh, then constrained at the level's own
+        hanging nodes so that it is a level function), condensed with the level's hanging
         constraints C_k: A~_k = Mf (C_k^T A_k C_k) Mf + (I - Mf), Mf keeping the
         free unknowns (not Dirichlet for u, not hanging, not level-active for
         phi); the finest level's A~ is the block-diagonal part of J~.
@@ -151,9 +152,15 @@ class GCVCycle:
         acts = gh.level_active(leaf_active)
         self.ops, self.P = [], [None]
         self.frees = []
+        self.states = []
         for k, m in enumerate(gh.meshes):
             li = gh.leaf_index[k]
-            ux, uy, pt = U_leaf[:n][li], U_leaf[n:2 * n][li], phit_leaf[li]
+            # the level's linearisation state is a function of the level's own
+            # space: the leaf values at its regular nodes, the constraint at its
+            # hanging nodes (C_k on the injected values)
+            Ck = gh.C[k]
+            ux, uy, pt = Ck @ U_leaf[:n][li], Ck @ U_leaf[n:2 * n][li], Ck @ phit_leaf[li]
+            self.states.append((ux, uy, pt))
             from .assemble import leaf_cells
             cs = leaf_cells(m, gh.el)
             g = cs.gather

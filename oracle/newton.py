@@ -106,7 +106,11 @@ def newton_step(lp: LeafProblem, hier: Hierarchy, mgp: MGParams, nwp: NewtonPara
     info.residual_before = base
     J = lp.masked_operator(U, phit, active)
     if linear_solver == "gmres":
-        vc = VCycle(hier, lp.prm, mgp, U, phit, active, eigen=eigen)
+        # hier: the local-smoothing hierarchy, or a GlobalHierarchy for the
+        # global-coarsening cycle (same smoother and coarse solve)
+        from .gc import GCVCycle, GlobalHierarchy
+        cycle = GCVCycle if isinstance(hier, GlobalHierarchy) else VCycle
+        vc = cycle(hier, lp.prm, mgp, U, phit, active, eigen=eigen)
         tol = max(nwp.gmres_atol, nwp.gmres_rtol * info.rhs_norm)
         dUf, ginfo = gmres(lambda v: J @ v, vc.apply, b, tol,
                            restart=nwp.gmres_restart, maxit=nwp.gmres_maxit)

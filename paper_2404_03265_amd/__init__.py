@@ -49,6 +49,7 @@ class SolverParams:
     ls_max: int = 10
     vcycle_fp32: int = 0
     pdas_c: float = 0.0
+    mg_kind: int = 0   # 0: local smoothing, 1: global coarsening (needs mg_global=True)
 
     def to_c(self):
         p = _lib.Params()
@@ -77,27 +78,20 @@ class PhaseFieldSolver:
 
     def __init__(self, n_base: int, n_local: int, degree: int, coarse: int = 16,
                  band=(2.0, 0.5), tile=(0, 0), params: SolverParams | None = None,
-                 torch_workspace: bool = True):
+                 torch_workspace: bool = True, mg_global: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("PhaseFieldSolver needs a HIP device")
         self.lib = _lib.load()
         self.params = params or SolverParams()
-        spec = _lib.MeshSpec(n_base, n_local, degree, coarse, band[0], band[1], tile[0], tile[1])
+        spec = _lib.MeshSpec(n_base, n_local, degree, coarse, band[0], band[1], tile[0], tile[1], int(mg_global))
         h = C.c_void_p()
         rc = self.lib.pff_create(C.byref(spec), C.byref(self.params.to_c()), C.byref(h))
         if rc != 0:
             msg = self.lib.pff_last_error(None)
             raise RuntimeError(f"pff_create failed ({rc}): {msg.decode() if msg else ''}")
         self.h = h
-        n = C.c_int64()
-        nl = C.c_int32()
-        self._check(self.lib.pff_sizes(self.h, C.byref(n), C.byref(nl), None))
-        self.n = n.value
-        self.n_levels = nl.value
-        lvl = (C.c_int64 * self.n_levels)()
-        self._check(self.lib.pff_sizes(self.h, None, None, C.cast(lvl, C.c_void_p)))
-        self.level_nodes = list(lvl)
+        self._sizes()
         M = C.c_int64()
         self._check(self.lib.pff_lattice(self.h, C.byref(M)))
         self.M = M.value
@@ -106,6 +100,17 @@ class PhaseFieldSolver:
         if torch_workspace:
             self._ws = torch.empty(self.workspace_bytes(), dtype=torch.uint8, device="cuda")
             self._check(self.lib.pff_bind_workspace(self.h, _ptr(self._ws), self._ws.numel()))
+
+    def _sizes(self):
+        # level sizes of the hierarchy that params.mg_kind selects
+        n = C.c_int64()
+        nl = C.c_int32()
+        self._check(self.lib.pff_sizes(self.h, C.byref(n), C.byref(nl), None))
+        self.n = n.value
+        self.n_levels = nl.value
+        lvl = (C.c_int64 * self.n_levels)()
+        self._check(self.lib.pff_sizes(self.h, None, None, C.cast(lvl, C.c_void_p)))
+        self.level_nodes = list(lvl)
 
     def workspace_bytes(self) -> int:
         b = C.c_size_t()
@@ -151,6 +156,7 @@ class PhaseFieldSolver:
     def set_params(self, params: SolverParams):
         self._check(self.lib.pff_set_params(self.h, C.byref(params.to_c())))
         self.params = params
+        self._sizes()
 
     # ---- state and operators ---------------------------------------------------
     def set_state(self, U, phi_old, phi_tilde, active=None, setup_mg: bool = True):

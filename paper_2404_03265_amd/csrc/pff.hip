@@ -82,6 +82,7 @@ struct DevLevel {
   LevelWork<double> w64;
   LevelWork<float> w32;
   double lam_max[2] = {1, 1}, lam_min[2] = {1, 1};
+  bool shares_leaf = false;   // tiles and flags are the leaf operator's (not freed with the level)
 };
 
 template <typename T>
@@ -199,17 +200,17 @@ void ell_from_csr(const Csr& A, const std::vector<int64_t>& rows, std::vector<do
   }
 }
 
-void upload_transfers(const Level& HL, DevLevel& D) {
+void upload_transfers(const Csr& P, const Csr& PT, DevLevel& D) {
   std::vector<uint32_t> E;
   std::vector<double> wtab(1, 0.0);   // index 0: padding
-  std::vector<int64_t> rows(size_t(HL.P.rows));
+  std::vector<int64_t> rows(size_t(P.rows));
   std::iota(rows.begin(), rows.end(), 0);
-  ell_from_csr(HL.P, rows, wtab, E, D.P_width);
+  ell_from_csr(P, rows, wtab, E, D.P_width);
   D.P_ell = upload(E);
   rows.clear();
-  for (int64_t r = 0; r < HL.PT.rows; ++r)
-    if (HL.PT.ptr[r + 1] > HL.PT.ptr[r]) rows.push_back(r);
-  ell_from_csr(HL.PT, rows, wtab, E, D.PT_width);
+  for (int64_t r = 0; r < PT.rows; ++r)
+    if (PT.ptr[r + 1] > PT.ptr[r]) rows.push_back(r);
+  ell_from_csr(PT, rows, wtab, E, D.PT_width);
   D.PT_ell = upload(E);
   std::vector<int32_t> r32(rows.begin(), rows.end());
   D.PT_rows = upload(r32);
@@ -264,7 +265,13 @@ struct pff_ctx {
   uint8_t* flags = nullptr;
   Hanging* hang = nullptr;
   int n_hang = 0;
-  std::vector<DevLevel> lv;
+  std::vector<DevLevel> lv;      // local-smoothing levels (Sec. 3.2)
+  // global-coarsening levels above the base mesh and the leaf level (the
+  // uniform levels up to the base mesh are lv's); H: the hierarchy in use
+  // (prm.mg_kind), level 0 = the coarse grid
+  std::vector<DevLevel> gcown;
+  std::vector<DevLevel*> H_ls, H_gc, H;
+  bool has_gc = false;
   double* U = nullptr;
   double* phio = nullptr;
   double* phit = nullptr;
@@ -301,6 +308,11 @@ struct pff_ctx {
   bool eig_fixed = false;
   std::string err;
   hipStream_t s = nullptr;
+
+  DevLevel& lev(int l) { return *H[size_t(l)]; }
+  const DevLevel& lev(int l) const { return *H[size_t(l)]; }
+  int nlev() const { return int(H.size()); }
+  void select_hierarchy() { H = (prm.mg_kind == 1 && has_gc) ? H_gc : H_ls; }
 
   Material mat() const {
     Material m;
@@ -356,7 +368,7 @@ struct pff_ctx {
     if (lds > size_t(160 * 1024)) throw std::runtime_error("tile needs more LDS than a CU has; use smaller tiles");
     // hanging nodes are handled on the tile's nodes; only the inverse
     // diagonal runs the per-cell constraint form
-    constexpr bool HANG = (MODE == MODE_DIAG_LEAF);
+    constexpr bool HANG = (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL);
     const void* kfn = p == 1 ? reinterpret_cast<const void*>(&tile_kernel<1, T, MODE, EPI, HANG>)
                              : reinterpret_cast<const void*>(&tile_kernel<2, T, MODE, EPI, HANG>);
     if (lds > size_t(64 * 1024))
@@ -465,7 +477,11 @@ struct pff_ctx {
     double* pp = nullptr;
     take(pp, int64_t(part_bytes / sizeof(double)));
     if (carve) part = pp;
-    for (DevLevel& L : lv) {
+    std::vector<DevLevel*> all;
+    for (DevLevel& L : lv) all.push_back(&L);
+    for (DevLevel& L : gcown) all.push_back(&L);
+    for (DevLevel* Lp : all) {
+      DevLevel& L = *Lp;
       const int64_t nl = 3 * L.n;
       LevelWork<double>& a = L.w64;
       LevelWork<float>& b = L.w32;
@@ -508,7 +524,7 @@ struct pff_ctx {
   LevelWork<T>& work(DevLevel& L);
 
   template <typename T>
-  void ensure_level_work(DevLevel& L, const Level& HL) {
+  void ensure_level_work(DevLevel& L) {
     LevelWork<T>& w = work<T>(L);
     if (w.ready) return;
     const int64_t nl = L.n;
@@ -516,14 +532,13 @@ struct pff_ctx {
     w.d = dalloc<T>(3 * nl);
     for (int i = 0; i < 2; ++i) { w.x[i] = dalloc<T>(3 * nl); w.dir[i] = dalloc<T>(3 * nl); }
     w.dinv = dalloc<T>(3 * nl);
-    (void)HL;
     w.ready = true;
   }
 
   template <typename T>
   void level_apply(int l, const T* x, T* dst, int epi, const T* b, const T* dold, T* xnew, const T c1[2],
                    const T c2[2], const T* c0 = nullptr) {
-    DevLevel& L = lv[l];
+    DevLevel& L = lev(l);
     LevelWork<T>& w = work<T>(L);
     TileArgs<T> a{};
     a.src = x;
@@ -548,7 +563,7 @@ struct pff_ctx {
 
   template <typename T>
   void level_diag(int l) {
-    DevLevel& L = lv[l];
+    DevLevel& L = lev(l);
     LevelWork<T>& w = work<T>(L);
     TileArgs<T> a{};
     a.dst = w.dinv;
@@ -560,7 +575,7 @@ struct pff_ctx {
 
   // smoothing interval per block on level l
   void interval(int l, double lo[2], double hi[2]) const {
-    const DevLevel& L = lv[l];
+    const DevLevel& L = lev(l);
     for (int b = 0; b < 2; ++b) {
       if (l == 0 && prm.coarse_mode == 0) {
         lo[b] = L.lam_min[b];
@@ -577,7 +592,7 @@ struct pff_ctx {
   // w.x[*out_idx].
   template <typename T>
   int chebyshev(int l, const T* b, int x_in_idx, int degree) {
-    DevLevel& L = lv[l];
+    DevLevel& L = lev(l);
     LevelWork<T>& w = work<T>(L);
     double lo[2], hi[2];
     interval(l, lo, hi);
@@ -686,7 +701,7 @@ struct pff_ctx {
   // per-step path); result in w.x[0]
   template <typename T>
   int coarse_fused() {
-    DevLevel& L = lv[0];
+    DevLevel& L = lev(0);
     LevelWork<T>& w = work<T>(L);
     CoarseArgs<T> a{};
     a.n0 = int(L.n);
@@ -740,7 +755,7 @@ struct pff_ctx {
   // side; the result is left in w.x[0].
   template <typename T>
   int coarse_cg() {
-    DevLevel& L = lv[0];
+    DevLevel& L = lev(0);
     LevelWork<T>& w = work<T>(L);
     T* x = w.x[0];
     T* r = w.x[1];
@@ -833,6 +848,46 @@ struct pff_ctx {
     HIPCHK(hipGetLastError());
   }
 
+  // Global-coarsening V-cycle (the level sequence of the design notes): the
+  // finest level is the leaf mesh; every level is smoothed over all of its
+  // free unknowns with its hanging-node constraints, restriction is the
+  // transpose of the interpolation, no refinement edge and no copies.
+  template <typename T>
+  void vcycle_gc_impl(double* dst, const double* src) {
+    const int L = nlev() - 1;
+    const int k = prm.cheb_degree;
+    std::vector<int> xi(L + 1, 0);
+    hipLaunchKernelGGL((k_leaf_to_level<T>), dim3(grid_for(n)), dim3(256), 0, s, work<T>(lev(L)).d, src, flags, n);
+    for (int l = L; l >= 1; --l) {
+      DevLevel& D = lev(l);
+      LevelWork<T>& w = work<T>(D);
+      xi[l] = chebyshev<T>(l, w.d, -1, k);
+      T* t = w.dir[0];
+      level_apply<T>(l, w.x[xi[l]], t, EPI_RESID, w.d, nullptr, nullptr, nullptr, nullptr);
+      DevLevel& C = lev(l - 1);
+      LevelWork<T>& wc = work<T>(C);
+      hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(3 * C.n)), dim3(256), 0, s, wc.d, T(0), 3 * C.n);
+      if (D.PT_nrows > 0) restrict_add<T>(wc.d, t, C.n, D);
+    }
+    {
+      LevelWork<T>& w0 = work<T>(lev(0));
+      if (coarse_fusable && prm.coarse_its <= COARSE_MAX_STEPS)
+        xi[0] = coarse_fused<T>();
+      else
+        xi[0] = prm.coarse_mode == 1 ? coarse_cg<T>() : chebyshev<T>(0, w0.d, -1, prm.coarse_its);
+    }
+    for (int l = 1; l <= L; ++l) {
+      DevLevel& D = lev(l);
+      LevelWork<T>& w = work<T>(D);
+      LevelWork<T>& wc = work<T>(lev(l - 1));
+      prolong_add<T>(w.x[xi[l]], wc.x[xi[l - 1]], lev(l - 1).n, D);
+      xi[l] = chebyshev<T>(l, w.d, xi[l], k);
+    }
+    hipLaunchKernelGGL((k_level_to_leaf<T>), dim3(grid_for(n)), dim3(256), 0, s, dst, work<T>(lev(L)).x[xi[L]], src,
+                       flags, n);
+    HIPCHK(hipGetLastError());
+  }
+
   // Extreme Ritz values of D^{-1} A (free unknowns of one block) from
   // `its` Jacobi-preconditioned CG steps on A x = 1.
   // Extreme eigenvalues of D^-1 A on each block of level l by `its` steps of
@@ -846,7 +901,7 @@ struct pff_ctx {
   // (2 EIG_SC + 4 EIG_MAX_ITS doubles). eig_finish turns them into the
   // extreme Ritz values once the stream has been synchronised.
   void eig_launch(int l, int its, double* out) {
-    DevLevel& L = lv[l];
+    DevLevel& L = lev(l);
     LevelWork<double>& w = w64of(L);
     const int64_t nl = L.n;
     double* r = w.x[0];
@@ -884,7 +939,7 @@ struct pff_ctx {
                           hipMemcpyDeviceToHost, s));
   }
   void eig_finish(int l, const double* in) {
-    DevLevel& L = lv[l];
+    DevLevel& L = lev(l);
     const int stride = EIG_MAX_ITS;
     const double* h = in;
     const double* al = in + 2 * EIG_SC;
@@ -907,10 +962,10 @@ struct pff_ctx {
   // every level's estimate with one host wait
   void eig_estimate_all() {
     const size_t per = size_t(2 * EIG_SC + 4 * EIG_MAX_ITS);
-    for (int l = 0; l < int(lv.size()); ++l)
+    for (int l = 0; l < nlev(); ++l)
       eig_launch(l, l == 0 ? prm.coarse_eig_its : prm.eig_cg_its, eig_host + per * size_t(l));
     HIPCHK(hipStreamSynchronize(s));
-    for (int l = 0; l < int(lv.size()); ++l) eig_finish(l, eig_host + per * size_t(l));
+    for (int l = 0; l < nlev(); ++l) eig_finish(l, eig_host + per * size_t(l));
   }
 
   // Smallest and largest eigenvalue of a symmetric tridiagonal matrix by
@@ -951,13 +1006,14 @@ struct pff_ctx {
 
   template <typename T>
   void setup_levels() {
-    for (int l = 0; l < int(lv.size()); ++l) {
-      ensure_level_work<T>(lv[l], mesh.levels[l]);
-      LevelWork<T>& w = work<T>(lv[l]);
-      hipLaunchKernelGGL((k_inject<T>), dim3(grid_for(lv[l].n)), dim3(256), 0, s, w.state, lv[l].n,
-                         lv[l].leaf_index, U, phit, n);
+    for (int l = 0; l < nlev(); ++l) {
+      DevLevel& L = lev(l);
+      ensure_level_work<T>(L);
+      LevelWork<T>& w = work<T>(L);
+      hipLaunchKernelGGL((k_inject<T>), dim3(grid_for(L.n)), dim3(256), 0, s, w.state, L.n, L.leaf_index, U, phit,
+                         n);
     }
-    for (int l = 0; l < int(lv.size()); ++l) level_diag<T>(l);
+    for (int l = 0; l < nlev(); ++l) level_diag<T>(l);
     HIPCHK(hipGetLastError());
   }
 
@@ -968,14 +1024,31 @@ struct pff_ctx {
       const int32_t* ptc = l < L ? lv[l + 1].PT_col : nullptr;
       const uint8_t* ff = l < L ? lv[l + 1].flags : nullptr;
       hipLaunchKernelGGL(k_level_active, dim3(grid_for(lv[l].n)), dim3(256), 0, s, lv[l].flags, lv[l].n,
-                         lv[l].leaf_index, flags, ptp, ptc, ff);
+                         lv[l].leaf_index, flags, ptp, ptc, ff, 1);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  // global coarsening: the finest level is the leaf mesh and shares the leaf
+  // flags (the leaf active set); a coarser unknown is active if the leaf
+  // unknown at its position is or any finer unknown its interpolation
+  // reaches (no home-level rule: every free leaf unknown is smoothed on the
+  // finest level)
+  void gc_level_active_sets() {
+    const int L = nlev() - 1;
+    for (int l = L - 1; l >= 0; --l) {
+      DevLevel& D = lev(l);
+      DevLevel& F = lev(l + 1);
+      hipLaunchKernelGGL(k_level_active, dim3(grid_for(D.n)), dim3(256), 0, s, D.flags, D.n, D.leaf_index, flags,
+                         F.PT_ptr, F.PT_col, F.flags, 0);
     }
     HIPCHK(hipGetLastError());
   }
 
   void setup_mg() {
     fp32_ready = false;
-    level_active_sets();
+    select_hierarchy();
+    if (H == H_gc && has_gc) gc_level_active_sets();
+    else level_active_sets();
     setup_levels<double>();
     if (!eig_fixed)
       eig_estimate_all();
@@ -1001,11 +1074,14 @@ struct pff_ctx {
     else leaf_op<MODE_J>(dst, src, st);
   }
   void apply_Minv(double* dst, const double* src, bool fp32) {
+    const bool gc = H == H_gc && has_gc;
     if (fp32) {
       if (!fp32_ready) setup_fp32();
-      vcycle_impl<float>(dst, src);
+      if (gc) vcycle_gc_impl<float>(dst, src);
+      else vcycle_impl<float>(dst, src);
     } else {
-      vcycle_impl<double>(dst, src);
+      if (gc) vcycle_gc_impl<double>(dst, src);
+      else vcycle_impl<double>(dst, src);
     }
   }
 
@@ -1144,7 +1220,8 @@ static bool params_valid(const pff_params& p) {
   return p.cheb_degree >= 1 && p.coarse_its >= 1 && p.gmres_restart >= 1 && p.gmres_restart <= 60 &&
          p.gmres_max_its >= 1 && p.ls_max >= 1 && p.ls_omega > 0.0 && p.ls_omega <= 1.0 &&
          p.coarse_mode >= 0 && p.coarse_mode <= 1 && p.eig_cg_its >= 1 && p.eig_cg_its <= EIG_MAX_ITS &&
-         p.coarse_eig_its >= 1 && p.coarse_eig_its <= EIG_MAX_ITS && std::isfinite(p.pdas_c) && p.pdas_c >= 0.0;
+         p.coarse_eig_its >= 1 && p.coarse_eig_its <= EIG_MAX_ITS && std::isfinite(p.pdas_c) && p.pdas_c >= 0.0 &&
+         p.mg_kind >= 0 && p.mg_kind <= 1;
 }
 
 extern "C" {
@@ -1198,7 +1275,10 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
   ms.band_y = spec->band_y;
   ms.tile_x = spec->tile_x;
   ms.tile_y = spec->tile_y;
+  ms.mg_global = spec->mg_global != 0;
   if (!params_valid(*params)) return create_failed(nullptr, PFF_E_ARG, "pff_create: invalid parameters");
+  if (params->mg_kind == 1 && !ms.mg_global)
+    return create_failed(nullptr, PFF_E_ARG, "pff_create: mg_kind = 1 needs a mesh spec with mg_global");
   try {
     bool built = false;
     try {
@@ -1212,6 +1292,7 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
                                                    std::to_string(COPY_MAX_LEVELS) + ")");
     bool too_big = c->mesh.tiles.max_local > 65535;
     for (const Level& L : c->mesh.levels) too_big = too_big || L.tiles.max_local > 65535;
+    for (const GcLevel& G : c->mesh.gc) too_big = too_big || G.tiles.max_local > 65535;
     if (too_big) return create_failed(nullptr, PFF_E_MESH, "pff_create: a tile has more than 65535 local nodes");
     c->prm = *params;
     c->p = ms.degree;
@@ -1232,12 +1313,52 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
       if (l > 0) {
         D.PT_ptr = upload(HL.PT.ptr);
         D.PT_col = upload(HL.PT.col);
-        upload_transfers(HL, D);
+        upload_transfers(HL.P, HL.PT, D);
       }
     }
+    for (size_t l = 0; l < c->lv.size(); ++l) c->H_ls.push_back(&c->lv[l]);
+    if (!c->mesh.gc.empty()) {
+      // global-coarsening levels: k <= b shared with local smoothing, own
+      // levels above the base mesh, the leaf level last
+      const int nl = int(c->mesh.gc.size());
+      c->gcown.reserve(size_t(nl));
+      for (int k = 0; k < nl; ++k) {
+        const GcLevel& G = c->mesh.gc[size_t(k)];
+        if (k < nl - 1 && !G.own) {
+          c->H_gc.push_back(&c->lv[size_t(k)]);
+          continue;
+        }
+        c->gcown.emplace_back();
+        DevLevel& D = c->gcown.back();
+        D.n = G.n;
+        if (k == nl - 1) {
+          D.tiles = c->tiles;
+          D.flags = c->flags;
+          D.shares_leaf = true;
+          std::vector<int32_t> id(size_t(G.n));
+          std::iota(id.begin(), id.end(), 0);
+          D.leaf_index = upload(id);
+        } else {
+          D.tiles = upload_tiles(G.tiles);
+          D.flags = upload(G.flags);
+          D.leaf_index = upload(G.leaf_index);
+        }
+        if (k > 0) {
+          const Csr& P = G.P.rows > 0 ? G.P : c->mesh.levels[size_t(k)].P;
+          const Csr& PT = G.P.rows > 0 ? G.PT : c->mesh.levels[size_t(k)].PT;
+          D.PT_ptr = upload(PT.ptr);
+          D.PT_col = upload(PT.col);
+          upload_transfers(P, PT, D);
+        }
+        c->H_gc.push_back(&D);
+      }
+      c->has_gc = true;
+    }
+    c->select_hierarchy();
     c->setup_coarse_cells();
     int64_t slots = c->mesh.tiles.n_slots;
     for (const Level& L : c->mesh.levels) slots = std::max(slots, L.tiles.n_slots);
+    for (const GcLevel& G : c->mesh.gc) slots = std::max(slots, G.tiles.n_slots);
     c->part_bytes = size_t(3 * std::max<int64_t>(slots, 1)) * sizeof(double);
     c->red_part = dalloc<double>(RED_BLOCKS * 64);
     c->red_out = dalloc<double>(256);
@@ -1270,9 +1391,16 @@ int pff_destroy(pff_ctx* c) {
   ft(c->tiles);
   f(c->flags);
   f(c->hang);
-  for (DevLevel& D : c->lv) {
-    ft(D.tiles);
-    f(D.flags); f(D.leaf_index); f(D.PT_ptr); f(D.PT_col); f(D.P_ell); f(D.PT_ell); f(D.PT_rows); f(D.P_wtab);
+  std::vector<DevLevel*> all;
+  for (DevLevel& D : c->lv) all.push_back(&D);
+  for (DevLevel& D : c->gcown) all.push_back(&D);
+  for (DevLevel* Dp : all) {
+    DevLevel& D = *Dp;
+    if (!D.shares_leaf) {
+      ft(D.tiles);
+      f(D.flags);
+    }
+    f(D.leaf_index); f(D.PT_ptr); f(D.PT_col); f(D.P_ell); f(D.PT_ell); f(D.PT_rows); f(D.P_wtab);
     if (!c->ws) {   // a bound workspace belongs to the caller
       LevelWork<double>& a = D.w64;
       f(a.state); f(a.d); f(a.x[0]); f(a.x[1]); f(a.dir[0]); f(a.dir[1]); f(a.dinv);
@@ -1299,9 +1427,14 @@ int pff_set_params(pff_ctx* c, const pff_params* p) {
     c->err = "gmres_restart exceeds the restart the bound workspace was sized for";
     return PFF_E_ARG;
   }
+  if (p->mg_kind == 1 && !c->has_gc) {
+    c->err = "mg_kind = 1 needs a context created with mg_global";
+    return PFF_E_ARG;
+  }
   c->prm = *p;
   c->mg_ready = false;
   c->fp32_ready = false;
+  c->select_hierarchy();
   return PFF_OK;
 }
 
@@ -1335,9 +1468,9 @@ int pff_bind_workspace(pff_ctx* c, void* ptr, size_t bytes) {
 int pff_sizes(const pff_ctx* c, int64_t* n_nodes, int32_t* n_levels, int64_t* level_nodes) {
   if (!c) return PFF_E_ARG;
   if (n_nodes) *n_nodes = c->n;
-  if (n_levels) *n_levels = int32_t(c->lv.size());
+  if (n_levels) *n_levels = int32_t(c->nlev());
   if (level_nodes)
-    for (size_t l = 0; l < c->lv.size(); ++l) level_nodes[l] = c->lv[l].n;
+    for (int l = 0; l < c->nlev(); ++l) level_nodes[l] = c->lev(l).n;
   return PFF_OK;
 }
 
@@ -1348,25 +1481,32 @@ int pff_lattice(const pff_ctx* c, int64_t* M) {
 }
 
 int pff_node_coords(const pff_ctx* c, int32_t level, int32_t* xy) {
-  if (!c || !xy || level < -1 || level >= int32_t(c->lv.size())) return PFF_E_ARG;
-  const std::vector<int32_t>& X = level < 0 ? c->mesh.NX : c->mesh.levels[level].NX;
-  const std::vector<int32_t>& Y = level < 0 ? c->mesh.NY : c->mesh.levels[level].NY;
+  if (!c || !xy || level < -1 || level >= int32_t(c->nlev())) return PFF_E_ARG;
+  const std::vector<int32_t>* Xp = level < 0 ? &c->mesh.NX : &c->mesh.levels[size_t(level)].NX;
+  const std::vector<int32_t>* Yp = level < 0 ? &c->mesh.NY : &c->mesh.levels[size_t(level)].NY;
+  if (level >= 0 && c->H == c->H_gc && c->has_gc) {
+    const GcLevel& G = c->mesh.gc[size_t(level)];
+    if (level == c->nlev() - 1) { Xp = &c->mesh.NX; Yp = &c->mesh.NY; }
+    else if (G.own) { Xp = &G.NX; Yp = &G.NY; }
+  }
+  const std::vector<int32_t>& X = *Xp;
+  const std::vector<int32_t>& Y = *Yp;
   std::memcpy(xy, X.data(), X.size() * sizeof(int32_t));
   std::memcpy(xy + X.size(), Y.data(), Y.size() * sizeof(int32_t));
   return PFF_OK;
 }
 
 int pff_node_flags(const pff_ctx* c, int32_t level, uint8_t* out) {
-  if (!c || !out || level < -1 || level >= int32_t(c->lv.size())) return PFF_E_ARG;
-  const int64_t nn = level < 0 ? c->n : c->lv[level].n;
-  const uint8_t* src = level < 0 ? c->flags : c->lv[level].flags;
+  if (!c || !out || level < -1 || level >= int32_t(c->nlev())) return PFF_E_ARG;
+  const int64_t nn = level < 0 ? c->n : c->lev(level).n;
+  const uint8_t* src = level < 0 ? c->flags : c->lev(level).flags;
   if (hipMemcpy(out, src, size_t(nn), hipMemcpyDeviceToHost) != hipSuccess) return PFF_E_HIP;
   return PFF_OK;
 }
 
 int pff_tile_stats(const pff_ctx* c, int32_t level, int64_t* n_tiles, int64_t* n_records, int64_t* max_cells) {
-  if (!c || level < -1 || level >= int32_t(c->lv.size())) return PFF_E_ARG;
-  const DevTiles& t = level < 0 ? c->tiles : c->lv[level].tiles;
+  if (!c || level < -1 || level >= int32_t(c->nlev())) return PFF_E_ARG;
+  const DevTiles& t = level < 0 ? c->tiles : c->lev(level).tiles;
   if (n_tiles) *n_tiles = t.n_tiles;
   if (n_records) *n_records = t.n_rec;
   if (max_cells) *max_cells = t.max_cells;
@@ -1483,7 +1623,7 @@ int pff_vmult_T(pff_ctx* c, double* dst, const double* src, int32_t batch, void*
 }
 
 int pff_inverse_diagonal(pff_ctx* c, int32_t level, void* dst, int32_t fp32, void* stream) {
-  if (!c || !dst || level < -1 || level >= int32_t(c->lv.size())) return PFF_E_ARG;
+  if (!c || !dst || level < -1 || level >= int32_t(c->nlev())) return PFF_E_ARG;
   if (!c->has_state) { c->err = "inverse_diagonal needs a state"; return PFF_E_STATE; }
   GUARD_BEGIN
   c->s = static_cast<hipStream_t>(stream);
@@ -1497,7 +1637,7 @@ int pff_inverse_diagonal(pff_ctx* c, int32_t level, void* dst, int32_t fp32, voi
     return PFF_OK;
   }
   if (!c->mg_ready) { c->err = "level diagonals need set_state with setup_mg"; return PFF_E_STATE; }
-  DevLevel& D = c->lv[level];
+  DevLevel& D = c->lev(level);
   if (fp32) {
     if (!c->fp32_ready) c->setup_fp32();
     HIPCHK(hipMemcpyAsync(dst, D.w32.dinv, sizeof(float) * 3 * D.n, hipMemcpyDeviceToDevice, c->s));
@@ -1520,21 +1660,21 @@ int pff_vcycle(pff_ctx* c, double* dst, const double* src, int32_t fp32, void* s
 
 int pff_get_eigen(const pff_ctx* c, double* lam_max, double* lam_min0) {
   if (!c) return PFF_E_ARG;
-  for (size_t l = 0; l < c->lv.size(); ++l)
+  for (int l = 0; l < c->nlev(); ++l)
     for (int b = 0; b < 2; ++b)
-      if (lam_max) lam_max[2 * l + b] = c->lv[l].lam_max[b];
+      if (lam_max) lam_max[2 * l + b] = c->lev(l).lam_max[b];
   if (lam_min0)
-    for (int b = 0; b < 2; ++b) lam_min0[b] = c->lv[0].lam_min[b];
+    for (int b = 0; b < 2; ++b) lam_min0[b] = c->lev(0).lam_min[b];
   return PFF_OK;
 }
 
 int pff_set_eigen(pff_ctx* c, const double* lam_max, const double* lam_min0) {
   if (!c) return PFF_E_ARG;
   if (!lam_max) { c->eig_fixed = false; return PFF_OK; }
-  for (size_t l = 0; l < c->lv.size(); ++l)
-    for (int b = 0; b < 2; ++b) c->lv[l].lam_max[b] = lam_max[2 * l + b];
+  for (int l = 0; l < c->nlev(); ++l)
+    for (int b = 0; b < 2; ++b) c->lev(l).lam_max[b] = lam_max[2 * l + b];
   if (lam_min0)
-    for (int b = 0; b < 2; ++b) c->lv[0].lam_min[b] = lam_min0[b];
+    for (int b = 0; b < 2; ++b) c->lev(0).lam_min[b] = lam_min0[b];
   c->eig_fixed = true;
   return PFF_OK;
 }

@@ -116,10 +116,10 @@ __device__ __forceinline__ void node_epilogue(const TileArgs<T>& a, int c, int64
       a.dst[i] = v;
     } else if constexpr (EPI == EPI_RESID) {
       // residual to restrict: zero on rows held at zero on this level
-      const bool held = (c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
+      const bool held = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
       a.dst[i] = held ? T(0) : a.b[i] - v;
     } else {
-      const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
+      const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_EDGE | NODE_HANGING));
       const int blk = c < 2 ? 0 : 1;
       T x, dp;
       if constexpr (EPI == EPI_CHEB_FIRST) {
@@ -145,7 +145,7 @@ __device__ __forceinline__ void node_epilogue(const TileArgs<T>& a, int c, int64
     const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
     a.dst[i] = cons ? T(1) : T(1) / v;
   } else if constexpr (MODE == MODE_DIAG_LEVEL) {
-    const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
+    const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_EDGE | NODE_HANGING));
     a.dst[i] = fixed ? T(0) : T(1) / v;
   } else {
     a.dst[i] = (f & NODE_HANGING) ? T(0) : v;
@@ -494,7 +494,9 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   // Hanging nodes: every mode but the inverse diagonal applies the
   // constraints on the tile's nodes (interpolate after staging, distribute
   // after accumulation); the inverse diagonal needs the per-cell form.
-  constexpr bool NODE_HANG = TR::leaf && MODE != MODE_DIAG_LEAF;
+  // (the level operator too: the levels of global-coarsening multigrid have
+  // hanging nodes; local-smoothing levels have no records, nhang = 0)
+  constexpr bool NODE_HANG = (TR::leaf && MODE != MODE_DIAG_LEAF) || MODE == MODE_LEVEL;
   const int hr0 = NODE_HANG ? ti[TILE_HANG0] : 0, nhang = NODE_HANG ? ti[TILE_NHANG] : 0;
   const int nhcol = NODE_HANG ? ti[TILE_NHCOLOR] : 0;
   const int nloc = no + ns;
@@ -512,7 +514,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   auto load_cell_record = [&]() {
     if (live) {
       const int64_t rec = int64_t(c0) + cell;
-      const uint16_t* cl = (MODE == MODE_DIAG_LEAF) ? a.cell_loc_sub : a.cell_loc;
+      const uint16_t* cl = (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) ? a.cell_loc_sub : a.cell_loc;
 #pragma unroll
       for (int k = 0; k < NL; ++k) loc[k] = cl[rec * NL + k];
       info = a.cell_info[rec];
@@ -689,7 +691,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       const int lev = int((info >> CELL_LEVEL_SHIFT) & 31u);
       const T H = T(ldexp(double(a.H0), -lev));
       // per-cell constraint form (inverse diagonal only)
-      const bool hang = HANG && MODE == MODE_DIAG_LEAF && (info & 15u);
+      const bool hang = HANG && (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) && (info & 15u);
       auto gather = [&](int field, T(&u)[NL]) {
 #pragma unroll
         for (int k = 0; k < NL; ++k) u[k] = T(lds[field * ML + loc[k]]);
@@ -765,14 +767,15 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
             a.dst[i] = cons ? raw[k][c] : v;
           } else if constexpr (CHEB) {
             // the level smoother step, as in node_epilogue
-            const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE)) : (f & (NODE_ACTIVE | NODE_EDGE));
+            const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_EDGE | NODE_HANGING));
             const int blk = c < 2 ? 0 : 1;
             const T x = raw[k][c];
             const T dn = a.c1[blk] * pdo[k][c] + a.c2[blk] * pdi[k][c] * (pb[k][c] - v);
             a.dst[i] = fixed ? T(0) : dn;
             a.xnew[i] = fixed ? x : x + dn;
           } else if constexpr (LPRE) {
-            const bool held = (c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
+            const bool held =
+                (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
             a.dst[i] = held ? T(0) : pb[k][c] - v;
           }
         }

@@ -180,19 +180,22 @@ __global__ void k_inject(T* st, int64_t nl, const int32_t* leaf_index, const dou
 
 // Level active set (Sec. 3.2: inactive only if every fine unknown it
 // interacts with is inactive): active if the leaf unknown at the same
-// position is active or any finer unknown in the prolongation stencil is;
-// on the home level of a leaf unknown (NODE_COPY) only its own flag counts,
-// so that no free leaf unknown is frozen on every level that holds it.
+// position is active or any finer unknown in the prolongation stencil is.
+// home_rule (local smoothing): on the home level of a leaf unknown
+// (NODE_COPY) only its own flag counts, so that no free leaf unknown is
+// frozen on every level that holds it; global coarsening smooths every free
+// leaf unknown on its finest level and passes home_rule = 0.
 __global__ void k_level_active(uint8_t* fl, int64_t nl, const int32_t* leaf_index, const uint8_t* leaf_flags,
-                               const int64_t* PT_ptr, const int32_t* PT_col, const uint8_t* fine_flags) {
+                               const int64_t* PT_ptr, const int32_t* PT_col, const uint8_t* fine_flags,
+                               int home_rule) {
   GRID_LOOP(i, nl) {
     uint8_t f = fl[i] & uint8_t(~NODE_ACTIVE);
     const bool own = (leaf_flags[leaf_index[i]] & NODE_ACTIVE) != 0;
     bool act = own;
-    if (!(f & NODE_COPY) && PT_ptr && !act)
+    if (!(home_rule && (f & NODE_COPY)) && PT_ptr && !act)
       for (int64_t e = PT_ptr[i]; e < PT_ptr[i + 1]; ++e)
         if (fine_flags[PT_col[e]] & NODE_ACTIVE) { act = true; break; }
-    if (act) f |= NODE_ACTIVE;
+    if (act && !(f & NODE_HANGING)) f |= NODE_ACTIVE;   // hanging unknowns are never active
     fl[i] = f;
   }
 }
@@ -254,6 +257,26 @@ __global__ void k_copy_from_levels(double* out, const LevelCopyArgs<T> a, const 
       for (int c = 0; c < 3; ++c)
         out[c * n + g] = leaf_constrained(lf, c) ? b[c * n + g] : double(a.vec[l][c * nl + k]);
     }
+  }
+}
+
+// Global coarsening: the finest level is the leaf mesh itself. Its right-hand
+// side is the leaf vector with constrained rows set to zero; the output takes
+// the level solution on free rows and the input on constrained ones.
+template <typename T>
+__global__ void k_leaf_to_level(T* d, const double* b, const uint8_t* leaf_flags, int64_t n) {
+  GRID_LOOP(k, n) {
+    const uint8_t f = leaf_flags[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[c * n + k] = leaf_constrained(f, c) ? T(0) : T(b[c * n + k]);
+  }
+}
+template <typename T>
+__global__ void k_level_to_leaf(double* out, const T* x, const double* b, const uint8_t* leaf_flags, int64_t n) {
+  GRID_LOOP(k, n) {
+    const uint8_t f = leaf_flags[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c * n + k] = leaf_constrained(f, c) ? b[c * n + k] : double(x[c * n + k]);
   }
 }
 

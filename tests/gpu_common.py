@@ -23,7 +23,7 @@ class Case:
 
     def __init__(self, n_base, n_local, p, coarse=16, band=(2.0, 0.5), seed=0, u_std=1e-4,
                  mask="bernoulli", prm=None, solver_params=None, tile=(0, 0), build_oracle=True,
-                 phit="phi"):
+                 phit="phi", mg_global=False):
         import torch
         from paper_2404_03265_amd import PhaseFieldSolver, SolverParams
         self.torch = torch
@@ -34,7 +34,8 @@ class Case:
         for k in ("E", "nu", "Gc", "pressure", "kappa", "ell"):
             setattr(sp_, k, getattr(self.prm, k))
         self.sp = sp_
-        self.g = PhaseFieldSolver(n_base, n_local, p, coarse=coarse, band=band, tile=tile, params=sp_)
+        self.g = PhaseFieldSolver(n_base, n_local, p, coarse=coarse, band=band, tile=tile, params=sp_,
+                                  mg_global=mg_global)
         X, Y = self.g.coords()
         self.X, self.Y, self.M = X, Y, self.g.M
         self.n = self.g.n

@@ -198,3 +198,42 @@ def test_coarse_hanging_values_reach_only_fine_hanging_rows(p, tiny_mesh_factory
         reach = np.flatnonzero(np.abs(gh.I[k][:, hc]).sum(axis=1).A.ravel() > 0)
         assert np.all(gh.meshes[k].hanging[reach]), k
         assert cols.size > 0
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_level_state_is_a_level_function(p):
+    """The linearisation state of a level is a function of that level's space:
+    the leaf values at its regular nodes and the constraint at its own
+    hanging nodes. In a 2:1 tree a hanging node of a cut mesh sits between a
+    leaf and the finer leaves next to it, so it is a hanging node of the leaf
+    mesh with the same masters: for a conforming leaf state the injected value
+    already is the constrained one; a leaf field with free values at hanging
+    nodes is corrected."""
+    mesh = Mesh(16, 2, p, coarse=4, band=(3.0, 1.0))
+    gh = GlobalHierarchy(mesh)
+    n = mesh.n_nodes
+    X = -10 + 20 * mesh.NX / mesh.M
+    Y = -10 + 20 * mesh.NY / mesh.M
+    lp = LeafProblem(mesh, Params())
+    phit_raw = np.cos(0.7 * X) * np.exp(0.3 * Y)
+    phit_raw[mesh.hanging] += 0.25     # not a leaf function
+    U = np.concatenate([lp.distribute(np.sin(0.5 * X + 0.2 * Y)), lp.distribute(np.cos(0.4 * Y) * X),
+                        lp.distribute(phit_raw)])
+    vc = GCVCycle(gh, Params(), MGParams(), U, phit_raw, np.zeros(n, bool), eigen=None)
+    seen = 0
+    for k, m in enumerate(gh.meshes):
+        li = gh.leaf_index[k]
+        lpk = LeafProblem(m, Params())
+        reg = ~m.hanging
+        assert np.all(mesh.hanging[li[m.hanging]]), k   # level hanging => leaf hanging
+        for comp, (got, leaf) in enumerate(zip(vc.states[k], (U[:n], U[n:2 * n], phit_raw))):
+            raw = leaf[li]
+            assert np.array_equal(got[reg], raw[reg])
+            assert np.allclose(got, lpk.distribute(raw), rtol=0, atol=1e-14)
+            if m.hanging.any():
+                if comp < 2:
+                    assert np.allclose(got[m.hanging], raw[m.hanging], rtol=0, atol=1e-13), k
+                else:
+                    assert np.abs(got[m.hanging] - raw[m.hanging]).min() > 0.1, k
+                    seen += 1
+    assert seen >= 2
