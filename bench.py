@@ -192,7 +192,7 @@ def main():
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--no-load-step", action="store_true",
                     help="time the Newton steps only, not the whole load step (for profiler runs)")
-    ap.add_argument("--newton-modes", default="fp64,mixed,mixed_cheb3",
+    ap.add_argument("--newton-modes", default="fp64,mixed,mixed_cheb3,gc_fp64,gc_mixed",
                     help="comma-separated subset of fp64,mixed,mixed_cheb3")
     ap.add_argument("--profile-pass", action="store_true",
                     help="only a few vmults and one plain device copy of the same vector "
@@ -219,8 +219,11 @@ def main():
     sp_ = SolverParams(E=spec.E, nu=spec.nu, Gc=spec.Gc, pressure=spec.pressure, kappa=spec.kappa,
                        ell=spec.ell)
     t0 = time.time()
+    # both multigrid hierarchies: local smoothing (Sec. 3.2) and global
+    # coarsening (modes gc_*)
+    want_gc = not args.no_newton and any(m.startswith("gc_") for m in args.newton_modes.split(","))
     g = PhaseFieldSolver(spec.n_base, spec.n_local, spec.degree, coarse=spec.coarse, band=spec.band,
-                         tile=tuple(args.tile), params=sp_)
+                         tile=tuple(args.tile), params=sp_, mg_global=want_gc)
     n_tiles, n_rec, _ = g.tile_stats()
     log(f"{spec.name}: {3 * g.n} unknowns, {g.n_levels} levels, {n_tiles} tiles, "
         f"built in {time.time() - t0:.1f}s")
@@ -261,9 +264,13 @@ def main():
         # steps); residual, GMRES and line search stay FP64 in both
         # "mixed_cheb3": the FP32 V-cycle with the FP64 configuration's smoother
         # and coarse solve, isolating the effect of the precision
-        modes = {"fp64": dict(vcycle_fp32=0, cheb_degree=3, coarse_mode=0, coarse_its=30),
-                 "mixed": dict(vcycle_fp32=1, cheb_degree=4, coarse_mode=1, coarse_its=30),
-                 "mixed_cheb3": dict(vcycle_fp32=1, cheb_degree=3, coarse_mode=0, coarse_its=30)}
+        # gc_fp64 / gc_mixed: the same two configurations with the
+        # global-coarsening hierarchy in place of local smoothing
+        modes = {"fp64": dict(vcycle_fp32=0, cheb_degree=3, coarse_mode=0, coarse_its=30, mg_kind=0),
+                 "mixed": dict(vcycle_fp32=1, cheb_degree=4, coarse_mode=1, coarse_its=30, mg_kind=0),
+                 "mixed_cheb3": dict(vcycle_fp32=1, cheb_degree=3, coarse_mode=0, coarse_its=30, mg_kind=0),
+                 "gc_fp64": dict(vcycle_fp32=0, cheb_degree=3, coarse_mode=0, coarse_its=30, mg_kind=1),
+                 "gc_mixed": dict(vcycle_fp32=1, cheb_degree=4, coarse_mode=1, coarse_its=30, mg_kind=1)}
         modes = {k: v for k, v in modes.items() if k in args.newton_modes.split(",")}
         U_ref = None
         tcv_ref = None
@@ -296,7 +303,8 @@ def main():
                             # GMRES solve per step; the solve time per GMRES iteration (V-cycle,
                             # vmult, orthogonalisation)
                             "setup_ms": t_setup / args.steps * 1e3, "solve_ms": t_solve / args.steps * 1e3,
-                            "ms_per_gmres_iteration": t_solve / max(sum(its), 1) * 1e3}
+                            "ms_per_gmres_iteration": t_solve / max(sum(its), 1) * 1e3,
+                            "level_nodes": list(g.level_nodes)}
             log(f"{mode}: Newton step {newton[mode]['ms_per_newton_step']:.1f} ms (gmres {its}; setup "
                 f"{newton[mode]['setup_ms']:.1f} ms, {newton[mode]['ms_per_gmres_iteration']:.2f} ms per GMRES "
                 f"iteration)")
@@ -329,7 +337,7 @@ def main():
             if U_ref is None:
                 U_ref, tcv_ref = Uw.clone(), tcv
             else:
-                # error of the mixed-precision load step against the FP64 one
+                # error of the other configurations' load step against the FP64 one
                 solve[mode]["rel_diff_U_vs_fp64"] = float(torch.linalg.norm(Uw - U_ref) / torch.linalg.norm(U_ref))
                 solve[mode]["rel_diff_tcv_vs_fp64"] = abs(tcv - tcv_ref) / abs(tcv_ref)
             log(f"{mode}: load step "
@@ -372,7 +380,8 @@ def main():
         "config": {"workload": spec.name, "unknowns": n_dof, "degree": spec.degree,
                    "step": "one Newton / primal-dual active set iteration of the load step from its "
                            "start (residual, active set, MG setup, GMRES(30) with the block V-cycle, "
-                           "line search), FP64"},
+                           "line search), FP64, local-smoothing V-cycle; the global-coarsening V-cycle "
+                           "is timed beside it (modes gc_*)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"leaf vmult = tile_kernel<{spec.degree}, double, MODE_J> + shared_fixup",
