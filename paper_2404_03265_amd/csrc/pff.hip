@@ -437,10 +437,9 @@ struct pff_ctx {
     }
   };
   template <int K>
-  struct McombMdotL {
-    static void run(hipStream_t st, const double* V, double* w, const double* h, int k, int64_t len, double* part) {
-      hipLaunchKernelGGL(k_mcombine_mdot_partial<K>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, w, h, k, len,
-                         part);
+  struct DcgsL {
+    static void run(hipStream_t st, double* V, const double* w, DcgsCoef cf, int64_t len, double* part) {
+      hipLaunchKernelGGL(k_dcgs2_partial<K>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, w, cf, len, part);
     }
   };
   // out = sums of the k partial columns left in red_part, copied to the host
@@ -1085,9 +1084,24 @@ struct pff_ctx {
     }
   }
 
+  // GMRES(m) with left preconditioning (Sec. 3.2, Table 1). Arnoldi by
+  // classical Gram-Schmidt twice with the second projection delayed by one
+  // step (DCGS2: Swirydowicz, Langou, Ananthan, Yang, Thomas, Numer. Linear
+  // Algebra Appl. 2021; Bielich et al., Parallel Comput. 2022). Column j of V
+  // holds q_j, the candidate for v_j after one projection, with its pending
+  // coefficients cq = V_j^T q_j and |q_j|^2; the operator is applied to q_j,
+  // and since the preconditioned operator is linear,
+  //   M^-1 A v_j = (M^-1 A q_j - V_(j+1) Hbar_j cq) / rho_j,
+  //   rho_j = (|q_j|^2 - |cq|^2)^(1/2),
+  // so the correction happens in coefficient space. Per step two sweeps over
+  // the basis: V_(j+1)^T w, then one pass writing v_j and q_(j+1) with the
+  // products V_(j+2)^T q_(j+1) and |q_(j+1)|^2 (the second projection of the
+  // next column and its norm). Where |cq|^2 would cancel more than a quarter
+  // of |q|^2, the second projection is applied explicitly instead.
   int gmres(double* x, const double* b, bool transpose, double tol, pff_gmres_info* info, bool fp32) {
     const int64_t N = 3 * n;
     const int m = std::max(1, prm.gmres_restart);
+    if (m + 2 > DCGS_MAX) throw std::runtime_error("gmres_restart too large");
     if (V_cap < m + 1) {
       if (ws) throw std::runtime_error("gmres_restart exceeds the bound workspace");
       if (V) hipFree(V);
@@ -1106,71 +1120,102 @@ struct pff_ctx {
     inf.tolerance = tol;
     int its = 0;
     bool conv = beta <= tol;
-    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), h1(m + 1), h2(m + 1);
+    // H: the Arnoldi Hessenberg matrix (for the coefficient-space
+    // correction), R: its rotated upper-triangular factor
+    std::vector<double> H(size_t(m + 1) * m), R(size_t(m) * m), cs(m), sn(m), g(m + 1);
     double* hdev = red_out + 64;
+    auto sumsq = [](const std::vector<double>& v) {
+      double r = 0.0;
+      for (double e : v) r += e * e;
+      return r;
+    };
     while (!conv && its < prm.gmres_max_its) {
-      hipLaunchKernelGGL(k_scale, dim3(grid_for(N)), dim3(256), 0, s, V, V, 1.0 / beta, N);
+      // q_0 = the preconditioned residual, unnormalised (rho_0 = beta)
+      std::vector<double> cq;
+      double nq2 = beta * beta;
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int jdone = 0;
       double resid = beta;
       for (int j = 0; j < m; ++j) {
-        double* vj = V + int64_t(j) * N;
-        double* vn = V + int64_t(j + 1) * N;
-        apply_A(t, vj, transpose);
-        apply_Minv(vn, t, fp32);
-        // classical Gram-Schmidt, twice: h1 = V^T vn; vn -= V h1 fused with
-        // h2 = V^T vn; vn -= V h2 fused with |vn|^2
-        const int k = j + 1;
-        // the coefficients stay on the device between the passes (h1 in
-        // red_out[0, k), h2 in red_out[64, 64 + k), |vn|^2 in red_out[128]);
-        // the host receives all three with one wait
-        double* d_h1 = red_out;
-        double* d_h2 = red_out + 64;
-        double* d_hn = red_out + 128;
-        launch_k<MdotL>(k, (const double*)V, (const double*)vn, k, N, red_part);
-        hipLaunchKernelGGL(k_reduce_final, dim3(k), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, k, d_h1);
-        launch_k<McombMdotL>(k, (const double*)V, vn, (const double*)d_h1, k, N, red_part);
-        hipLaunchKernelGGL(k_reduce_final, dim3(k), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, k, d_h2);
-        hipLaunchKernelGGL(k_mcombine_sq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, vn, d_h2, k, N,
-                           red_part);
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, 1, d_hn);
-        HIPCHK(hipMemcpyAsync(host_red, red_out, sizeof(double) * 129, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int i = 0; i < k; ++i) {
-          h1[i] = host_red[i];
-          h2[i] = host_red[64 + i];
-        }
-        const double hn2 = host_red[128];
-        double hn = std::sqrt(hn2);
-        std::vector<double> h(j + 2);
-        for (int i = 0; i <= j; ++i) h[i] = h1[i] + h2[i];
-        bool finite = std::isfinite(hn);
-        for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(h[i]);
+        double* qj = V + int64_t(j) * N;
+        double* qn = V + int64_t(j + 1) * N;
+        apply_A(t, qj, transpose);
+        apply_Minv(w, t, fp32);
+        const double rho = std::sqrt(nq2 - sumsq(cq));
+        // sweep 1: a_i = v_i . w (i < j), a_j = q_j . w
+        launch_k<MdotL>(j + 1, (const double*)V, (const double*)w, j + 1, N, red_part);
+        reduce_to_host(j + 1, host_red);
+        std::vector<double> a(host_red, host_red + j + 1);
+        bool finite = std::isfinite(rho) && rho > 0.0;
+        for (double e : a) finite = finite && std::isfinite(e);
         if (!finite) throw nonfinite_error("GMRES: a Gram-Schmidt coefficient or norm is not finite");
+        // e = Hbar_j cq (rows 0..j), h1 = V_(j+1)^T M^-1 A v_j
+        std::vector<double> e(j + 1, 0.0), h1(j + 1);
+        for (int i = 0; i < j; ++i)
+          for (int l = 0; l <= i + 1; ++l) e[l] += H[size_t(l) * m + i] * cq[i];
+        double ca = 0.0;
+        for (int i = 0; i < j; ++i) ca += cq[i] * a[i];
+        const double vjw = (a[j] - ca) / rho;
+        for (int i = 0; i < j; ++i) h1[i] = (a[i] - e[i]) / rho;
+        h1[j] = (vjw - e[j]) / rho;
+        // sweep 2: v_j in place, q_(j+1), V_(j+2)^T q_(j+1) and |q_(j+1)|^2
+        DcgsCoef cf{};
+        for (int i = 0; i < j; ++i) {
+          cf.c[i] = cq[i];
+          cf.d[i] = e[i] / rho + h1[i];
+        }
+        cf.gamma = e[j] / rho + h1[j];
+        cf.inv_rho = 1.0 / rho;
+        cf.j = j;
+        launch_k<DcgsL>(j + 2, V, (const double*)w, cf, N, red_part);
+        reduce_to_host(j + 2, host_red);
+        std::vector<double> cn(host_red, host_red + j + 1);
+        double nn2 = host_red[j + 1];
+        finite = std::isfinite(nn2);
+        for (double v : cn) finite = finite && std::isfinite(v);
+        if (!finite) throw nonfinite_error("GMRES: a Gram-Schmidt coefficient or norm is not finite");
+        if (sumsq(cn) > 0.25 * nn2) {
+          // the delayed norm would cancel: project q_(j+1) now
+          HIPCHK(hipMemcpyAsync(hdev, cn.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, s));
+          hipLaunchKernelGGL(k_mcombine_sq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, (const double*)V, qn,
+                             (const double*)hdev, j + 1, N, red_part);
+          reduce_to_host(1, host_red);
+          nn2 = host_red[0];
+          if (!std::isfinite(nn2)) throw nonfinite_error("GMRES: a Gram-Schmidt norm is not finite");
+          cq.assign(size_t(j + 1), 0.0);
+        } else {
+          cq = cn;
+        }
+        nq2 = nn2;
+        const double hn = std::sqrt(std::max(nq2 - sumsq(cq), 0.0));
+        std::vector<double> h(j + 2);
+        for (int i = 0; i <= j; ++i) h[i] = h1[i] + cn[i];
         for (int i = 0; i < j; ++i) {
           const double tt = cs[i] * h[i] + sn[i] * h[i + 1];
           h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
           h[i] = tt;
         }
+        for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = h1[i] + cn[i];
+        H[size_t(j + 1) * m + j] = hn;
         const double den = std::hypot(h[j], hn);
         cs[j] = h[j] / den;
         sn[j] = hn / den;
-        h[j] = den;
         g[j + 1] = -sn[j] * g[j];
         g[j] = cs[j] * g[j];
-        for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = h[i];
+        // the triangular factor R (rotated columns) for the back substitution
+        for (int i = 0; i < j; ++i) R[size_t(i) * m + j] = h[i];
+        R[size_t(j) * m + j] = den;
         resid = std::fabs(g[j + 1]);
         ++its;
         jdone = j + 1;
-        if (hn > 0.0) hipLaunchKernelGGL(k_scale, dim3(grid_for(N)), dim3(256), 0, s, vn, vn, 1.0 / hn, N);
         if (resid <= tol || its >= prm.gmres_max_its || hn == 0.0) break;
       }
       std::vector<double> y(jdone);
       for (int i = jdone - 1; i >= 0; --i) {
         double sum = g[i];
-        for (int k = i + 1; k < jdone; ++k) sum -= H[size_t(i) * m + k] * y[k];
-        y[i] = sum / H[size_t(i) * m + i];
+        for (int k = i + 1; k < jdone; ++k) sum -= R[size_t(i) * m + k] * y[k];
+        y[i] = sum / R[size_t(i) * m + i];
       }
       HIPCHK(hipMemcpyAsync(hdev, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL(k_mcombine, dim3(grid_for(N)), dim3(256), 0, s, x, V, hdev, jdone, N, 1.0);

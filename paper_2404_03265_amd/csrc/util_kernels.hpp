@@ -510,41 +510,6 @@ __global__ void __launch_bounds__(RED_THREADS) k_mdot_partial(const double* V, c
   block_partials<K>(s, k, part);
 }
 
-// w -= sum_j h[j] V[j], then partials of V[j] . w for the updated w (the
-// second pass's products, taken from the vector the first pass leaves)
-template <int K>
-__global__ void __launch_bounds__(RED_THREADS) k_mcombine_mdot_partial(const double* V, double* w, const double* h,
-                                                                         int k, int64_t len, double* part) {
-  double s[K];
-#pragma unroll
-  for (int j = 0; j < K; ++j) s[j] = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x) {
-    double wi = w[i];
-    if constexpr (K <= 32) {
-      // the K values of element i stay in registers for both passes (a second
-      // read would miss the caches: a wave touches K lines per element)
-      double v[K];
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        v[j] = j < k ? V[int64_t(j) * len + i] : 0.0;
-        wi -= h[j < k ? j : 0] * v[j];
-      }
-      w[i] = wi;
-#pragma unroll
-      for (int j = 0; j < K; ++j) s[j] += v[j] * wi;
-    } else {
-#pragma unroll
-      for (int j = 0; j < K; ++j)
-        if (j < k) wi -= h[j] * V[int64_t(j) * len + i];
-      w[i] = wi;
-#pragma unroll
-      for (int j = 0; j < K; ++j)
-        if (j < k) s[j] += V[int64_t(j) * len + i] * wi;
-    }
-  }
-  block_partials<K>(s, k, part);
-}
-
 // w -= sum_j h[j] V[j], then the partial of w . w
 __global__ void __launch_bounds__(RED_THREADS) k_mcombine_sq_partial(const double* V, double* w, const double* h,
                                                                        int k, int64_t len, double* part) {
@@ -556,6 +521,71 @@ __global__ void __launch_bounds__(RED_THREADS) k_mcombine_sq_partial(const doubl
     s[0] += wi * wi;
   }
   block_partials<1>(s, 1, part);
+}
+
+// Second sweep of the delayed classical Gram-Schmidt step of GMRES: column j
+// of V holds q_j (one projection done, second one pending with coefficients
+// c), w = M^-1 A q_j. Per element:
+//   v_j     = (q_j - sum_l c_l v_l) / rho_j            (written over q_j)
+//   q_(j+1) = w / rho_j - sum_l d_l v_l - gamma v_j    (written to column j + 1)
+// (l < j) and the partials of v_l . q_(j+1) (l <= j) and |q_(j+1)|^2, j + 2
+// sums in all.
+constexpr int DCGS_MAX = 64;
+struct DcgsCoef {
+  double c[DCGS_MAX];
+  double d[DCGS_MAX];
+  double inv_rho, gamma;
+  int j;
+};
+
+template <int K>
+__global__ void __launch_bounds__(RED_THREADS) k_dcgs2_partial(double* V, const double* w, const DcgsCoef cf,
+                                                                 int64_t len, double* part) {
+  const int j = cf.j;
+  double s[K];
+#pragma unroll
+  for (int l = 0; l < K; ++l) s[l] = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x) {
+    const double q = V[int64_t(j) * len + i];
+    const double wi = w[i];
+    double vj, qn;
+    if constexpr (K <= 32) {
+      // the basis values of element i stay in registers for the products
+      double v[K];
+      double sc = 0.0, sd = 0.0;
+#pragma unroll
+      for (int l = 0; l < K; ++l) {
+        v[l] = l < j ? V[int64_t(l) * len + i] : 0.0;
+        sc += cf.c[l < j ? l : 0] * v[l];
+        sd += cf.d[l < j ? l : 0] * v[l];
+      }
+      vj = (q - sc) * cf.inv_rho;
+      qn = wi * cf.inv_rho - sd - cf.gamma * vj;
+#pragma unroll
+      for (int l = 0; l < K; ++l) s[l] += v[l] * qn;
+    } else {
+      double sc = 0.0, sd = 0.0;
+      for (int l = 0; l < j; ++l) {
+        const double vl = V[int64_t(l) * len + i];
+        sc += cf.c[l] * vl;
+        sd += cf.d[l] * vl;
+      }
+      vj = (q - sc) * cf.inv_rho;
+      qn = wi * cf.inv_rho - sd - cf.gamma * vj;
+#pragma unroll
+      for (int l = 0; l < K; ++l)
+        if (l < j) s[l] += V[int64_t(l) * len + i] * qn;
+    }
+    V[int64_t(j) * len + i] = vj;
+    V[int64_t(j + 1) * len + i] = qn;
+    // slots j and j + 1 (the padded register slots l >= j summed zero products)
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      if (l == j) s[l] += vj * qn;
+      if (l == j + 1) s[l] += qn * qn;
+    }
+  }
+  block_partials<K>(s, j + 2, part);
 }
 
 // stage 2: out[j] = sum over nb blocks of part[blk * k + j]
