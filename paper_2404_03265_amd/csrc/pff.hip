@@ -17,6 +17,7 @@
 #include "../../include/pff.h"
 #include "mesh.hpp"
 #include "tile_kernel.hpp"
+#include "tile_batch.hpp"
 #include "util_kernels.hpp"
 #include "coarse_kernel.hpp"
 
@@ -294,6 +295,7 @@ struct pff_ctx {
   bool coarse_fusable = false;
   void* part = nullptr;         // partial sums of shared nodes (largest tile set)
   size_t part_bytes = 0;
+  double* part_jt = nullptr;    // leaf partial sums of JT_BATCH_MAX right-hand sides (vmult_T)
   void* scratch_dev = nullptr;  // device address of `scratch` on this context's GPU
   int V_cap = 0;
   // caller-bound workspace (pff_bind_workspace): the work vectors, level
@@ -337,26 +339,7 @@ struct pff_ctx {
       part_buf = part;
       part_cap = part_bytes;
     }
-    a.tile_info = t.info;
-    a.shared = t.shared;
-    a.cell_loc = t.loc;
-    a.cell_loc_sub = t.loc_sub;
-    a.cell_info = t.cinfo;
-    a.hang_rec = t.hang_rec;
-    a.hang_w = t.hang_w;
-    a.hang_col = t.hang_col;
-    a.flags = fl;
-    a.n = nn;
-    a.max_local = t.max_local;
-    a.part = reinterpret_cast<T*>(part_buf);
-    a.n_slots = t.n_slots;
-    a.n_private = t.n_private;
-    a.n_shared = t.n_shared;
-    a.sh_tab = t.sh_tab;
-    a.sh_w = t.sh_w;
-    a.H0 = T(mesh.level_H[0]);
-    a.B = make_basis<T>(p);
-    a.mat = mat();
+    tile_args(t, fl, nn, a, part_buf);
     using TR = ModeTraits<MODE>;
     constexpr int NF = TR::n_src + TR::n_state;
     // staged fields (the accumulators reuse the first three), node flags
@@ -382,6 +365,63 @@ struct pff_ctx {
     }
     if (t.n_shared > 0)
       hipLaunchKernelGGL((shared_fixup<T, MODE, EPI>), dim3(grid_for(t.n_shared)), dim3(256), 0, s, a);
+    HIPCHK(hipGetLastError());
+  }
+
+  // the tables, sizes and constants of a tile set in TileArgs
+  template <typename T>
+  void tile_args(const DevTiles& t, const uint8_t* fl, int64_t nn, TileArgs<T>& a, void* part_buf) {
+    a.tile_info = t.info;
+    a.shared = t.shared;
+    a.cell_loc = t.loc;
+    a.cell_loc_sub = t.loc_sub;
+    a.cell_info = t.cinfo;
+    a.hang_rec = t.hang_rec;
+    a.hang_w = t.hang_w;
+    a.hang_col = t.hang_col;
+    a.flags = fl;
+    a.n = nn;
+    a.max_local = t.max_local;
+    a.part = reinterpret_cast<T*>(part_buf);
+    a.n_slots = t.n_slots;
+    a.n_private = t.n_private;
+    a.n_shared = t.n_shared;
+    a.sh_tab = t.sh_tab;
+    a.sh_w = t.sh_w;
+    a.H0 = T(mesh.level_H[0]);
+    a.B = make_basis<T>(p);
+    a.mat = mat();
+  }
+
+  // dst = J~^T src for nb <= JT_BATCH_MAX right-hand sides (3n each), the
+  // leaf state read once per tile
+  void leaf_jt_batch(double* dst, const double* src, int nb) {
+    const DevTiles& t = tiles;
+    TileArgs<double> a{};
+    tile_args(t, flags, n, a, part_jt);
+    a.src = src;
+    a.dst = dst;
+    const double* st[4];
+    leaf_state4(st);
+    for (int i = 0; i < 4; ++i) a.st[i] = st[i];
+    const size_t lds = size_t(7 * t.max_local) * sizeof(double) + size_t(t.max_local);
+    const int threads = std::max(64, ((t.max_cells + 63) / 64) * 64);
+    if (threads > 256) throw std::runtime_error("a tile holds at most 256 cells");
+    if (nb < 1 || nb > JT_BATCH_MAX) throw std::runtime_error("vmult_T batch chunk out of range");
+    if (lds > size_t(160 * 1024)) throw std::runtime_error("tile needs more LDS than a CU has; use smaller tiles");
+    const void* kfn = p == 1 ? reinterpret_cast<const void*>(&tile_kernel_jt_batch<1>)
+                             : reinterpret_cast<const void*>(&tile_kernel_jt_batch<2>);
+    if (lds > size_t(64 * 1024))
+      HIPCHK(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    a.tile_base = 0;
+    if (t.n_tiles > 0) {
+      if (p == 1)
+        hipLaunchKernelGGL(tile_kernel_jt_batch<1>, dim3(t.n_tiles), dim3(threads), lds, s, a, nb);
+      else
+        hipLaunchKernelGGL(tile_kernel_jt_batch<2>, dim3(t.n_tiles), dim3(threads), lds, s, a, nb);
+    }
+    if (t.n_shared > 0)
+      hipLaunchKernelGGL(shared_fixup_jt_batch, dim3(grid_for(t.n_shared * nb)), dim3(256), 0, s, a, nb);
     HIPCHK(hipGetLastError());
   }
 
@@ -476,6 +516,7 @@ struct pff_ctx {
     double* pp = nullptr;
     take(pp, int64_t(part_bytes / sizeof(double)));
     if (carve) part = pp;
+    take(carve ? part_jt : dummy, int64_t(JT_BATCH_MAX) * 3 * tiles.n_slots);
     std::vector<DevLevel*> all;
     for (DevLevel& L : lv) all.push_back(&L);
     for (DevLevel& L : gcown) all.push_back(&L);
@@ -511,6 +552,7 @@ struct pff_ctx {
       mass = dalloc<double>(3 * n);
       for (int i = 0; i < 8; ++i) wv[i] = dalloc<double>(3 * n);
       part = dalloc<double>(int64_t(part_bytes / sizeof(double)));
+      part_jt = dalloc<double>(int64_t(JT_BATCH_MAX) * 3 * tiles.n_slots);
     }
     // lumped phase-field mass (the B of Alg. 2)
     leaf_op<MODE_MASS>(mass, nullptr, nullptr);
@@ -1456,7 +1498,7 @@ int pff_destroy(pff_ctx* c) {
   if (!c->ws) {
     f(c->U); f(c->phio); f(c->phit); f(c->mass);
     for (int i = 0; i < 8; ++i) f(c->wv[i]);
-    f(c->V); f(c->part);
+    f(c->V); f(c->part); f(c->part_jt);
   }
   f(c->red_part); f(c->red_out); f(c->ccg_s); f(c->coarse_nodes); f(c->eig_sc); f(c->eig_al); f(c->eig_be);
   if (c->host_red) hipHostFree(c->host_red);
@@ -1662,7 +1704,17 @@ int pff_vmult_T(pff_ctx* c, double* dst, const double* src, int32_t batch, void*
   if (!c->has_state) { c->err = "vmult_T needs a state"; return PFF_E_STATE; }
   GUARD_BEGIN
   c->s = static_cast<hipStream_t>(stream);
-  for (int b = 0; b < batch; ++b) c->apply_A(dst + int64_t(b) * 3 * c->n, src + int64_t(b) * 3 * c->n, true);
+  c->ensure_work();
+  if (batch == 1) {
+    c->apply_A(dst, src, true);
+    return PFF_OK;
+  }
+  // chunks of at most JT_BATCH_MAX right-hand sides, the state read once per
+  // tile and chunk
+  for (int b = 0; b < batch; b += JT_BATCH_MAX) {
+    const int nb = std::min(JT_BATCH_MAX, batch - b);
+    c->leaf_jt_batch(dst + int64_t(b) * 3 * c->n, src + int64_t(b) * 3 * c->n, nb);
+  }
   return PFF_OK;
   GUARD_END(c)
 }

@@ -248,6 +248,95 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
   }
 }
 
+// One cell of the transposed Jacobian, in the reference units of
+// jacobian_cell: the coupling block G_phi,u moves from the phi rows to the u
+// rows, weighted by the phase-field operand,
+//   u rows:   [g(phit) sigma^(du) + dphi H B] : grad^ psi
+//   phi rows: H^2 c1 dphi psi + Gc l grad^ dphi . grad^ psi
+// (same fields and the same H B, c1 as the forward routine). The order keeps
+// few values live: state coefficients, then the phase-field rows (whose
+// operand scales H B in place), then the displacement rows.
+template <int P, typename T, class Gather>
+__device__ __forceinline__ void jacobian_t_cell(const Basis<T>& B, T H, T mu, T lam, T kap, T pr, T Gc, T ell,
+                                                Gather&& gather, T (&out)[3][(P + 1) * (P + 1)]) {
+  constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
+  constexpr int FUX = 3, FUY = 4, FPHI = 5, FPT = 6;
+  const T twopH = T(2) * pr * H, gcl2 = H * H * Gc / ell, gcell = Gc * ell;
+  T bxx[NQ], byy[NQ], bxy[NQ];
+  {
+    T c1[NQ];
+    {
+      T u[NL], sx1[NQ], sy1[NQ], sx2[NQ], sy2[NQ];
+      gather(FUX, u);
+      interp_g<P, T>(B, u, sx1, sy1);
+      gather(FUY, u);
+      interp_g<P, T>(B, u, sx2, sy2);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const T exx = sx1[q], eyy = sy2[q], exy = T(0.5) * (sy1[q] + sx2[q]);
+        const T tr = exx + eyy;
+        const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+        const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
+        c1[q] = (T(1) - kap) * S + twopH * tr + gcl2;
+        bxx[q] = sxx;
+        byy[q] = syy;
+        bxy[q] = sxy;
+      }
+    }
+    {
+      T u[NL], pq[NQ];
+      gather(FPHI, u);
+      interp_v<P, T>(B, u, pq);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const T f = T(2) * (T(1) - kap) * pq[q], t = twopH * pq[q];
+        bxx[q] = f * bxx[q] + t;
+        byy[q] = f * byy[q] + t;
+        bxy[q] = f * bxy[q];
+      }
+    }
+    // phi rows; the operand dphi then scales H B for the u rows
+    T u[NL], pv[NQ], px[NQ], py[NQ];
+    gather(2, u);
+    interp_vg<P, T>(B, u, pv, px, py);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      bxx[q] *= pv[q];
+      byy[q] *= pv[q];
+      bxy[q] *= pv[q];
+      pv[q] = c1[q] * pv[q];
+      px[q] = gcell * px[q];
+      py[q] = gcell * py[q];
+    }
+    integrate_w<P, T>(B, pv, px, py, out[2]);
+  }
+  T dxx[NQ], dxy[NQ], dyx[NQ], dyy[NQ];
+  {
+    T u[NL];
+    gather(0, u);
+    interp_g<P, T>(B, u, dxx, dxy);
+    gather(1, u);
+    interp_g<P, T>(B, u, dyx, dyy);
+  }
+  {
+    T u[NL], tq[NQ];
+    gather(FPT, u);
+    interp_v<P, T>(B, u, tq);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const T gq = (T(1) - kap) * tq[q] * tq[q] + kap;
+      const T exx = dxx[q], eyy = dyy[q], exy2 = dxy[q] + dyx[q];
+      const T tr = exx + eyy;
+      const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = mu * exy2;
+      dxx[q] = gq * sxx + bxx[q];
+      dxy[q] = gq * sxy + bxy[q];
+      dyx[q] = gq * sxy + bxy[q];
+      dyy[q] = gq * syy + byy[q];
+    }
+  }
+  integrate_gw<P, T>(B, dxx, dxy, out[0]);
+  integrate_gw<P, T>(B, dyx, dyy, out[1]);
+}
 
 // One cell of an operator mode: gather(f, u) fetches the cell's nodal values
 // of staged field f, out receives the cell's contributions to its (p+1)^2
@@ -272,27 +361,23 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
 
   if constexpr (MODE == MODE_J || MODE == MODE_LEVEL) {
     jacobian_cell<P, T, MODE == MODE_J>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
-  } else if constexpr (MODE == MODE_JT || MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
+  } else if constexpr (MODE == MODE_JT) {
+    jacobian_t_cell<P, T>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
+  } else if constexpr (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
     // state-derived coefficients at the Gauss points:
-    //   g = (1-k) phit^2 + k, c1 = (1-k) S + 2 p tr e(u) + Gc/l,
-    //   B = 2 (1-k) phi sigma(u) + 2 p phi I (coupling, leaf only)
+    //   g = (1-k) phit^2 + k, c1 = (1-k) S + 2 p tr e(u) + Gc/l
+    // (the leaf stages u_x, u_y, phi, phit; a level u_x, u_y, phit)
     constexpr int SU = TR::n_src;
-    T cg[NQ], cc1[NQ], bxx[NQ], byy[NQ], bxy[NQ];
+    constexpr int FPT = SU + (TR::leaf ? 3 : 2);
+    T cg[NQ], cc1[NQ];
     {
-      T u[NL], gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pq[NQ], tq[NQ];
+      T u[NL], gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], tq[NQ];
       gather(SU + 0, u);
       interp_g<P, T>(a.B, u, gx1, gy1);
       gather(SU + 1, u);
       interp_g<P, T>(a.B, u, gx2, gy2);
-      if constexpr (TR::leaf) {
-        gather(SU + 2, u);
-        interp_v<P, T>(a.B, u, pq);
-        gather(SU + 3, u);
-        interp_v<P, T>(a.B, u, tq);
-      } else {
-        gather(SU + 2, u);
-        interp_v<P, T>(a.B, u, tq);
-      }
+      gather(FPT, u);
+      interp_v<P, T>(a.B, u, tq);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
@@ -301,69 +386,28 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
         const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
         cg[q] = (T(1) - kap) * tq[q] * tq[q] + kap;
         cc1[q] = (T(1) - kap) * S + T(2) * pr * tr + Gc / ell;
-        if constexpr (TR::leaf) {
-          const T ph = pq[q];
-          bxx[q] = T(2) * (T(1) - kap) * ph * sxx + T(2) * pr * ph;
-          byy[q] = T(2) * (T(1) - kap) * ph * syy + T(2) * pr * ph;
-          bxy[q] = T(2) * (T(1) - kap) * ph * sxy;
-        } else {
-          bxx[q] = byy[q] = bxy[q] = T(0);
-        }
       }
     }
-    if constexpr (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
-      // diagonal of the block-diagonal part for each local master dof:
-      // interpolate the (hanging-mapped) unit vector and evaluate the forms
+    // diagonal of the block-diagonal part for each local master dof:
+    // interpolate the (hanging-mapped) unit vector and evaluate the forms
 #pragma unroll
-      for (int k = 0; k < NL; ++k) {
-        T u[NL], vq[NQ], gxq[NQ], gyq[NQ];
+    for (int k = 0; k < NL; ++k) {
+      T u[NL], vq[NQ], gxq[NQ], gyq[NQ];
 #pragma unroll
-        for (int j = 0; j < NL; ++j) u[j] = (j == k) ? T(1) : T(0);
-        if (hang) hang_apply<P, T>(a.B, u, info);
-        interp_vg<P, T>(a.B, u, vq, gxq, gyq);
-        T dux = T(0), duy = T(0), dph = T(0);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          const T gx = gxq[q] * invH, gy = gyq[q] * invH, JxW = H * H * wq[q];
-          dux += JxW * cg[q] * ((T(2) * mu + lam) * gx * gx + mu * gy * gy);
-          duy += JxW * cg[q] * (mu * gx * gx + (T(2) * mu + lam) * gy * gy);
-          dph += JxW * (cc1[q] * vq[q] * vq[q] + Gc * ell * (gx * gx + gy * gy));
-        }
-        out[0][k] = dux;
-        out[1][k] = duy;
-        out[2][k] = dph;
-      }
-    } else {
-      // transpose of the Jacobian: the coupling moves to the u rows,
-      //   u rows: g sigma(s_u) : grad psi + s_phi B : grad psi
-      T gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], pv[NQ], px[NQ], py[NQ];
-      {
-        T u[NL];
-        gather(0, u);
-        interp_g<P, T>(a.B, u, gx1, gy1);
-        gather(1, u);
-        interp_g<P, T>(a.B, u, gx2, gy2);
-        gather(2, u);
-        interp_vg<P, T>(a.B, u, pv, px, py);
-      }
+      for (int j = 0; j < NL; ++j) u[j] = (j == k) ? T(1) : T(0);
+      if (hang) hang_apply<P, T>(a.B, u, info);
+      interp_vg<P, T>(a.B, u, vq, gxq, gyq);
+      T dux = T(0), duy = T(0), dph = T(0);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
-        const T tr = exx + eyy;
-        const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
-        const T wg = H * wq[q];
-        const T gq = cg[q];
-        gx1[q] = wg * (gq * sxx + pv[q] * bxx[q]);
-        gy1[q] = wg * (gq * sxy + pv[q] * bxy[q]);
-        gx2[q] = wg * (gq * sxy + pv[q] * bxy[q]);
-        gy2[q] = wg * (gq * syy + pv[q] * byy[q]);
-        pv[q] = H * H * wq[q] * cc1[q] * pv[q];
-        px[q] = wq[q] * Gc * ell * px[q];
-        py[q] = wq[q] * Gc * ell * py[q];
+        const T gx = gxq[q] * invH, gy = gyq[q] * invH, JxW = H * H * wq[q];
+        dux += JxW * cg[q] * ((T(2) * mu + lam) * gx * gx + mu * gy * gy);
+        duy += JxW * cg[q] * (mu * gx * gx + (T(2) * mu + lam) * gy * gy);
+        dph += JxW * (cc1[q] * vq[q] * vq[q] + Gc * ell * (gx * gx + gy * gy));
       }
-      integrate_g<P, T>(a.B, gx1, gy1, out[0]);
-      integrate_g<P, T>(a.B, gx2, gy2, out[1]);
-      integrate<P, T>(a.B, pv, px, py, out[2]);
+      out[0][k] = dux;
+      out[1][k] = duy;
+      out[2][k] = dph;
     }
   } else if constexpr (MODE == MODE_RESID || MODE == MODE_DGC || MODE == MODE_DE || MODE == MODE_DP) {
     // residual F(U) of Problem 2 (phi~ in degradation and u-pressure):

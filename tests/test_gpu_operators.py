@@ -121,15 +121,22 @@ def test_vmult_matches_oracle(name, p, mask):
 
 @pytest.mark.parametrize("name,p", [(n, p) for n in MESHES for p in (1, 2)])
 def test_vmult_transpose_matches_oracle(name, p):
+    """J~^T against the oracle's assembled transpose: one vector, and a
+    batch of 11 (a full chunk of 8 right-hand sides with the state read once
+    per tile, then a ragged chunk of 3), each equal bit for bit to the
+    one-vector kernel."""
     c = case(name, p)
     J = c.lp.masked_operator(c.U_o, c.phit_o, c.active_o)
-    batch = 3
+    batch = 11
     srcs = [inputs.random_vector(c.X, c.Y, 100 + i) for i in range(batch)]
     out = c.g.vmult_T(c.dev(np.concatenate(srcs)), batch=batch).cpu().numpy()
     for i in range(batch):
         ref = c.to_g(J.T @ c.to_o(srcs[i]))
         got = out[i * 3 * c.n:(i + 1) * 3 * c.n]
-        assert rel_err(got, ref) <= TOL
+        assert rel_err(got, ref) <= TOL, i
+        one = c.g.vmult_T(c.dev(srcs[i])).cpu().numpy()
+        assert rel_err(one, ref) <= TOL, i
+        assert np.array_equal(got, one), (i, np.abs(got - one).max())
 
 
 @pytest.mark.parametrize("name,p", [(n, p) for n in MESHES for p in (1, 2)])

@@ -5,7 +5,7 @@ These shapes take the kernels' other code paths: Q1 tiles of 8 x 8 and 3 x 5
 cells need several staging rounds, so their Jacobian identity rows are written
 while staging and the level epilogues load their inputs themselves; Q2 tiles
 of 16 x 16 cells span four waves and accumulate in colour phases. The leaf
-vmult, its transpose and the residual must match the FP64 oracle at 1e-12,
+vmult, its transpose (one vector and a batch) and the residual must match the FP64 oracle at 1e-12,
 and the FP64 V-cycle must match the one of the default tiles at 1e-12 (same
 operators, different summation order)."""
 import numpy as np
@@ -42,6 +42,12 @@ def test_leaf_operators_other_tiles(p, tile):
     assert rel_err(got, c.to_g(J @ c.to_o(src))) <= TOL
     gotT = c.g.vmult_T(c.dev(src), batch=1).cpu().numpy()
     assert rel_err(gotT, c.to_g(J.T @ c.to_o(src))) <= TOL
+    # the batched transpose (state staged once per tile, one pass per
+    # right-hand side): bit for bit the one-vector result
+    src2 = inputs.random_vector(c.X, c.Y, 22)
+    gotB = c.g.vmult_T(c.dev(np.concatenate([src, src2])), batch=2).cpu().numpy()
+    assert np.array_equal(gotB[:3 * c.n], gotT)
+    assert rel_err(gotB[3 * c.n:], c.to_g(J.T @ c.to_o(src2))) <= TOL
     U = c.dev(c.to_g(c.U_o))
     R = c.g.residual(U).cpu().numpy()
     ref = c.to_g(c.lp.residual(c.U_o, c.phit_o) * np.concatenate([~c.om.hanging] * 3))
