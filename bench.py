@@ -71,6 +71,14 @@ def tcv_sneddon(spec) -> float:
     return 2.0 * math.pi * spec.pressure / (spec.E / (1.0 - spec.nu ** 2))
 
 
+def cod_sneddon(spec, x: float) -> float:
+    """Sneddon's opening 4 p l0 / E' (1 - x^2 / l0^2)^(1/2) for |x| < l0 (l0 = 1), the
+    total jump whose integral over x is the crack volume 2 pi p l0^2 / E'."""
+    import math
+    ep = spec.E / (1.0 - spec.nu ** 2)
+    return 4.0 * spec.pressure / ep * math.sqrt(max(0.0, 1.0 - x * x)) if abs(x) < 1.0 else 0.0
+
+
 def make_state(g, spec, seed=0, random=True):
     import numpy as np
     import torch
@@ -593,12 +601,18 @@ def scenario_table2(log, local_max=8, kappa="1e-10"):
         tcv = g.tcv(U)
         gm = [i["gmres_iterations"] for i in infos]
         ref = tcv_sneddon(spec)
+        # COD(x) (Sec. 4) across the crack against Sneddon's opening
+        xs = [-0.75, -0.5, -0.25, 0.0, 0.25, 0.5, 0.75]
+        cod = [float(v) for v in g.cod(U, xs)]
+        cod_ref = [cod_sneddon(spec, x) for x in xs]
         row = {"local_levels": L, "h": h, "kappa": kap, "unknowns": 3 * g.n, "tcv": tcv,
-               "tcv_error": abs(tcv - ref) / ref, "newton_steps": len(infos),
+               "tcv_error": abs(tcv - ref) / ref, "cod_x": xs, "cod": cod, "cod_ref": cod_ref,
+               "cod_error_x0": abs(cod[3] - cod_ref[3]) / cod_ref[3], "newton_steps": len(infos),
                "converged": bool(infos[-1]["active_changed"] == 0 and infos[-1]["residual_before"] <= 1e-7),
                "mean_gmres": sum(gm) / len(gm), "max_gmres": max(gm), "seconds": dt}
         rows.append(row)
         log(f"table2 L={L}: h {h:.4f}, {row['unknowns']} unknowns, TCV error {100 * row['tcv_error']:.2f} %, "
+            f"COD(0) error {100 * row['cod_error_x0']:.2f} %, "
             f"{len(infos)} Newton steps, GMRES mean {row['mean_gmres']:.2f} max {row['max_gmres']}, {dt:.2f} s")
         g.close()
         del g

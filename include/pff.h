@@ -86,7 +86,11 @@ typedef struct {
  *  cheb_degree: Chebyshev updates per smoothing step; smooth_range (0.08) and
  *  upper_factor (1.2): smoothing interval [smooth_range, upper_factor] *
  *  lambda_max (Sec. 3.2); eig_cg_its: CG steps of the eigenvalue estimate
- *  (1..200, else PFF_E_ARG);
+ *  on levels > 0 (1..200, else PFF_E_ARG; default 20: with 10, the estimate
+ *  of the finest level's displacement block stays up to 37 % below
+ *  lambda_max once a crack of stiffness kappa ~ 1e-12 h is present, beyond
+ *  the 1.2 safety factor, and the smoother amplifies the top of the
+ *  spectrum);
  *  coarse_mode 0: Chebyshev over [lambda_min, upper_factor * lambda_max] on
  *  level 0 with coarse_its updates (Sec. 3.2); coarse_mode 1: coarse_its
  *  Jacobi-preconditioned CG steps from zero on level 0, each block with its
@@ -307,6 +311,16 @@ int pff_residual(pff_ctx* ctx, double* R, const double* U, int32_t masked, void*
  * if dTCVdU != NULL, its derivative with respect to the unknowns (3n,
  * condensed). Synchronises. */
 int pff_tcv(pff_ctx* ctx, const double* U, double* tcv, double* dTCVdU, void* stream);
+/* Crack opening displacement COD(x) = int u . grad phi dy along the vertical
+ * line at x (Sec. 4), for nx positions x (host array, physical coordinates
+ * in (-10, 10)); cod: host array of nx results. U: device, 3n; hanging
+ * entries are not read (cells with hanging faces take the coarse face's
+ * values). A line on a cell edge belongs to the cell on its right; a
+ * position outside [-10, 10) gives 0. Each cell integrates with p + 1 Gauss
+ * points in y (exact for the degree-2p integrand). Lines are processed in
+ * launches of up to 64; no device allocation. Synchronises. Errors: PFF_E_ARG
+ * (null pointers with nx > 0, nx < 0, a non-finite position). */
+int pff_cod(pff_ctx* ctx, const double* U, const double* x, int32_t nx, double* cod, void* stream);
 /* out[0..2] = z^T dF~/d(Gc, E, p) at the loaded state, constrained rows of z
  * ignored (host out): the residual of Problem 2 differentiated in the
  * material parameters of Table 1 (sigma is linear in E at fixed nu; Gc and

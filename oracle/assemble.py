@@ -33,7 +33,7 @@ from dataclasses import dataclass
 import numpy as np
 import scipy.sparse as sp
 
-from .fe import Element
+from .fe import Element, basis_1d, gauss_01
 from .mesh import Mesh
 
 
@@ -321,6 +321,41 @@ class LeafProblem:
         vy, _, _ = at_points(cs.el, cs.H, uy)
         _, px, py = at_points(cs.el, cs.H, ph)
         return float(np.sum(cs.JxW * (vx * px + vy * py)))
+
+    def cod(self, U, xs):
+        """Crack opening displacement (Sec. 4): COD(x) = the integral over y of
+        u . grad phi along the vertical line at x, for each x in xs. Summed
+        over the leaf cells whose x-range [x_c, x_c + H) holds x (a line on a
+        cell boundary belongs to the cell on its right; x = 10 lies in none),
+        each by p + 1 Gauss points in y, which is exact for the degree-2p
+        integrand. U: nodal values with hanging entries set (as in tcv)."""
+        m = self.mesh
+        n = self.n
+        p = m.p
+        t, wt = gauss_01(p + 1)
+        vt, dt = basis_1d(p, t)                       # (p+1 points) x (p+1 functions)
+        H = m.H(m.cell_level)
+        xc = -10.0 + m.cell_i * H
+        out = np.zeros(len(xs))
+        comps = [U[:n], U[n:2 * n], U[2 * n:3 * n]]
+        for j, x in enumerate(xs):
+            sel = np.flatnonzero((xc <= x) & (x < xc + H))
+            total = 0.0
+            for c in sel:
+                s = (x - xc[c]) / H[c]
+                vs, ds = basis_1d(p, [s])
+                vs, ds = vs[0], ds[0]
+                # nodal values as (b, a) arrays: node k = a + (p + 1) b
+                ux, uy, ph = (v[m.cell_nodes[c]].reshape(p + 1, p + 1) for v in comps)
+                # along the line: f(t_q) = sum_ab f_ab l_a(s) l_b(t_q); reference
+                # derivatives, since dy = H dt cancels the 1 / H of the gradient
+                uxq = vt @ ux @ vs
+                uyq = vt @ uy @ vs
+                psq = vt @ ph @ ds
+                ptq = dt @ ph @ vs
+                total += float(np.sum(wt * (uxq * psq + uyq * ptq)))
+            out[j] = total
+        return out
 
     def tcv_gradient(self, U):
         """d TCV / d(master values), blocked, as C^T of the nodal gradient."""

@@ -50,7 +50,7 @@ class MGParams:
     cheb_degree: int = 3        # number of Chebyshev updates per smoothing
     smooth_range: float = 0.08  # lower end of the interval as a fraction of lambda_max
     upper_factor: float = 1.2   # upper end: factor on lambda_max
-    eig_cg_its: int = 10        # CG iterations for the eigenvalue estimate
+    eig_cg_its: int = 20        # CG iterations for the eigenvalue estimate (levels > 0)
     coarse_mode: str = "cheb"   # 'cheb' (Sec. 3.2) or 'cg'
     coarse_its: int = 30        # coarse Chebyshev degree or CG iterations
     coarse_eig_its: int = 40    # CG iterations for the coarse eigenvalue estimate

@@ -37,7 +37,7 @@ class SolverParams:
     cheb_degree: int = 3
     smooth_range: float = 0.08
     upper_factor: float = 1.2
-    eig_cg_its: int = 10
+    eig_cg_its: int = 20
     coarse_mode: int = 0
     coarse_its: int = 30
     coarse_eig_its: int = 40
@@ -258,6 +258,14 @@ class PhaseFieldSolver:
         g = torch.empty_like(U) if grad else None
         self._check(self.lib.pff_tcv(self.h, _ptr(U), C.byref(v), _ptr(g), _stream()))
         return (v.value, g) if grad else v.value
+
+    def cod(self, U, xs):
+        """Crack opening displacement COD(x) (Sec. 4) at the positions xs."""
+        x = np.ascontiguousarray(np.asarray(xs, dtype=np.float64))
+        out = np.zeros(x.size)
+        self._check(self.lib.pff_cod(self.h, _ptr(U), x.ctypes.data_as(C.c_void_p), int(x.size),
+                                     out.ctypes.data_as(C.c_void_p), _stream()))
+        return out
 
     def param_grad(self, z):
         out = np.zeros(3)

@@ -70,6 +70,7 @@ _SIGS = {
     "pff_newton_step": (C.c_int, [VP, VP, VP, VP, VP, C.POINTER(NewtonInfo), VP]),
     "pff_residual": (C.c_int, [VP, VP, VP, C.c_int32, VP]),
     "pff_tcv": (C.c_int, [VP, VP, C.POINTER(C.c_double), VP, VP]),
+    "pff_cod": (C.c_int, [VP, VP, VP, C.c_int32, VP, VP]),
     "pff_param_grad": (C.c_int, [VP, VP, VP, VP]),
     "pff_adjoint_tcv": (C.c_int, [VP, VP, C.POINTER(C.c_double), VP, VP, C.c_double, C.POINTER(GmresInfo), VP]),
     "pff_distribute": (C.c_int, [VP, VP, C.c_int32, VP]),

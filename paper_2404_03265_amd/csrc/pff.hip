@@ -20,6 +20,7 @@
 #include "tile_batch.hpp"
 #include "util_kernels.hpp"
 #include "coarse_kernel.hpp"
+#include "cod_kernel.hpp"
 
 using namespace pff;
 
@@ -296,6 +297,7 @@ struct pff_ctx {
   void* part = nullptr;         // partial sums of shared nodes (largest tile set)
   size_t part_bytes = 0;
   double* part_jt = nullptr;    // leaf partial sums of JT_BATCH_MAX right-hand sides (vmult_T)
+  int32_t* nodeX = nullptr;     // lattice x coordinate of every leaf node (COD lines)
   void* scratch_dev = nullptr;  // device address of `scratch` on this context's GPU
   int V_cap = 0;
   // caller-bound workspace (pff_bind_workspace): the work vectors, level
@@ -1325,7 +1327,7 @@ int pff_default_params(pff_params* p) {
   p->cheb_degree = 3;
   p->smooth_range = 0.08;
   p->upper_factor = 1.2;
-  p->eig_cg_its = 10;
+  p->eig_cg_its = 20;
   p->coarse_mode = 0;
   p->coarse_its = 30;
   p->coarse_eig_its = 40;
@@ -1387,6 +1389,7 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
     const int64_t n = c->n;
     c->tiles = upload_tiles(c->mesh.tiles);
     c->flags = upload(c->mesh.flags);
+    c->nodeX = upload(c->mesh.NX);
     c->hang = upload(c->mesh.hanging);
     c->n_hang = int(c->mesh.hanging.size());
     c->lv.resize(c->mesh.levels.size());
@@ -1477,6 +1480,7 @@ int pff_destroy(pff_ctx* c) {
   };
   ft(c->tiles);
   f(c->flags);
+  f(c->nodeX);
   f(c->hang);
   std::vector<DevLevel*> all;
   for (DevLevel& D : c->lv) all.push_back(&D);
@@ -1915,6 +1919,55 @@ int pff_param_grad(pff_ctx* c, const double* z, double* out, void* stream) {
   out[1] = c->dot(zm, v, N);
   c->leaf_op<MODE_DP>(v, c->U, st);
   out[2] = c->dot(zm, v, N);
+  return PFF_OK;
+  GUARD_END(c)
+}
+
+int pff_cod(pff_ctx* c, const double* U, const double* x, int32_t nx, double* cod, void* stream) {
+  if (!c || !U || nx < 0 || (nx > 0 && (!x || !cod))) return PFF_E_ARG;
+  GUARD_BEGIN
+  c->s = static_cast<hipStream_t>(stream);
+  c->ensure_work();
+  const DevTiles& t = c->tiles;
+  TileArgs<double> a{};
+  c->tile_args(t, c->flags, c->n, a, c->part);
+  // lines per launch: at most COD_MAX_LINES and what the partial-sum buffer
+  // holds for one partial per tile and line
+  const int64_t cap = int64_t(c->part_bytes / sizeof(double)) / std::max(1, t.n_tiles);
+  const int chunk = int(std::min<int64_t>(COD_MAX_LINES, cap));
+  if (chunk < 1) throw std::runtime_error("cod: partial-sum buffer too small");
+  for (int j0 = 0; j0 < nx; j0 += chunk) {
+    CodLines L{};
+    L.n = std::min(chunk, nx - j0);
+    for (int j = 0; j < L.n; ++j) {
+      const double xv = x[j0 + j];
+      if (!std::isfinite(xv)) {
+        c->err = "cod: a line position is not finite";
+        return PFF_E_ARG;
+      }
+      L.X[j] = (xv + 10.0) * double(c->mesh.M) / 20.0;   // physical -> lattice
+    }
+    double* part = static_cast<double*>(c->part);
+    auto launch = [&](auto kfn) {
+      if (t.n_tiles > 0) hipLaunchKernelGGL(kfn, dim3(t.n_tiles), dim3(RED_THREADS), 0, c->s, a, c->nodeX, U, L, part);
+    };
+    const bool q1 = c->p == 1;
+    if (L.n <= 8) launch(q1 ? k_cod_partial<1, 8> : k_cod_partial<2, 8>);
+    else if (L.n <= 16) launch(q1 ? k_cod_partial<1, 16> : k_cod_partial<2, 16>);
+    else if (L.n <= 32) launch(q1 ? k_cod_partial<1, 32> : k_cod_partial<2, 32>);
+    else launch(q1 ? k_cod_partial<1, 64> : k_cod_partial<2, 64>);
+    HIPCHK(hipGetLastError());
+    if (t.n_tiles == 0) {
+      for (int j = 0; j < L.n; ++j) cod[j0 + j] = 0.0;
+      continue;
+    }
+    // per-line sums of the per-tile partials, in tile order
+    hipLaunchKernelGGL(k_reduce_final, dim3(L.n), dim3(RED_THREADS), 0, c->s, (const double*)part, t.n_tiles, L.n,
+                       c->red_out);
+    HIPCHK(hipMemcpyAsync(c->host_red, c->red_out, sizeof(double) * L.n, hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    for (int j = 0; j < L.n; ++j) cod[j0 + j] = c->host_red[j];
+  }
   return PFF_OK;
   GUARD_END(c)
 }
