@@ -394,7 +394,14 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"leaf vmult = tile_kernel<{spec.degree}, double, MODE_J> + shared_fixup",
                      "algorithmic_bytes": algo, "vmult_us": ms_vmult * 1e3,
-                     "vmult_us_median": med_vmult * 1e3},
+                     "vmult_us_median": med_vmult * 1e3,
+                     # beside the required figures: the algorithmic fraction at the
+                     # median call time, and the measured HBM traffic (counters) as
+                     # a rate at the mean and median times
+                     "frac_at_median": algo / (med_vmult * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic_gbs": traffic / (ms_vmult * 1e-3) / 1e9 if traffic else None,
+                     "traffic_frac_at_median": (traffic / (med_vmult * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                                if traffic else None)},
     }
     out.update(extra)
     if args.scenario == "diff":
