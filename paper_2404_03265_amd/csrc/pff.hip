@@ -85,6 +85,15 @@ struct DevLevel {
   LevelWork<float> w32;
   double lam_max[2] = {1, 1}, lam_min[2] = {1, 1};
   bool shares_leaf = false;   // tiles and flags are the leaf operator's (not freed with the level)
+  // the level's own scratch for its eigenvalue estimate, so that the levels'
+  // estimates run concurrently: partial sums of the level operator's shared
+  // nodes, CG scalars, Lanczos coefficients, reduction partials
+  double* epart = nullptr;
+  size_t epart_bytes = 0;
+  double* esc = nullptr;
+  double* eal = nullptr;
+  double* ebe = nullptr;
+  double* ered = nullptr;
 };
 
 template <typename T>
@@ -274,6 +283,12 @@ struct pff_ctx {
   std::vector<DevLevel> gcown;
   std::vector<DevLevel*> H_ls, H_gc, H;
   bool has_gc = false;
+  // side streams (default priority) for the levels' concurrent eigenvalue
+  // estimates, forked from and joined into the caller's stream by events
+  static constexpr int EIG_STREAMS = 4;
+  hipStream_t es[EIG_STREAMS] = {};
+  hipEvent_t efork = nullptr;
+  hipEvent_t ejoin[EIG_STREAMS] = {};
   double* U = nullptr;
   double* phio = nullptr;
   double* phit = nullptr;
@@ -281,10 +296,6 @@ struct pff_ctx {
   double* wv[8] = {};
   double* red_part = nullptr;
   double* red_out = nullptr;
-  // eigenvalue-estimate CG: per-block scalars and Lanczos coefficients
-  double* eig_sc = nullptr;
-  double* eig_al = nullptr;
-  double* eig_be = nullptr;
   double* host_red = nullptr;   // pinned
   double* eig_host = nullptr;   // pinned: per level 2 EIG_SC + 4 EIG_MAX_ITS doubles of estimate output
   double* V = nullptr;          // GMRES basis
@@ -453,9 +464,10 @@ struct pff_ctx {
     return host_red[0];
   }
   template <typename T>
-  void dot2_async(const T* a, const T* b, int64_t len, double* out_dev) {
-    hipLaunchKernelGGL((k_dot_partial<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, a, b, len, red_part);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, red_part, RED_BLOCKS, 1, out_dev);
+  void dot2_async(const T* a, const T* b, int64_t len, double* out_dev, double* partials = nullptr) {
+    if (!partials) partials = red_part;
+    hipLaunchKernelGGL((k_dot_partial<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, a, b, len, partials);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, partials, RED_BLOCKS, 1, out_dev);
   }
   // the k <= 64 running sums of the orthogonalisation kernels are held in
   // registers: instantiate for the smallest bound that covers k
@@ -580,7 +592,7 @@ struct pff_ctx {
 
   template <typename T>
   void level_apply(int l, const T* x, T* dst, int epi, const T* b, const T* dold, T* xnew, const T c1[2],
-                   const T c2[2], const T* c0 = nullptr) {
+                   const T c2[2], const T* c0 = nullptr, void* part_buf = nullptr, size_t part_cap = 0) {
     DevLevel& L = lev(l);
     LevelWork<T>& w = work<T>(L);
     TileArgs<T> a{};
@@ -598,7 +610,7 @@ struct pff_ctx {
       a.c2[i] = c2 ? c2[i] : T(0);
       a.c0[i] = c0 ? c0[i] : T(0);
     }
-    if (epi == EPI_PLAIN) launch_tile<T, MODE_LEVEL, EPI_PLAIN>(L.tiles, L.flags, L.n, a);
+    if (epi == EPI_PLAIN) launch_tile<T, MODE_LEVEL, EPI_PLAIN>(L.tiles, L.flags, L.n, a, part_buf, part_cap);
     else if (epi == EPI_RESID) launch_tile<T, MODE_LEVEL, EPI_RESID>(L.tiles, L.flags, L.n, a);
     else if (epi == EPI_CHEB_FIRST) launch_tile<T, MODE_LEVEL, EPI_CHEB_FIRST>(L.tiles, L.flags, L.n, a);
     else launch_tile<T, MODE_LEVEL, EPI_CHEB>(L.tiles, L.flags, L.n, a);
@@ -956,10 +968,12 @@ struct pff_ctx {
     hipLaunchKernelGGL(k_free_ones, dim3(grid_for(3 * nl)), dim3(256), 0, s, r, w.dinv, 3 * nl);
     hipLaunchKernelGGL(k_mul, dim3(grid_for(3 * nl)), dim3(256), 0, s, z, w.dinv, r, 3 * nl);
     HIPCHK(hipMemcpyAsync(pv, z, sizeof(double) * 3 * nl, hipMemcpyDeviceToDevice, s));
-    double* sc = eig_sc;
+    // the level's own scratch (the levels' estimates run concurrently)
+    double* sc = L.esc;
+    double* rp = L.ered;
     for (int b = 0; b < 2; ++b) {
-      dot2_async(r + off[b], r + off[b], len[b], sc + EIG_SC * b + EIG_PQ);   // n_free (scratch slot)
-      dot2_async(r + off[b], z + off[b], len[b], sc + EIG_SC * b + EIG_RZ);
+      dot2_async(r + off[b], r + off[b], len[b], sc + EIG_SC * b + EIG_PQ, rp);   // n_free (scratch slot)
+      dot2_async(r + off[b], z + off[b], len[b], sc + EIG_SC * b + EIG_RZ, rp);
     }
     hipLaunchKernelGGL(k_eig_init, dim3(1), dim3(64), 0, s, sc, its);
     const int stride = EIG_MAX_ITS;
@@ -968,17 +982,17 @@ struct pff_ctx {
     // partials, beta, direction update (both blocks in every launch)
     const int nb = std::min(RED_BLOCKS, grid_for(3 * nl));
     for (int it = 0; it < max_it; ++it) {
-      level_apply<double>(l, pv, q, EPI_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr);
-      hipLaunchKernelGGL(k_eig_pq_partial, dim3(nb), dim3(RED_THREADS), 0, s, pv, q, nl, red_part);
-      hipLaunchKernelGGL(k_eig_alpha_reduce, dim3(1), dim3(RED_THREADS), 0, s, red_part, nb, sc, eig_al, stride, it);
-      hipLaunchKernelGGL(k_eig_update_partial, dim3(nb), dim3(RED_THREADS), 0, s, r, z, q, w.dinv, sc, nl,
-                         red_part);
-      hipLaunchKernelGGL(k_eig_beta_reduce, dim3(1), dim3(RED_THREADS), 0, s, red_part, nb, sc, eig_be, stride, it);
+      level_apply<double>(l, pv, q, EPI_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, L.epart,
+                          L.epart_bytes);
+      hipLaunchKernelGGL(k_eig_pq_partial, dim3(nb), dim3(RED_THREADS), 0, s, pv, q, nl, rp);
+      hipLaunchKernelGGL(k_eig_alpha_reduce, dim3(1), dim3(RED_THREADS), 0, s, rp, nb, sc, L.eal, stride, it);
+      hipLaunchKernelGGL(k_eig_update_partial, dim3(nb), dim3(RED_THREADS), 0, s, r, z, q, w.dinv, sc, nl, rp);
+      hipLaunchKernelGGL(k_eig_beta_reduce, dim3(1), dim3(RED_THREADS), 0, s, rp, nb, sc, L.ebe, stride, it);
       hipLaunchKernelGGL(k_eig_waxpy, dim3(grid_for(3 * nl)), dim3(256), 0, s, pv, z, sc, nl);
     }
     HIPCHK(hipMemcpyAsync(out, sc, sizeof(double) * 2 * EIG_SC, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(out + 2 * EIG_SC, eig_al, sizeof(double) * 2 * stride, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(out + 2 * EIG_SC + 2 * stride, eig_be, sizeof(double) * 2 * stride,
+    HIPCHK(hipMemcpyAsync(out + 2 * EIG_SC, L.eal, sizeof(double) * 2 * stride, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(out + 2 * EIG_SC + 2 * stride, L.ebe, sizeof(double) * 2 * stride,
                           hipMemcpyDeviceToHost, s));
   }
   void eig_finish(int l, const double* in) {
@@ -1002,13 +1016,32 @@ struct pff_ctx {
       L.lam_min[b] = lo;
     }
   }
-  // every level's estimate with one host wait
+  // every level's estimate with one host wait. The levels are independent
+  // (own vectors and scratch): they run on the side streams, largest level
+  // first and round-robin, forked from and joined into the caller's stream;
+  // each level's arithmetic is the same on any stream.
   void eig_estimate_all() {
     const size_t per = size_t(2 * EIG_SC + 4 * EIG_MAX_ITS);
-    for (int l = 0; l < nlev(); ++l)
+    const int nl = nlev();
+    std::vector<int> order(static_cast<size_t>(nl));
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lev(a).n > lev(b).n; });
+    hipStream_t main = s;
+    HIPCHK(hipEventRecord(efork, main));
+    for (int k = 0; k < EIG_STREAMS; ++k) HIPCHK(hipStreamWaitEvent(es[k], efork, 0));
+    for (int i = 0; i < nl; ++i) {
+      const int l = order[size_t(i)];
+      s = es[i % EIG_STREAMS];
       eig_launch(l, l == 0 ? prm.coarse_eig_its : prm.eig_cg_its, eig_host + per * size_t(l));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int l = 0; l < nlev(); ++l) eig_finish(l, eig_host + per * size_t(l));
+    }
+    s = main;
+    for (int k = 0; k < EIG_STREAMS; ++k) {
+      HIPCHK(hipEventRecord(ejoin[k], es[k]));
+      HIPCHK(hipStreamWaitEvent(main, ejoin[k], 0));
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(main));
+    for (int l = 0; l < nl; ++l) eig_finish(l, eig_host + per * size_t(l));
   }
 
   // Smallest and largest eigenvalue of a symmetric tridiagonal matrix by
@@ -1450,11 +1483,26 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
     for (const Level& L : c->mesh.levels) slots = std::max(slots, L.tiles.n_slots);
     for (const GcLevel& G : c->mesh.gc) slots = std::max(slots, G.tiles.n_slots);
     c->part_bytes = size_t(3 * std::max<int64_t>(slots, 1)) * sizeof(double);
+    {
+      // per-level scratch of the concurrent eigenvalue estimates
+      std::vector<DevLevel*> all;
+      for (DevLevel& D : c->lv) all.push_back(&D);
+      for (DevLevel& D : c->gcown) all.push_back(&D);
+      for (DevLevel* D : all) {
+        D->epart_bytes = size_t(3 * std::max<int64_t>(D->tiles.n_slots, 1)) * sizeof(double);
+        D->epart = dalloc<double>(int64_t(D->epart_bytes / sizeof(double)));
+        D->esc = dalloc<double>(2 * EIG_SC);
+        D->eal = dalloc<double>(2 * EIG_MAX_ITS);
+        D->ebe = dalloc<double>(2 * EIG_MAX_ITS);
+        D->ered = dalloc<double>(2 * RED_BLOCKS);
+      }
+      for (int k = 0; k < pff_ctx::EIG_STREAMS; ++k) HIPCHK(hipStreamCreateWithFlags(&c->es[k], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&c->efork, hipEventDisableTiming));
+      for (int k = 0; k < pff_ctx::EIG_STREAMS; ++k)
+        HIPCHK(hipEventCreateWithFlags(&c->ejoin[k], hipEventDisableTiming));
+    }
     c->red_part = dalloc<double>(RED_BLOCKS * 64);
     c->red_out = dalloc<double>(256);
-    c->eig_sc = dalloc<double>(2 * EIG_SC);
-    c->eig_al = dalloc<double>(2 * EIG_MAX_ITS);
-    c->eig_be = dalloc<double>(2 * EIG_MAX_ITS);
     c->ccg_s = dalloc<double>(8);
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->host_red), 256 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->eig_host),
@@ -1491,6 +1539,7 @@ int pff_destroy(pff_ctx* c) {
       ft(D.tiles);
       f(D.flags);
     }
+    f(D.epart); f(D.esc); f(D.eal); f(D.ebe); f(D.ered);
     f(D.leaf_index); f(D.PT_ptr); f(D.PT_col); f(D.P_ell); f(D.PT_ell); f(D.PT_rows); f(D.P_wtab);
     if (!c->ws) {   // a bound workspace belongs to the caller
       LevelWork<double>& a = D.w64;
@@ -1504,7 +1553,12 @@ int pff_destroy(pff_ctx* c) {
     for (int i = 0; i < 8; ++i) f(c->wv[i]);
     f(c->V); f(c->part); f(c->part_jt);
   }
-  f(c->red_part); f(c->red_out); f(c->ccg_s); f(c->coarse_nodes); f(c->eig_sc); f(c->eig_al); f(c->eig_be);
+  for (int k = 0; k < pff_ctx::EIG_STREAMS; ++k) {
+    if (c->es[k]) hipStreamDestroy(c->es[k]);
+    if (c->ejoin[k]) hipEventDestroy(c->ejoin[k]);
+  }
+  if (c->efork) hipEventDestroy(c->efork);
+  f(c->red_part); f(c->red_out); f(c->ccg_s); f(c->coarse_nodes); 
   if (c->host_red) hipHostFree(c->host_red);
   if (c->eig_host) hipHostFree(c->eig_host);
   delete c;
