@@ -200,7 +200,7 @@ def main():
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--no-load-step", action="store_true",
                     help="time the Newton steps only, not the whole load step (for profiler runs)")
-    ap.add_argument("--newton-modes", default="fp64,mixed,mixed_cheb3,gc_fp64,gc_mixed",
+    ap.add_argument("--newton-modes", default="fp64,mixed,mixed_cheb3,gc_fp64,gc_mixed,tri_fp64",
                     help="comma-separated subset of fp64,mixed,mixed_cheb3")
     ap.add_argument("--profile-pass", action="store_true",
                     help="only a few vmults and one plain device copy of the same vector "
@@ -274,11 +274,17 @@ def main():
         # and coarse solve, isolating the effect of the precision
         # gc_fp64 / gc_mixed: the same two configurations with the
         # global-coarsening hierarchy in place of local smoothing
-        modes = {"fp64": dict(vcycle_fp32=0, cheb_degree=3, coarse_mode=0, coarse_its=30, mg_kind=0),
-                 "mixed": dict(vcycle_fp32=1, cheb_degree=4, coarse_mode=1, coarse_its=30, mg_kind=0),
-                 "mixed_cheb3": dict(vcycle_fp32=1, cheb_degree=3, coarse_mode=0, coarse_its=30, mg_kind=0),
-                 "gc_fp64": dict(vcycle_fp32=0, cheb_degree=3, coarse_mode=0, coarse_its=30, mg_kind=1),
-                 "gc_mixed": dict(vcycle_fp32=1, cheb_degree=4, coarse_mode=1, coarse_its=30, mg_kind=1)}
+        modes = {"fp64": dict(vcycle_fp32=0, cheb_degree=3, coarse_mode=0, coarse_its=30, mg_kind=0, prec_kind=0),
+                 "mixed": dict(vcycle_fp32=1, cheb_degree=4, coarse_mode=1, coarse_its=30, mg_kind=0, prec_kind=0),
+                 "mixed_cheb3": dict(vcycle_fp32=1, cheb_degree=3, coarse_mode=0, coarse_its=30, mg_kind=0,
+                                     prec_kind=0),
+                 "gc_fp64": dict(vcycle_fp32=0, cheb_degree=3, coarse_mode=0, coarse_its=30, mg_kind=1,
+                                 prec_kind=0),
+                 "gc_mixed": dict(vcycle_fp32=1, cheb_degree=4, coarse_mode=1, coarse_its=30, mg_kind=1,
+                                  prec_kind=0),
+                 # the block-triangular preconditioner (keeps the coupling block)
+                 "tri_fp64": dict(vcycle_fp32=0, cheb_degree=3, coarse_mode=0, coarse_its=30, mg_kind=0,
+                                  prec_kind=1)}
         modes = {k: v for k, v in modes.items() if k in args.newton_modes.split(",")}
         U_ref = None
         tcv_ref = None

@@ -115,7 +115,13 @@ typedef struct {
  *  unknowns with its own hanging-node constraints; transfers interpolate the
  *  coarse finite-element function; a coarse phase-field unknown is active if
  *  any finer unknown its interpolation reaches is). 1 needs a context created
- *  with pff_mesh_spec.mg_global != 0, else PFF_E_ARG. */
+ *  with pff_mesh_spec.mg_global != 0, else PFF_E_ARG.
+ *  prec_kind: 0 (default): the block-diagonal preconditioner of Sec. 3.2 (one
+ *  V-cycle per diagonal block; the coupling block G_phi,u dropped). 1: block
+ *  triangular, keeping G_phi,u (the Jacobian is lower block triangular, since
+ *  the u-equation uses phi~): forward substitution x_u = M_u^-1 b_u,
+ *  x_phi = M_phi^-1 (b_phi - G_phi,u x_u), and for transposed solves the
+ *  backward form; two V-cycles and one operator application per use. */
 typedef struct {
   double E, nu, Gc, pressure, kappa, ell;
   int32_t cheb_degree;
@@ -131,6 +137,7 @@ typedef struct {
   int32_t vcycle_fp32;
   double pdas_c;
   int32_t mg_kind;
+  int32_t prec_kind;
 } pff_params;
 
 typedef struct {
@@ -278,9 +285,10 @@ int pff_inverse_diagonal(pff_ctx* ctx, int32_t level, void* dst, int32_t fp32, v
 /* dst = P^{-1} src: one V-cycle per diagonal block (Sec. 3.2) with local
  * smoothing (mg_kind 0) or global coarsening (mg_kind 1: smoothing on every
  * level over all its free unknowns, restriction the transpose of the
- * interpolation, leaf rows enter and leave on the finest level). src, dst: 3n
- * doubles (the V-cycle runs in FP32 inside when fp32 != 0). Identity on
- * constrained leaf rows. */
+ * interpolation, leaf rows enter and leave on the finest level); with
+ * prec_kind = 1 the block-triangular form (forward substitution, see
+ * pff_params). src, dst: 3n doubles (the V-cycle runs in FP32 inside when
+ * fp32 != 0). Identity on constrained leaf rows. */
 int pff_vcycle(pff_ctx* ctx, double* dst, const double* src, int32_t fp32, void* stream);
 /* Eigenvalue estimates per level and block (host arrays): lam_max[2 * l + b]
  * for level l and block b (0 = u, 1 = phi), lam_min0[b] on level 0. get

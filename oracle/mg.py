@@ -412,3 +412,31 @@ class VCycle:
                     lv = h.levels[int(h.copy_level[g])]
                     out[c * n + g] = x[int(h.copy_level[g])][c * lv.n + h.copy_index[g]]
         return out
+
+
+def block_triangular_apply(block_solve, J, b, n, transpose=False):
+    """Block-triangular preconditioner (the alternative to the block-diagonal
+    P of Sec. 3.2 that keeps the coupling block G_phi,u of the linearised
+    Jacobian, which is lower block triangular since the u-equation uses phi~,
+    Sec. 2 after Problem 1). block_solve(v) applies the diagonal blocks'
+    approximate inverses to both blocks of v at once (the V-cycle of either
+    hierarchy); J is the masked Jacobian. Forward substitution:
+        x_u   = M_uu^-1 b_u,
+        x_phi = M_phiphi^-1 (b_phi - G_phi,u x_u),
+    with G_phi,u x_u read off the phi rows of J (x_u, 0). transpose=True gives
+    the upper-triangular form for systems with J^T: x_phi first, then x_u with
+    b_u - G_phi,u^T x_phi from the u rows of J^T (0, x_phi). Constrained rows
+    pass through as in block_solve."""
+    b = np.asarray(b, dtype=float)
+    first = np.zeros_like(b)
+    if not transpose:
+        first[:2 * n] = b[:2 * n]
+        y1 = block_solve(first)
+        r = np.zeros_like(b)
+        r[2 * n:] = b[2 * n:] - (J @ y1)[2 * n:]
+    else:
+        first[2 * n:] = b[2 * n:]
+        y1 = block_solve(first)
+        r = np.zeros_like(b)
+        r[:2 * n] = b[:2 * n] - (J.T @ y1)[:2 * n]
+    return y1 + block_solve(r)

@@ -50,6 +50,7 @@ class SolverParams:
     vcycle_fp32: int = 0
     pdas_c: float = 0.0
     mg_kind: int = 0   # 0: local smoothing, 1: global coarsening (needs mg_global=True)
+    prec_kind: int = 0  # 0: block diagonal, 1: block triangular (keeps the coupling block)
 
     def to_c(self):
         p = _lib.Params()

@@ -23,7 +23,8 @@ class Params(C.Structure):
                 ("coarse_eig_its", C.c_int32), ("gmres_restart", C.c_int32),
                 ("gmres_max_its", C.c_int32), ("gmres_rtol", C.c_double),
                 ("gmres_atol", C.c_double), ("ls_omega", C.c_double), ("ls_max", C.c_int32),
-                ("vcycle_fp32", C.c_int32), ("pdas_c", C.c_double), ("mg_kind", C.c_int32)]
+                ("vcycle_fp32", C.c_int32), ("pdas_c", C.c_double), ("mg_kind", C.c_int32),
+                ("prec_kind", C.c_int32)]
 
 
 class GmresInfo(C.Structure):

@@ -293,7 +293,8 @@ struct pff_ctx {
   double* phio = nullptr;
   double* phit = nullptr;
   double* mass = nullptr;
-  double* wv[8] = {};
+  static constexpr int N_WORK = 10;   // leaf work vectors
+  double* wv[N_WORK] = {};
   double* red_part = nullptr;
   double* red_out = nullptr;
   double* host_red = nullptr;   // pinned
@@ -526,7 +527,7 @@ struct pff_ctx {
     take(carve ? phio : dummy, n);
     take(carve ? phit : dummy, n);
     take(carve ? mass : dummy, N);
-    for (int i = 0; i < 8; ++i) take(carve ? wv[i] : dummy, N);
+    for (int i = 0; i < N_WORK; ++i) take(carve ? wv[i] : dummy, N);
     double* pp = nullptr;
     take(pp, int64_t(part_bytes / sizeof(double)));
     if (carve) part = pp;
@@ -564,7 +565,7 @@ struct pff_ctx {
       phio = dalloc<double>(n);
       phit = dalloc<double>(n);
       mass = dalloc<double>(3 * n);
-      for (int i = 0; i < 8; ++i) wv[i] = dalloc<double>(3 * n);
+      for (int i = 0; i < N_WORK; ++i) wv[i] = dalloc<double>(3 * n);
       part = dalloc<double>(int64_t(part_bytes / sizeof(double)));
       part_jt = dalloc<double>(int64_t(JT_BATCH_MAX) * 3 * tiles.n_slots);
     }
@@ -1149,7 +1150,28 @@ struct pff_ctx {
     if (transpose) leaf_op<MODE_JT>(dst, src, st);
     else leaf_op<MODE_J>(dst, src, st);
   }
-  void apply_Minv(double* dst, const double* src, bool fp32) {
+  // P^-1 src: the block-diagonal V-cycle (Sec. 3.2), or with prec_kind = 1
+  // the block-triangular form that keeps the coupling block: forward
+  // substitution x_u = M_u^-1 b_u, x_phi = M_phi^-1 (b_phi - G_phi,u x_u)
+  // (G_phi,u x_u from the phi rows of J~ (x_u, 0)); for systems with J~^T the
+  // backward form, phi block first. Work vectors wv[8], wv[9].
+  void apply_Minv(double* dst, const double* src, bool fp32, bool transpose = false) {
+    if (prm.prec_kind != 1) {
+      apply_block(dst, src, fp32);
+      return;
+    }
+    double* t1 = wv[8];
+    double* t2 = wv[9];
+    const int first = transpose ? 1 : 0;
+    hipLaunchKernelGGL(k_block_select, dim3(grid_for(3 * n)), dim3(256), 0, s, t1, src, n, first);
+    apply_block(dst, t1, fp32);
+    apply_A(t1, dst, transpose);
+    hipLaunchKernelGGL(k_block_rhs, dim3(grid_for(3 * n)), dim3(256), 0, s, t1, src, n, 1 - first);
+    apply_block(t2, t1, fp32);
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(3 * n)), dim3(256), 0, s, dst, t2, 1.0, 3 * n);
+    HIPCHK(hipGetLastError());
+  }
+  void apply_block(double* dst, const double* src, bool fp32) {
     const bool gc = H == H_gc && has_gc;
     if (fp32) {
       if (!fp32_ready) setup_fp32();
@@ -1188,7 +1210,7 @@ struct pff_ctx {
     double* w = wv[0];
     double* t = wv[1];
     HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
-    apply_Minv(V, b, fp32);
+    apply_Minv(V, b, fp32, transpose);
     double beta = norm(V, N);
     if (!std::isfinite(beta)) throw nonfinite_error("GMRES: |P^-1 b| is not finite");
     pff_gmres_info inf{};
@@ -1218,7 +1240,7 @@ struct pff_ctx {
         double* qj = V + int64_t(j) * N;
         double* qn = V + int64_t(j + 1) * N;
         apply_A(t, qj, transpose);
-        apply_Minv(w, t, fp32);
+        apply_Minv(w, t, fp32, transpose);
         const double rho = std::sqrt(nq2 - sumsq(cq));
         // sweep 1: a_i = v_i . w (i < j), a_j = q_j . w
         launch_k<MdotL>(j + 1, (const double*)V, (const double*)w, j + 1, N, red_part);
@@ -1302,7 +1324,7 @@ struct pff_ctx {
       // restart: V_0 = Minv (b - A x)
       apply_A(t, x, transpose);
       hipLaunchKernelGGL(k_sub, dim3(grid_for(N)), dim3(256), 0, s, w, b, t, N);
-      apply_Minv(V, w, fp32);
+      apply_Minv(V, w, fp32, transpose);
       beta = norm(V, N);
       if (!std::isfinite(beta)) throw nonfinite_error("GMRES: restart residual is not finite");
       inf.final_residual = beta;
@@ -1343,7 +1365,7 @@ static bool params_valid(const pff_params& p) {
          p.gmres_max_its >= 1 && p.ls_max >= 1 && p.ls_omega > 0.0 && p.ls_omega <= 1.0 &&
          p.coarse_mode >= 0 && p.coarse_mode <= 1 && p.eig_cg_its >= 1 && p.eig_cg_its <= EIG_MAX_ITS &&
          p.coarse_eig_its >= 1 && p.coarse_eig_its <= EIG_MAX_ITS && std::isfinite(p.pdas_c) && p.pdas_c >= 0.0 &&
-         p.mg_kind >= 0 && p.mg_kind <= 1;
+         p.mg_kind >= 0 && p.mg_kind <= 1 && p.prec_kind >= 0 && p.prec_kind <= 1;
 }
 
 extern "C" {
@@ -1550,7 +1572,7 @@ int pff_destroy(pff_ctx* c) {
   }
   if (!c->ws) {
     f(c->U); f(c->phio); f(c->phit); f(c->mass);
-    for (int i = 0; i < 8; ++i) f(c->wv[i]);
+    for (int i = 0; i < pff_ctx::N_WORK; ++i) f(c->wv[i]);
     f(c->V); f(c->part); f(c->part_jt);
   }
   for (int k = 0; k < pff_ctx::EIG_STREAMS; ++k) {

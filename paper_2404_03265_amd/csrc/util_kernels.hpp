@@ -382,6 +382,16 @@ __global__ void k_cast(TO* o, const TI* in, int64_t len) {
   GRID_LOOP(i, len) o[i] = TO(in[i]);
 }
 
+// Block-triangular preconditioner: out = the rows of one block of in (u
+// rows for phi_block = 0, phi rows for 1), zero elsewhere; and t = b - t on
+// the rows of one block, zero elsewhere
+__global__ void k_block_select(double* out, const double* in, int64_t n, int phi_block) {
+  GRID_LOOP(i, 3 * n) out[i] = ((i >= 2 * n) == (phi_block != 0)) ? in[i] : 0.0;
+}
+__global__ void k_block_rhs(double* t, const double* b, int64_t n, int phi_block) {
+  GRID_LOOP(i, 3 * n) t[i] = ((i >= 2 * n) == (phi_block != 0)) ? b[i] - t[i] : 0.0;
+}
+
 // y = a x + y
 __global__ void k_axpy(double* y, const double* x, double a, int64_t len) {
   GRID_LOOP(i, len) y[i] += a * x[i];

@@ -818,3 +818,35 @@ def test_row_sampled_operators_equal_full_assembly(p, tiny_mesh_factory):
     assert np.abs(lp.masked_rows(rows, src, U, phit, act, transpose=True) - JT[rows]).max() <= 1e-13 * np.abs(JT).max()
     R = lp.residual(U, phit)
     assert np.abs(lp.residual_rows(rows, U, phit) - R[rows]).max() <= 1e-13 * np.abs(R).max()
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_block_triangular_with_exact_blocks_inverts_the_jacobian(p, tiny_mesh_factory):
+    """The Jacobian is lower block triangular (the u-equation uses phi~), so
+    forward substitution with exact diagonal-block solves is its exact
+    inverse, and backward substitution that of its transpose; the
+    block-diagonal form is not (the coupling block is dropped)."""
+    import scipy.sparse.linalg as spla
+    from oracle.mg import block_triangular_apply
+    mesh = tiny_mesh_factory(p)
+    n = mesh.n_nodes
+    X = -10 + 20 * mesh.NX / mesh.M
+    Y = -10 + 20 * mesh.NY / mesh.M
+    prm = Params(pressure=1e-2, kappa=1e-3, ell=0.5)
+    lp = LeafProblem(mesh, prm)
+    ux, uy, ph = inputs.sneddon_state(mesh.NX, mesh.NY, mesh.M, p, seed=3, u_std=1e-2)
+    U = lp.distribute(np.concatenate([ux, uy, ph]))
+    phit = lp.distribute(0.9 * ph + 0.05)
+    act = inputs.bernoulli_mask(mesh.NX, mesh.NY, 2, 0.1) & ~mesh.hanging
+    J = lp.masked_operator(U, phit, act).tocsc()
+    Jd = lp.masked_operator(U, phit, act, blocks="diag").tocsc()
+    assert abs(J[2 * n:, :2 * n]).max() > 1e-6          # a genuine coupling block
+    assert abs(J[:2 * n, 2 * n:]).max() == 0.0           # none above the diagonal
+    lu = spla.splu(Jd)
+    v = inputs.random_vector(mesh.NX, mesh.NY, 7)
+    x = block_triangular_apply(lu.solve, J, J @ v, n)
+    assert np.abs(x - v).max() <= 1e-9 * np.abs(v).max()
+    xt = block_triangular_apply(lambda w: lu.solve(w, trans="T"), J, J.T @ v, n, transpose=True)
+    assert np.abs(xt - v).max() <= 1e-9 * np.abs(v).max()
+    xd = lu.solve(J @ v)
+    assert np.abs(xd - v).max() > 1e-6 * np.abs(v).max()
