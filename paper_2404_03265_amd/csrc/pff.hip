@@ -283,6 +283,9 @@ struct pff_ctx {
   std::vector<DevLevel> gcown;
   std::vector<DevLevel*> H_ls, H_gc, H;
   bool has_gc = false;
+  // the displacement block's eigenvalue estimates belong to the current phi~,
+  // hierarchy and parameters (cleared when any of them changes)
+  bool ucache = false;
   // side streams (default priority) for the levels' concurrent eigenvalue
   // estimates, forked from and joined into the caller's stream by events
   static constexpr int EIG_STREAMS = 4;
@@ -956,7 +959,10 @@ struct pff_ctx {
   // scalars and Lanczos coefficients are copied to the pinned area `out`
   // (2 EIG_SC + 4 EIG_MAX_ITS doubles). eig_finish turns them into the
   // extreme Ritz values once the stream has been synchronised.
-  void eig_launch(int l, int its, double* out) {
+  // skip_u: the displacement block keeps its estimate and the vector passes
+  // cover the phase-field rows only (the level operator is block diagonal,
+  // so the phase-field rows of q do not depend on the other rows of p)
+  void eig_launch(int l, int its, double* out, bool skip_u = false) {
     DevLevel& L = lev(l);
     LevelWork<double>& w = w64of(L);
     const int64_t nl = L.n;
@@ -965,44 +971,47 @@ struct pff_ctx {
     double* pv = w.dir[0];
     double* q = w.dir[1];
     const int64_t off[2] = {0, 2 * nl}, len[2] = {2 * nl, nl};
+    const int64_t begin = skip_u ? 2 * nl : 0, span = 3 * nl - begin;
     // r = 1 on free unknowns (dinv != 0 exactly there), z = D^-1 r, p = z
-    hipLaunchKernelGGL(k_free_ones, dim3(grid_for(3 * nl)), dim3(256), 0, s, r, w.dinv, 3 * nl);
-    hipLaunchKernelGGL(k_mul, dim3(grid_for(3 * nl)), dim3(256), 0, s, z, w.dinv, r, 3 * nl);
-    HIPCHK(hipMemcpyAsync(pv, z, sizeof(double) * 3 * nl, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_free_ones, dim3(grid_for(span)), dim3(256), 0, s, r + begin, w.dinv + begin, span);
+    hipLaunchKernelGGL(k_mul, dim3(grid_for(span)), dim3(256), 0, s, z + begin, w.dinv + begin, r + begin, span);
+    HIPCHK(hipMemcpyAsync(pv + begin, z + begin, sizeof(double) * span, hipMemcpyDeviceToDevice, s));
     // the level's own scratch (the levels' estimates run concurrently)
     double* sc = L.esc;
     double* rp = L.ered;
-    for (int b = 0; b < 2; ++b) {
+    for (int b = skip_u ? 1 : 0; b < 2; ++b) {
       dot2_async(r + off[b], r + off[b], len[b], sc + EIG_SC * b + EIG_PQ, rp);   // n_free (scratch slot)
       dot2_async(r + off[b], z + off[b], len[b], sc + EIG_SC * b + EIG_RZ, rp);
     }
-    hipLaunchKernelGGL(k_eig_init, dim3(1), dim3(64), 0, s, sc, its);
+    hipLaunchKernelGGL(k_eig_init, dim3(1), dim3(64), 0, s, sc, its, skip_u ? 1 : 0);
     const int stride = EIG_MAX_ITS;
     const int max_it = std::min(its, stride);
     // per step: operator, p.q partials, alpha, update fused with the r.z
     // partials, beta, direction update (both blocks in every launch)
-    const int nb = std::min(RED_BLOCKS, grid_for(3 * nl));
+    // the same partition of the rows with and without the displacement block
+    const int nb = std::min(RED_BLOCKS, grid_for(2 * nl));
     for (int it = 0; it < max_it; ++it) {
       level_apply<double>(l, pv, q, EPI_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, L.epart,
                           L.epart_bytes);
-      hipLaunchKernelGGL(k_eig_pq_partial, dim3(nb), dim3(RED_THREADS), 0, s, pv, q, nl, rp);
+      hipLaunchKernelGGL(k_eig_pq_partial, dim3(nb), dim3(RED_THREADS), 0, s, pv, q, nl, begin, rp);
       hipLaunchKernelGGL(k_eig_alpha_reduce, dim3(1), dim3(RED_THREADS), 0, s, rp, nb, sc, L.eal, stride, it);
-      hipLaunchKernelGGL(k_eig_update_partial, dim3(nb), dim3(RED_THREADS), 0, s, r, z, q, w.dinv, sc, nl, rp);
+      hipLaunchKernelGGL(k_eig_update_partial, dim3(nb), dim3(RED_THREADS), 0, s, r, z, q, w.dinv, sc, nl, begin,
+                         rp);
       hipLaunchKernelGGL(k_eig_beta_reduce, dim3(1), dim3(RED_THREADS), 0, s, rp, nb, sc, L.ebe, stride, it);
-      hipLaunchKernelGGL(k_eig_waxpy, dim3(grid_for(3 * nl)), dim3(256), 0, s, pv, z, sc, nl);
+      hipLaunchKernelGGL(k_eig_waxpy, dim3(grid_for(span)), dim3(256), 0, s, pv, z, sc, nl, begin);
     }
     HIPCHK(hipMemcpyAsync(out, sc, sizeof(double) * 2 * EIG_SC, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(out + 2 * EIG_SC, L.eal, sizeof(double) * 2 * stride, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(out + 2 * EIG_SC + 2 * stride, L.ebe, sizeof(double) * 2 * stride,
                           hipMemcpyDeviceToHost, s));
   }
-  void eig_finish(int l, const double* in) {
+  void eig_finish(int l, const double* in, bool skip_u = false) {
     DevLevel& L = lev(l);
     const int stride = EIG_MAX_ITS;
     const double* h = in;
     const double* al = in + 2 * EIG_SC;
     const double* be = in + 2 * EIG_SC + 2 * stride;
-    for (int b = 0; b < 2; ++b) {
+    for (int b = skip_u ? 1 : 0; b < 2; ++b) {
       const int m = int(h[EIG_SC * b + EIG_STEPS]);
       double lo = 1.0, hi = 1.0;
       if (m > 0) {
@@ -1021,7 +1030,7 @@ struct pff_ctx {
   // (own vectors and scratch): they run on the side streams, largest level
   // first and round-robin, forked from and joined into the caller's stream;
   // each level's arithmetic is the same on any stream.
-  void eig_estimate_all() {
+  void eig_estimate_all(bool skip_u = false) {
     const size_t per = size_t(2 * EIG_SC + 4 * EIG_MAX_ITS);
     const int nl = nlev();
     std::vector<int> order(static_cast<size_t>(nl));
@@ -1033,7 +1042,7 @@ struct pff_ctx {
     for (int i = 0; i < nl; ++i) {
       const int l = order[size_t(i)];
       s = es[i % EIG_STREAMS];
-      eig_launch(l, l == 0 ? prm.coarse_eig_its : prm.eig_cg_its, eig_host + per * size_t(l));
+      eig_launch(l, l == 0 ? prm.coarse_eig_its : prm.eig_cg_its, eig_host + per * size_t(l), skip_u);
     }
     s = main;
     for (int k = 0; k < EIG_STREAMS; ++k) {
@@ -1042,7 +1051,7 @@ struct pff_ctx {
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(main));
-    for (int l = 0; l < nl; ++l) eig_finish(l, eig_host + per * size_t(l));
+    for (int l = 0; l < nl; ++l) eig_finish(l, eig_host + per * size_t(l), skip_u);
   }
 
   // Smallest and largest eigenvalue of a symmetric tridiagonal matrix by
@@ -1127,8 +1136,14 @@ struct pff_ctx {
     if (H == H_gc && has_gc) gc_level_active_sets();
     else level_active_sets();
     setup_levels<double>();
-    if (!eig_fixed)
-      eig_estimate_all();
+    if (!eig_fixed) {
+      // the displacement block's level operators depend on phi~ alone (the
+      // degradation g(phi~) times elasticity, Dirichlet and edge rows fixed):
+      // while phi~ is unchanged their diagonals and estimates repeat bit for
+      // bit, so only the phase-field block is estimated again
+      eig_estimate_all(ucache);
+      ucache = true;
+    }
     if (prm.vcycle_fp32) setup_fp32();
     mg_ready = true;
   }
@@ -1601,6 +1616,7 @@ int pff_set_params(pff_ctx* c, const pff_params* p) {
   c->prm = *p;
   c->mg_ready = false;
   c->fp32_ready = false;
+  c->ucache = false;
   c->select_hierarchy();
   return PFF_OK;
 }
@@ -1689,6 +1705,9 @@ int pff_set_state(pff_ctx* c, const double* U, const double* phi_old, const doub
   const int64_t n = c->n;
   HIPCHK(hipMemcpyAsync(c->U, U, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, c->s));
   HIPCHK(hipMemcpyAsync(c->phio, phi_old, sizeof(double) * n, hipMemcpyDeviceToDevice, c->s));
+  // keep the previous phi~ to tell whether it changed (wv[9] is free here)
+  const bool compare = c->has_state && c->ucache;
+  if (compare) HIPCHK(hipMemcpyAsync(c->wv[9], c->phit, sizeof(double) * n, hipMemcpyDeviceToDevice, c->s));
   HIPCHK(hipMemcpyAsync(c->phit, phi_tilde, sizeof(double) * n, hipMemcpyDeviceToDevice, c->s));
   if (c->n_hang) {
     const int np1 = c->p + 1;
@@ -1698,6 +1717,17 @@ int pff_set_state(pff_ctx* c, const double* U, const double* phi_old, const doub
                        c->n_hang, np1);
     hipLaunchKernelGGL((k_distribute<double>), dim3(grid_for(c->n_hang)), dim3(256), 0, c->s, c->phio, n, 1, c->hang,
                        c->n_hang, np1);
+  }
+  if (compare) {
+    hipLaunchKernelGGL(k_neq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->s, c->wv[9], c->phit, n,
+                       c->red_part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, c->s, c->red_part, RED_BLOCKS, 1,
+                       c->red_out + 210);
+    HIPCHK(hipMemcpyAsync(c->host_red + 210, c->red_out + 210, sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    if (c->host_red[210] != 0.0) c->ucache = false;
+  } else {
+    c->ucache = false;
   }
   if (active) {
     hipLaunchKernelGGL(k_set_active, dim3(grid_for(n)), dim3(256), 0, c->s, c->flags, active, n);
@@ -1847,6 +1877,7 @@ int pff_get_eigen(const pff_ctx* c, double* lam_max, double* lam_min0) {
 
 int pff_set_eigen(pff_ctx* c, const double* lam_max, const double* lam_min0) {
   if (!c) return PFF_E_ARG;
+  c->ucache = false;
   if (!lam_max) { c->eig_fixed = false; return PFF_OK; }
   for (int l = 0; l < c->nlev(); ++l)
     for (int b = 0; b < 2; ++b) c->lev(l).lam_max[b] = lam_max[2 * l + b];

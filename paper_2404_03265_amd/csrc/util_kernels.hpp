@@ -392,6 +392,22 @@ __global__ void k_block_rhs(double* t, const double* b, int64_t n, int phi_block
   GRID_LOOP(i, 3 * n) t[i] = ((i >= 2 * n) == (phi_block != 0)) ? b[i] - t[i] : 0.0;
 }
 
+// partials of the number of entries where a and b differ (bit for bit)
+__global__ void __launch_bounds__(RED_THREADS) k_neq_partial(const double* a, const double* b, int64_t len,
+                                                              double* part) {
+  __shared__ double sh[RED_THREADS];
+  double s = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x)
+    s += (__double_as_longlong(a[i]) != __double_as_longlong(b[i])) ? 1.0 : 0.0;
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 // y = a x + y
 __global__ void k_axpy(double* y, const double* x, double a, int64_t len) {
   GRID_LOOP(i, len) y[i] += a * x[i];
@@ -445,10 +461,16 @@ enum { EIG_RZ = 0, EIG_PQ, EIG_RZ2, EIG_ALPHA, EIG_BETA, EIG_RZ0, EIG_ACTIVE, EI
 // number of free unknowns in the EIG_PQ slot, r.z in EIG_RZ): at most `its`
 // steps and never more than the free unknowns; a block without free unknowns
 // or with r.z = 0 takes no step
-__global__ void k_eig_init(double* sc, int its) {
+// skip_u: the displacement block takes no step (its estimate is kept)
+__global__ void k_eig_init(double* sc, int its, int skip_u) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int b = 0; b < 2; ++b) {
     double* c = sc + EIG_SC * b;
+    if (b == 0 && skip_u) {
+      c[EIG_ACTIVE] = 0.0;
+      c[EIG_STEPS] = 0.0;
+      continue;
+    }
     const double n_free = c[EIG_PQ];
     c[EIG_RZ0] = c[EIG_RZ];
     c[EIG_MAX] = fmin(double(its), n_free);
@@ -662,14 +684,23 @@ __device__ __forceinline__ void eig_reduce2(const double* part, int nb, double* 
 }
 
 // partials of p.q per block
+// Each block's rows run in a loop of their own with the thread index counted
+// from the block's first row (begin = 2 nl: the displacement block is
+// skipped), so the phase-field partial sums are the same with and without
+// the other block.
+template <class F>
+__device__ __forceinline__ void eig_block_loops(int64_t nl, int64_t begin, F&& body) {
+  const int64_t st = int64_t(gridDim.x) * blockDim.x;
+  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (begin == 0)
+    for (int64_t i = t0; i < 2 * nl; i += st) body(0, i);
+  for (int64_t i = 2 * nl + t0; i < 3 * nl; i += st) body(1, i);
+}
 __global__ void __launch_bounds__(RED_THREADS) k_eig_pq_partial(const double* p, const double* q, int64_t nl,
-                                                                  double* part) {
-  double s0 = 0.0, s1 = 0.0;
-  GRID_LOOP(i, 3 * nl) {
-    const double c = p[i] * q[i];
-    if (i < 2 * nl) s0 += c; else s1 += c;
-  }
-  eig_block_partials(s0, s1, part);
+                                                                  int64_t begin, double* part) {
+  double s[2] = {0.0, 0.0};
+  eig_block_loops(nl, begin, [&](int b, int64_t i) { s[b] += p[i] * q[i]; });
+  eig_block_partials(s[0], s[1], part);
 }
 // p.q per block, then alpha = r.z / p.q (a block with p.q <= 0 stops)
 __global__ void __launch_bounds__(RED_THREADS) k_eig_alpha_reduce(const double* part, int nb, double* sc, double* al,
@@ -691,12 +722,11 @@ __global__ void __launch_bounds__(RED_THREADS) k_eig_alpha_reduce(const double* 
 // r -= alpha q on free rows, z = D^-1 r (active blocks), partials of r.z
 __global__ void __launch_bounds__(RED_THREADS) k_eig_update_partial(double* r, double* z, const double* q,
                                                                       const double* dinv, const double* sc,
-                                                                      int64_t nl, double* part) {
+                                                                      int64_t nl, int64_t begin, double* part) {
   const bool act[2] = {sc[EIG_ACTIVE] != 0.0, sc[EIG_SC + EIG_ACTIVE] != 0.0};
   const double alpha[2] = {sc[EIG_ALPHA], sc[EIG_SC + EIG_ALPHA]};
-  double s0 = 0.0, s1 = 0.0;
-  GRID_LOOP(i, 3 * nl) {
-    const int b = i < 2 * nl ? 0 : 1;
+  double s[2] = {0.0, 0.0};
+  eig_block_loops(nl, begin, [&](int b, int64_t i) {
     double ri = r[i], zi = z[i];
     if (act[b]) {
       const double di = dinv[i];
@@ -705,10 +735,9 @@ __global__ void __launch_bounds__(RED_THREADS) k_eig_update_partial(double* r, d
       r[i] = ri;
       z[i] = zi;
     }
-    const double c = ri * zi;
-    if (b == 0) s0 += c; else s1 += c;
-  }
-  eig_block_partials(s0, s1, part);
+    s[b] += ri * zi;
+  });
+  eig_block_partials(s[0], s[1], part);
 }
 // r.z per block, beta = r.z_new / r.z; stop once r.z <= 1e-24 r.z_0 or after
 // the block's step count
@@ -728,10 +757,11 @@ __global__ void __launch_bounds__(RED_THREADS) k_eig_beta_reduce(const double* p
   if (rz2[b] <= 1e-24 * c[EIG_RZ0] || double(it + 1) >= c[EIG_MAX]) c[EIG_ACTIVE] = 0.0;
 }
 // p = z + beta p on active blocks
-__global__ void k_eig_waxpy(double* p, const double* z, const double* sc, int64_t nl) {
+__global__ void k_eig_waxpy(double* p, const double* z, const double* sc, int64_t nl, int64_t begin) {
   const bool act[2] = {sc[EIG_ACTIVE] != 0.0, sc[EIG_SC + EIG_ACTIVE] != 0.0};
   const double beta[2] = {sc[EIG_BETA], sc[EIG_SC + EIG_BETA]};
-  GRID_LOOP(i, 3 * nl) {
+  for (int64_t i = begin + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < 3 * nl;
+       i += int64_t(gridDim.x) * blockDim.x) {
     const int b = i < 2 * nl ? 0 : 1;
     if (act[b]) p[i] = z[i] + beta[b] * p[i];
   }

@@ -566,3 +566,32 @@ def test_gmres_restarts_match_oracle(p):
     _, oinfo = gmres(lambda v: J @ v, vc.apply, c.to_o(b), tol, restart=4, maxit=300)
     assert oinfo.converged
     assert abs(info["iterations"] - oinfo.iterations) <= 2, (info["iterations"], oinfo.iterations)
+
+
+@pytest.mark.parametrize("p", (1, 2))
+def test_displacement_estimates_reused_while_phi_tilde_is_unchanged(p):
+    """The displacement block's level operators depend on phi~ alone, so a
+    set-up at a new U with the same phi~ estimates the phase-field block
+    only. Its eigenvalues and V-cycle equal those of a fresh context at the
+    second state bit for bit; a changed phi~ is estimated again."""
+    import torch
+    m = MESHES["tiny"]
+
+    def fresh():
+        return Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], u_std=1e-2,
+                    phit="shifted", build_oracle=False)
+    a = fresh()
+    a.load_state(setup_mg=True)
+    n = a.n
+    act = a.dev(a.active.astype(np.uint8), torch.uint8)
+    U2 = a.U_raw.copy()
+    U2[:2 * n] *= 1.7
+    src = inputs.random_vector(a.X, a.Y, 31)
+    for phit in (a.phit_raw, 0.95 * a.phit_raw + 0.01):
+        a.g.set_state(a.dev(U2), a.dev(a.phi_old_raw), a.dev(phit), act, setup_mg=True)
+        b = fresh()
+        b.g.set_state(b.dev(U2), b.dev(b.phi_old_raw), b.dev(phit), act, setup_mg=True)
+        la, lb = a.g.get_eigen(), b.g.get_eigen()
+        assert np.array_equal(la[0], lb[0]) and np.array_equal(la[1], lb[1])
+        assert np.array_equal(a.g.vcycle(a.dev(src)).cpu().numpy(), b.g.vcycle(b.dev(src)).cpu().numpy())
+        U2[:2 * n] *= 0.8
