@@ -3,9 +3,10 @@
 // iteration vectors in LDS and runs every step of the fixed-length solve:
 // Chebyshev from x = 0 over [lambda_min, upper_factor * lambda_max], or
 // Jacobi-preconditioned CG from x = 0 with per-block scalars. Each thread
-// evaluates one level-0 cell with the same cell routine as the tile kernels
-// and adds it into the accumulator in colour phases (cells of one colour
-// share no node), so the summation order is fixed. Replaces 2-3 launches per
+// evaluates one level-0 cell with the same cell routines as the tile kernels
+// (its state coefficients once, kept in registers for every step) and adds it
+// into the accumulator in colour phases (cells of one colour share no node),
+// so the summation order is fixed. Replaces 2-3 launches per
 // step (tile kernel, shared-node fix-up, CG scalars) by one launch.
 #pragma once
 
@@ -88,10 +89,24 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
   const T kap = T(m.kappa), pr = T(m.pressure), Gc = T(m.Gc), ell = T(m.ell);
   const T mu = T(m.mu), lam = T(m.lam);
   auto gather = [&](int f, T(&u)[NL]) {
-    const double* base = f < 3 ? xo + f * n0 : st + (f - 3) * n0;
 #pragma unroll
-    for (int k = 0; k < NL; ++k) u[k] = T(base[nodes[k]]);
+    for (int k = 0; k < NL; ++k) u[k] = T(xo[f * n0 + nodes[k]]);
   };
+  __syncthreads();
+  // the state enters every step only through these coefficients
+  T cg[NL], cc1[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    cg[k] = T(0);
+    cc1[k] = T(0);
+  }
+  if (live) {
+    auto gather_state = [&](int f, T(&u)[NL]) {
+#pragma unroll
+      for (int k = 0; k < NL; ++k) u[k] = T(st[f * n0 + nodes[k]]);
+    };
+    level_coefs<P, T>(a.B, a.H, mu, lam, kap, pr, Gc, ell, gather_state, cg, cc1);
+  }
   // acc = A xo (level block operator, held columns of xo are zero)
   auto apply = [&]() {
     for (int i = tid; i < N; i += COARSE_THREADS) acc[i] = 0.0;
@@ -101,7 +116,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int k = 0; k < NL; ++k) out[c][k] = T(0);
-    if (live) jacobian_cell<P, T, false>(a.B, a.H, mu, lam, kap, pr, Gc, ell, gather, out);
+    if (live) level_cell<P, T>(a.B, mu, lam, Gc * ell, cg, cc1, gather, out);
     for (int col = 0; col < a.ncolor; ++col) {
       if (color == col) {
 #pragma unroll

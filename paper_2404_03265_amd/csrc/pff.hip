@@ -63,6 +63,7 @@ struct LevelWork {
   T* x[2] = {nullptr, nullptr};
   T* dir[2] = {nullptr, nullptr};
   T* dinv = nullptr;
+  T* coef = nullptr;   // operator state coefficients: [2 (p+1)^2][cell records]
 };
 
 struct DevLevel {
@@ -380,7 +381,7 @@ struct pff_ctx {
       else
         hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI, HANG>), dim3(t.n_tiles), dim3(threads), lds, s, a);
     }
-    if (t.n_shared > 0)
+    if (MODE != MODE_LEVEL_COEF && t.n_shared > 0)
       hipLaunchKernelGGL((shared_fixup<T, MODE, EPI>), dim3(grid_for(t.n_shared)), dim3(256), 0, s, a);
     HIPCHK(hipGetLastError());
   }
@@ -548,9 +549,11 @@ struct pff_ctx {
       take(carve ? a.state : d64, nl); take(carve ? a.d : d64, nl); take(carve ? a.x[0] : d64, nl);
       take(carve ? a.x[1] : d64, nl); take(carve ? a.dir[0] : d64, nl); take(carve ? a.dir[1] : d64, nl);
       take(carve ? a.dinv : d64, nl);
+      take(carve ? a.coef : d64, int64_t(2 * (p + 1) * (p + 1)) * L.tiles.n_rec);
       take(carve ? b.state : d32, nl); take(carve ? b.d : d32, nl); take(carve ? b.x[0] : d32, nl);
       take(carve ? b.x[1] : d32, nl); take(carve ? b.dir[0] : d32, nl); take(carve ? b.dir[1] : d32, nl);
       take(carve ? b.dinv : d32, nl);
+      take(carve ? b.coef : d32, int64_t(2 * (p + 1) * (p + 1)) * L.tiles.n_rec);
       if (carve) a.ready = b.ready = true;
     }
     take(carve ? V : dummy, int64_t(m + 1) * N);
@@ -591,6 +594,7 @@ struct pff_ctx {
     w.d = dalloc<T>(3 * nl);
     for (int i = 0; i < 2; ++i) { w.x[i] = dalloc<T>(3 * nl); w.dir[i] = dalloc<T>(3 * nl); }
     w.dinv = dalloc<T>(3 * nl);
+    w.coef = dalloc<T>(int64_t(2 * (p + 1) * (p + 1)) * L.tiles.n_rec);
     w.ready = true;
   }
 
@@ -602,9 +606,8 @@ struct pff_ctx {
     TileArgs<T> a{};
     a.src = x;
     a.dst = dst;
-    a.st[0] = w.state;
-    a.st[1] = w.state + L.n;
-    a.st[2] = w.state + 2 * L.n;
+    a.coef = w.coef;
+    a.n_coef = L.tiles.n_rec;
     a.b = b;
     a.dold = dold;
     a.dinv = w.dinv;
@@ -618,6 +621,20 @@ struct pff_ctx {
     else if (epi == EPI_RESID) launch_tile<T, MODE_LEVEL, EPI_RESID>(L.tiles, L.flags, L.n, a);
     else if (epi == EPI_CHEB_FIRST) launch_tile<T, MODE_LEVEL, EPI_CHEB_FIRST>(L.tiles, L.flags, L.n, a);
     else launch_tile<T, MODE_LEVEL, EPI_CHEB>(L.tiles, L.flags, L.n, a);
+  }
+
+  // the level operator's state coefficients per cell (from the level state)
+  template <typename T>
+  void level_coef(int l) {
+    DevLevel& L = lev(l);
+    LevelWork<T>& w = work<T>(L);
+    TileArgs<T> a{};
+    a.st[0] = w.state;
+    a.st[1] = w.state + L.n;
+    a.st[2] = w.state + 2 * L.n;
+    a.coef = w.coef;
+    a.n_coef = L.tiles.n_rec;
+    launch_tile<T, MODE_LEVEL_COEF, EPI_PLAIN>(L.tiles, L.flags, L.n, a);
   }
 
   template <typename T>
@@ -1099,7 +1116,10 @@ struct pff_ctx {
       hipLaunchKernelGGL((k_inject<T>), dim3(grid_for(L.n)), dim3(256), 0, s, w.state, L.n, L.leaf_index, U, phit,
                          n);
     }
-    for (int l = 0; l < nlev(); ++l) level_diag<T>(l);
+    for (int l = 0; l < nlev(); ++l) {
+      level_coef<T>(l);
+      level_diag<T>(l);
+    }
     HIPCHK(hipGetLastError());
   }
 
@@ -1580,9 +1600,9 @@ int pff_destroy(pff_ctx* c) {
     f(D.leaf_index); f(D.PT_ptr); f(D.PT_col); f(D.P_ell); f(D.PT_ell); f(D.PT_rows); f(D.P_wtab);
     if (!c->ws) {   // a bound workspace belongs to the caller
       LevelWork<double>& a = D.w64;
-      f(a.state); f(a.d); f(a.x[0]); f(a.x[1]); f(a.dir[0]); f(a.dir[1]); f(a.dinv);
+      f(a.state); f(a.d); f(a.x[0]); f(a.x[1]); f(a.dir[0]); f(a.dir[1]); f(a.dinv); f(a.coef);
       LevelWork<float>& b = D.w32;
-      f(b.state); f(b.d); f(b.x[0]); f(b.x[1]); f(b.dir[0]); f(b.dir[1]); f(b.dinv);
+      f(b.state); f(b.d); f(b.x[0]); f(b.x[1]); f(b.dir[0]); f(b.dir[1]); f(b.dinv); f(b.coef);
     }
   }
   if (!c->ws) {

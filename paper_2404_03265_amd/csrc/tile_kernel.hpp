@@ -36,6 +36,7 @@ enum Mode : int {
   MODE_DE,         // dF/dE
   MODE_DP,         // dF/dp
   MODE_MASS,       // lumped phase-field mass (row sums)
+  MODE_LEVEL_COEF, // state coefficients of a level operator at its Gauss points
 };
 
 // EPI_CHEB_FIRST: the first two Chebyshev updates from x = 0 in one pass: the
@@ -80,17 +81,23 @@ struct TileArgs {
   T* xnew;
   T c1[2], c2[2];    // Chebyshev coefficients per block (u, phi)
   T c0[2];           // EPI_CHEB_FIRST: coefficient of the first update d_0 = c0 D^-1 b
+  // level operator state coefficients per cell record (MODE_LEVEL reads,
+  // MODE_LEVEL_COEF writes): [2 (p+1)^2][n_coef], g at the Gauss points,
+  // then H^2 c1 (see level_coefs)
+  T* coef;
+  int64_t n_coef;
 };
 
 template <int MODE>
 struct ModeTraits {
-  static constexpr bool leaf = !(MODE == MODE_LEVEL || MODE == MODE_DIAG_LEVEL);
+  static constexpr bool leaf = !(MODE == MODE_LEVEL || MODE == MODE_DIAG_LEVEL || MODE == MODE_LEVEL_COEF);
   static constexpr int n_src = (MODE == MODE_J || MODE == MODE_JT || MODE == MODE_LEVEL) ? 3
                                : (MODE == MODE_RESID || MODE == MODE_TCVGRAD || MODE == MODE_DGC ||
                                   MODE == MODE_DE || MODE == MODE_DP) ? 3 : 0;
-  // state fields staged besides src
+  // state fields staged besides src (the level operator reads its state
+  // through the per-cell coefficients of MODE_LEVEL_COEF instead)
   static constexpr int n_state = (MODE == MODE_J || MODE == MODE_JT || MODE == MODE_DIAG_LEAF) ? 4
-                                 : (MODE == MODE_LEVEL || MODE == MODE_DIAG_LEVEL) ? 3
+                                 : (MODE == MODE_DIAG_LEVEL || MODE == MODE_LEVEL_COEF) ? 3
                                  : (MODE == MODE_RESID || MODE == MODE_DGC || MODE == MODE_DE || MODE == MODE_DP) ? 1
                                  : 0;
   // src columns are masked (constrained columns of the operator)
@@ -248,6 +255,80 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
   }
 }
 
+// State coefficients of the level block operator at the Gauss points of one
+// cell, in the reference units of jacobian_cell (fields: 0, 1 the state
+// u_x, u_y; 2 phit):
+//   g = (1-k) phit^2 + k,   H^2 c1 = (1-k) S^ + 2 p H tr e^ + H^2 Gc/l.
+// The level state is fixed for a multigrid set-up, so they are evaluated
+// once per set-up (MODE_LEVEL_COEF) rather than in every application.
+template <int P, typename T, class Gather>
+__device__ __forceinline__ void level_coefs(const Basis<T>& B, T H, T mu, T lam, T kap, T pr, T Gc, T ell,
+                                            Gather&& gather, T (&g)[(P + 1) * (P + 1)],
+                                            T (&c1)[(P + 1) * (P + 1)]) {
+  constexpr int NL = (P + 1) * (P + 1), NQ = NL;
+  const T twopH = T(2) * pr * H, gcl2 = H * H * Gc / ell;
+  {
+    T u[NL], sx1[NQ], sy1[NQ], sx2[NQ], sy2[NQ];
+    gather(0, u);
+    interp_g<P, T>(B, u, sx1, sy1);
+    gather(1, u);
+    interp_g<P, T>(B, u, sx2, sy2);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const T exx = sx1[q], eyy = sy2[q], exy = T(0.5) * (sy1[q] + sx2[q]);
+      const T tr = exx + eyy;
+      const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = T(2) * mu * exy;
+      const T S = sxx * exx + syy * eyy + T(2) * sxy * exy;
+      c1[q] = (T(1) - kap) * S + twopH * tr + gcl2;
+    }
+  }
+  T u[NL], tq[NQ];
+  gather(2, u);
+  interp_v<P, T>(B, u, tq);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) g[q] = (T(1) - kap) * tq[q] * tq[q] + kap;
+}
+
+// One cell of the level block operator diag(G_uu, G_phiphi) (Sec. 3.2) from
+// its state coefficients (level_coefs); gather(f, u), f = 0..2, fetches the
+// operand. The same arithmetic as jacobian_cell without the coupling.
+template <int P, typename T, class Gather>
+__device__ __forceinline__ void level_cell(const Basis<T>& B, T mu, T lam, T gcell, const T (&g)[(P + 1) * (P + 1)],
+                                           const T (&c1)[(P + 1) * (P + 1)], Gather&& gather,
+                                           T (&out)[3][(P + 1) * (P + 1)]) {
+  constexpr int NL = (P + 1) * (P + 1), NQ = NL;
+  {
+    T u[NL], dxx[NQ], dxy[NQ], dyx[NQ], dyy[NQ];
+    gather(0, u);
+    interp_g<P, T>(B, u, dxx, dxy);
+    gather(1, u);
+    interp_g<P, T>(B, u, dyx, dyy);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const T gq = g[q];
+      const T exx = dxx[q], eyy = dyy[q], exy2 = dxy[q] + dyx[q];
+      const T tr = exx + eyy;
+      const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = mu * exy2;
+      dxx[q] = gq * sxx;
+      dxy[q] = gq * sxy;
+      dyx[q] = gq * sxy;
+      dyy[q] = gq * syy;
+    }
+    integrate_gw<P, T>(B, dxx, dxy, out[0]);
+    integrate_gw<P, T>(B, dyx, dyy, out[1]);
+  }
+  T u[NL], pv[NQ], px[NQ], py[NQ];
+  gather(2, u);
+  interp_vg<P, T>(B, u, pv, px, py);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    pv[q] = c1[q] * pv[q];
+    px[q] = gcell * px[q];
+    py[q] = gcell * py[q];
+  }
+  integrate_w<P, T>(B, pv, px, py, out[2]);
+}
+
 // One cell of the transposed Jacobian, in the reference units of
 // jacobian_cell: the coupling block G_phi,u moves from the phi rows to the u
 // rows, weighted by the phase-field operand,
@@ -359,8 +440,8 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
     for (int qx = 0; qx < N1; ++qx) wq[qy * N1 + qx] = a.B.w[qx] * a.B.w[qy];
   const T invH = T(1) / H;
 
-  if constexpr (MODE == MODE_J || MODE == MODE_LEVEL) {
-    jacobian_cell<P, T, MODE == MODE_J>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
+  if constexpr (MODE == MODE_J) {
+    jacobian_cell<P, T, true>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
   } else if constexpr (MODE == MODE_JT) {
     jacobian_t_cell<P, T>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
   } else if constexpr (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
@@ -540,7 +621,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   // after accumulation); the inverse diagonal needs the per-cell form.
   // (the level operator too: the levels of global-coarsening multigrid have
   // hanging nodes; local-smoothing levels have no records, nhang = 0)
-  constexpr bool NODE_HANG = (TR::leaf && MODE != MODE_DIAG_LEAF) || MODE == MODE_LEVEL;
+  constexpr bool NODE_HANG = (TR::leaf && MODE != MODE_DIAG_LEAF) || MODE == MODE_LEVEL || MODE == MODE_LEVEL_COEF;
   const int hr0 = NODE_HANG ? ti[TILE_HANG0] : 0, nhang = NODE_HANG ? ti[TILE_NHANG] : 0;
   const int nhcol = NODE_HANG ? ti[TILE_NHCOLOR] : 0;
   const int nloc = no + ns;
@@ -553,6 +634,9 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   const bool live = cell < nc;
   int loc[NL];
   unsigned info = 0;
+  // level operator: the cell's state coefficients (g, then H^2 c1)
+  constexpr int NCF = MODE == MODE_LEVEL ? 2 * NQ : 1;
+  T cf[NCF];
   // the cell record is requested after the first round's node loads (see
   // below): its latency overlaps theirs instead of preceding them
   auto load_cell_record = [&]() {
@@ -562,6 +646,10 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
 #pragma unroll
       for (int k = 0; k < NL; ++k) loc[k] = cl[rec * NL + k];
       info = a.cell_info[rec];
+      if constexpr (MODE == MODE_LEVEL) {
+#pragma unroll
+        for (int k = 0; k < NCF; ++k) cf[k] = a.coef[k * a.n_coef + rec];
+      }
     }
   };
 
@@ -722,6 +810,27 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
     }
   }
 
+  if constexpr (MODE == MODE_LEVEL_COEF) {
+    // the level state's coefficients of every cell; no accumulation
+    if (live) {
+      const int lev = int((info >> CELL_LEVEL_SHIFT) & 31u);
+      const T H = T(ldexp(double(a.H0), -lev));
+      auto gather = [&](int field, T(&u)[NL]) {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) u[k] = T(lds[field * ML + loc[k]]);
+      };
+      T g[NQ], c1[NQ];
+      level_coefs<P, T>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, g, c1);
+      const int64_t rec = int64_t(c0) + cell;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        a.coef[q * a.n_coef + rec] = g[q];
+        a.coef[(NQ + q) * a.n_coef + rec] = c1[q];
+      }
+    }
+    return;
+  }
+
   // 2./3. one cell per thread, colour-phased accumulation
   {
     T out[3][NL];
@@ -741,7 +850,17 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         for (int k = 0; k < NL; ++k) u[k] = T(lds[field * ML + loc[k]]);
         if (hang) hang_apply<P, T>(a.B, u, info);
       };
-      compute_cell<P, T, MODE>(a, H, hang, info, gather, out);
+      if constexpr (MODE == MODE_LEVEL) {
+        T g[NQ], c1[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          g[q] = cf[q];
+          c1[q] = cf[NQ + q];
+        }
+        level_cell<P, T>(a.B, mu, lam, Gc * ell, g, c1, gather, out);
+      } else {
+        compute_cell<P, T, MODE>(a, H, hang, info, gather, out);
+      }
     }
     // every gather is done: the accumulators take over the field arrays
     __syncthreads();
