@@ -618,6 +618,7 @@ struct pff_ctx {
       a.c0[i] = c0 ? c0[i] : T(0);
     }
     if (epi == EPI_PLAIN) launch_tile<T, MODE_LEVEL, EPI_PLAIN>(L.tiles, L.flags, L.n, a, part_buf, part_cap);
+    else if (epi == EPI_PHI) launch_tile<T, MODE_LEVEL, EPI_PHI>(L.tiles, L.flags, L.n, a, part_buf, part_cap);
     else if (epi == EPI_RESID) launch_tile<T, MODE_LEVEL, EPI_RESID>(L.tiles, L.flags, L.n, a);
     else if (epi == EPI_CHEB_FIRST) launch_tile<T, MODE_LEVEL, EPI_CHEB_FIRST>(L.tiles, L.flags, L.n, a);
     else launch_tile<T, MODE_LEVEL, EPI_CHEB>(L.tiles, L.flags, L.n, a);
@@ -1008,8 +1009,9 @@ struct pff_ctx {
     // the same partition of the rows with and without the displacement block
     const int nb = std::min(RED_BLOCKS, grid_for(2 * nl));
     for (int it = 0; it < max_it; ++it) {
-      level_apply<double>(l, pv, q, EPI_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, L.epart,
-                          L.epart_bytes);
+      // the phase-field block alone: its rows of the block operator
+      level_apply<double>(l, pv, q, skip_u ? EPI_PHI : EPI_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr,
+                          nullptr, L.epart, L.epart_bytes);
       hipLaunchKernelGGL(k_eig_pq_partial, dim3(nb), dim3(RED_THREADS), 0, s, pv, q, nl, begin, rp);
       hipLaunchKernelGGL(k_eig_alpha_reduce, dim3(1), dim3(RED_THREADS), 0, s, rp, nb, sc, L.eal, stride, it);
       hipLaunchKernelGGL(k_eig_update_partial, dim3(nb), dim3(RED_THREADS), 0, s, r, z, q, w.dinv, sc, nl, begin,

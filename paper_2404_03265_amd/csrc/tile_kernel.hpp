@@ -42,7 +42,10 @@ enum Mode : int {
 // EPI_CHEB_FIRST: the first two Chebyshev updates from x = 0 in one pass: the
 // operand x = d_0 = c0 D^-1 b is formed while staging (never stored), then the
 // EPI_CHEB update with d_old = d_0.
-enum Epi : int { EPI_PLAIN = 0, EPI_RESID = 1, EPI_CHEB = 2, EPI_CHEB_FIRST = 3 };
+// EPI_PHI (level operator): the phase-field rows alone, from the phase-field
+// operand alone (the block operator has no coupling); the displacement rows
+// of dst are not written.
+enum Epi : int { EPI_PLAIN = 0, EPI_RESID = 1, EPI_CHEB = 2, EPI_CHEB_FIRST = 3, EPI_PHI = 4 };
 
 template <typename T>
 struct TileArgs {
@@ -119,7 +122,7 @@ __device__ __forceinline__ void node_epilogue(const TileArgs<T>& a, int c, int64
       a.dst[i] = cons ? a.src[i] : v;
     }
   } else if constexpr (MODE == MODE_LEVEL) {
-    if constexpr (EPI == EPI_PLAIN) {
+    if constexpr (EPI == EPI_PLAIN || EPI == EPI_PHI) {
       a.dst[i] = v;
     } else if constexpr (EPI == EPI_RESID) {
       // residual to restrict: zero on rows held at zero on this level
@@ -327,6 +330,24 @@ __device__ __forceinline__ void level_cell(const Basis<T>& B, T mu, T lam, T gce
     py[q] = gcell * py[q];
   }
   integrate_w<P, T>(B, pv, px, py, out[2]);
+}
+
+// The phase-field rows of level_cell alone: gather(0, u) fetches the
+// phase-field operand, c1 holds H^2 c1 at the Gauss points.
+template <int P, typename T, class Gather>
+__device__ __forceinline__ void level_cell_phi(const Basis<T>& B, T gcell, const T (&c1)[(P + 1) * (P + 1)],
+                                               Gather&& gather, T (&out)[(P + 1) * (P + 1)]) {
+  constexpr int NL = (P + 1) * (P + 1), NQ = NL;
+  T u[NL], pv[NQ], px[NQ], py[NQ];
+  gather(0, u);
+  interp_vg<P, T>(B, u, pv, px, py);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    pv[q] = c1[q] * pv[q];
+    px[q] = gcell * px[q];
+    py[q] = gcell * py[q];
+  }
+  integrate_w<P, T>(B, pv, px, py, out);
 }
 
 // One cell of the transposed Jacobian, in the reference units of
@@ -574,7 +595,10 @@ template <int P, typename T, int MODE, int EPI, bool HANG>
 __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
   using TR = ModeTraits<MODE>;
-  constexpr int NF = TR::n_src + TR::n_state;
+  // EPI_PHI stages the phase-field operand alone (field 0 is component 2)
+  constexpr bool PHI = MODE == MODE_LEVEL && EPI == EPI_PHI;
+  constexpr int NF = PHI ? 1 : TR::n_src + TR::n_state;
+  constexpr int C0 = PHI ? 2 : 0;   // first output component
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ML = a.max_local;
   using LT = double;   // LDS values (FP64 for both precisions)
@@ -635,7 +659,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   int loc[NL];
   unsigned info = 0;
   // level operator: the cell's state coefficients (g, then H^2 c1)
-  constexpr int NCF = MODE == MODE_LEVEL ? 2 * NQ : 1;
+  constexpr int NCF = MODE == MODE_LEVEL ? (PHI ? NQ : 2 * NQ) : 1;
   T cf[NCF];
   // the cell record is requested after the first round's node loads (see
   // below): its latency overlaps theirs instead of preceding them
@@ -647,8 +671,9 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       for (int k = 0; k < NL; ++k) loc[k] = cl[rec * NL + k];
       info = a.cell_info[rec];
       if constexpr (MODE == MODE_LEVEL) {
+        // EPI_PHI: H^2 c1 alone
 #pragma unroll
-        for (int k = 0; k < NCF; ++k) cf[k] = a.coef[k * a.n_coef + rec];
+        for (int k = 0; k < NCF; ++k) cf[k] = a.coef[((PHI ? NQ : 0) + k) * a.n_coef + rec];
       }
     }
   };
@@ -723,6 +748,8 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         if constexpr (FIRST) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) vp[k][c] = a.c0[c < 2 ? 0 : 1] * a.dinv[c * n + g] * a.b[c * n + g];
+        } else if constexpr (PHI) {
+          vp[k][0] = a.src[2 * n + g];
         } else if constexpr (TR::n_src > 0) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) vp[k][c] = a.src[c * n + g];
@@ -739,6 +766,8 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         if constexpr (FIRST) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) vsh[k][c] = a.c0[c < 2 ? 0 : 1] * a.dinv[c * n + g] * a.b[c * n + g];
+        } else if constexpr (PHI) {
+          vsh[k][0] = a.src[2 * n + g];
         } else if constexpr (TR::n_src > 0) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) vsh[k][c] = a.src[c * n + g];
@@ -757,7 +786,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
           T x = v[c];
           if constexpr (TR::mask_src) {
             if (c < 3) {
-              const bool fixed = (c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
+              const bool fixed = (C0 + c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
               if (fixed) x = T(0);
             }
           }
@@ -850,7 +879,12 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         for (int k = 0; k < NL; ++k) u[k] = T(lds[field * ML + loc[k]]);
         if (hang) hang_apply<P, T>(a.B, u, info);
       };
-      if constexpr (MODE == MODE_LEVEL) {
+      if constexpr (PHI) {
+        T c1[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) c1[q] = cf[q];
+        level_cell_phi<P, T>(a.B, Gc * ell, c1, gather, out[2]);
+      } else if constexpr (MODE == MODE_LEVEL) {
         T g[NQ], c1[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -865,9 +899,8 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
     // every gather is done: the accumulators take over the field arrays
     __syncthreads();
     for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
-      acc[l] = LT(0);
-      acc[ML + l] = LT(0);
-      acc[2 * ML + l] = LT(0);
+#pragma unroll
+      for (int c = C0; c < 3; ++c) acc[c * ML + l] = LT(0);
     }
     __syncthreads();
     // LDS atomic adds without return: no read-modify-write round trip per
@@ -884,7 +917,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         for (int k = 0; k < NL; ++k) {
           const int l = loc[k];
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
+          for (int c = C0; c < 3; ++c)
             __hip_atomic_fetch_add(&acc[c * ML + l], LT(out[c][k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
@@ -901,7 +934,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         const double* hw = a.hang_w + 3 * int64_t(hr0 + r);
         const int h = hr[0];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = C0; c < 3; ++c) {
           const LT v = acc[c * ML + h];
 #pragma unroll
           for (int k = 0; k <= P; ++k)
@@ -948,12 +981,12 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
     for (int l = threadIdx.x; l < no; l += blockDim.x) {
       const uint8_t f = lflag[l];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, true, T>(a, c, int64_t(o0) + l, f, T(acc[c * ML + l]));
+      for (int c = C0; c < 3; ++c) node_epilogue<MODE, EPI, true, T>(a, c, int64_t(o0) + l, f, T(acc[c * ML + l]));
     }
   }
   for (int r = threadIdx.x; r < ns; r += blockDim.x) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.part[c * a.n_slots + slot0 + r] = T(acc[c * ML + no + r]);
+    for (int c = C0; c < 3; ++c) a.part[c * a.n_slots + slot0 + r] = T(acc[c * ML + no + r]);
   }
 }
 
@@ -961,6 +994,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
 // ascending tile order, then apply the mode's epilogue.
 template <typename T, int MODE, int EPI>
 __global__ void __launch_bounds__(256) shared_fixup(const TileArgs<T> a) {
+  constexpr int C0 = (MODE == MODE_LEVEL && EPI == EPI_PHI) ? 2 : 0;
   for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < a.n_shared;
        s += int64_t(gridDim.x) * blockDim.x) {
     const int64_t g = a.n_private + s;
@@ -975,18 +1009,18 @@ __global__ void __launch_bounds__(256) shared_fixup(const TileArgs<T> a) {
       for (int j = 0; j < SHARED_SLOTS; ++j)
         if (slot[j] >= 0) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) v[c] += a.part[c * a.n_slots + slot[j]];
+          for (int c = C0; c < 3; ++c) v[c] += a.part[c * a.n_slots + slot[j]];
         }
     } else {
       for (int j = 0; j < a.sh_w; ++j) {
         const int slot = a.sh_tab[s * a.sh_w + j];
         if (slot < 0) break;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] += a.part[c * a.n_slots + slot];
+        for (int c = C0; c < 3; ++c) v[c] += a.part[c * a.n_slots + slot];
       }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) node_epilogue<MODE, EPI, false, T>(a, c, g, f, v[c]);
+    for (int c = C0; c < 3; ++c) node_epilogue<MODE, EPI, false, T>(a, c, g, f, v[c]);
   }
 }
 
