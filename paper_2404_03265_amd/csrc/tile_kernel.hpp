@@ -75,7 +75,7 @@ struct TileArgs {
   Basis<T> B;
   Material mat;
   const T* src;      // 3n input (operand / state U)
-  const T* st[4];    // state fields: leaf (ux, uy, phi, phit); level (ux, uy, phit)
+  const T* st[4];    // state fields: leaf (ux, uy, phi, phit); level (ux, uy, phit: inverse diagonal, coefficients)
   T* dst;            // 3n output
   // level epilogues
   const T* b;        // right-hand side (EPI_RESID, EPI_CHEB)
@@ -162,11 +162,10 @@ __device__ __forceinline__ void node_epilogue(const TileArgs<T>& a, int c, int64
   }
 }
 
-// One cell of the Jacobian (CPL: with the u-phi coupling) or of the level
-// block operator (without it): gather(f, u) fetches the cell's nodal values of
-// field f (0..2 the operand, then the state fields: u_x, u_y, [phi,] phit),
-// out receives the cell's contributions to its nodes.
-template <int P, typename T, bool CPL, class Gather>
+// One cell of the Jacobian: gather(f, u) fetches the cell's nodal values of
+// field f (0..2 the operand, then the state fields: u_x, u_y, phi, phit), out
+// receives the cell's contributions to its nodes.
+template <int P, typename T, class Gather>
 __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T lam, T kap, T pr, T Gc, T ell,
                                               Gather&& gather, T (&out)[3][(P + 1) * (P + 1)]) {
   constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
@@ -176,10 +175,10 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
   //   u rows:   g(phit) sigma^(du) : grad^ psi
   //   phi rows: [H^2 c1 dphi + H B : e(du)] psi + Gc l grad^ dphi . grad^ psi
   //   H^2 c1 = (1-k) S^ + 2 p H tr e^ + H^2 Gc/l,
-  //   H B    = 2 (1-k) phi sigma^(u) + 2 p H phi I   (coupling; not on levels)
+  //   H B    = 2 (1-k) phi sigma^(u) + 2 p H phi I   (the coupling G_phi,u)
   // The level block operator diag(G_uu, G_phiphi) (Sec. 3.2) is the same
-  // without the coupling term, with the injected level state (u_x, u_y, phit).
-  constexpr int FUX = 3, FUY = 4, FPHI = 5, FPT = CPL ? 6 : 5;
+  // without the coupling term (level_coefs, level_cell).
+  constexpr int FUX = 3, FUY = 4, FPHI = 5, FPT = 6;
   const T twopH = T(2) * pr * H, gcl2 = H * H * Gc / ell, gcell = Gc * ell;
   T c1[NQ], bxx[NQ], byy[NQ], bxy[NQ];
   {
@@ -200,7 +199,7 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
       bxy[q] = sxy;
     }
   }
-  if constexpr (CPL) {
+  {
     T u[NL], pq[NQ];
     gather(FPHI, u);
     interp_v<P, T>(B, u, pq);
@@ -219,11 +218,8 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
     interp_g<P, T>(B, u, dxx, dxy);
     gather(1, u);
     interp_g<P, T>(B, u, dyx, dyy);
-    if constexpr (CPL) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        be[q] = bxx[q] * dxx[q] + byy[q] * dyy[q] + bxy[q] * (dxy[q] + dyx[q]);
-    }
+    for (int q = 0; q < NQ; ++q) be[q] = bxx[q] * dxx[q] + byy[q] * dyy[q] + bxy[q] * (dxy[q] + dyx[q]);
   }
   {
     T u[NL], tq[NQ];
@@ -249,8 +245,7 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
     interp_vg<P, T>(B, u, pv, px, py);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      if constexpr (CPL) pv[q] = c1[q] * pv[q] + be[q];
-      else pv[q] = c1[q] * pv[q];
+      pv[q] = c1[q] * pv[q] + be[q];
       px[q] = gcell * px[q];
       py[q] = gcell * py[q];
     }
@@ -462,7 +457,7 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
   const T invH = T(1) / H;
 
   if constexpr (MODE == MODE_J) {
-    jacobian_cell<P, T, true>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
+    jacobian_cell<P, T>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
   } else if constexpr (MODE == MODE_JT) {
     jacobian_t_cell<P, T>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
   } else if constexpr (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
