@@ -568,18 +568,24 @@ def test_gmres_restarts_match_oracle(p):
     assert abs(info["iterations"] - oinfo.iterations) <= 2, (info["iterations"], oinfo.iterations)
 
 
+@pytest.mark.parametrize("hier", ("local", "global"))
 @pytest.mark.parametrize("p", (1, 2))
-def test_displacement_estimates_reused_while_phi_tilde_is_unchanged(p):
+def test_displacement_estimates_reused_while_phi_tilde_is_unchanged(p, hier):
     """The displacement block's level operators depend on phi~ alone, so a
     set-up at a new U with the same phi~ estimates the phase-field block
-    only. Its eigenvalues and V-cycle equal those of a fresh context at the
-    second state bit for bit; a changed phi~ is estimated again."""
+    only (its level operator evaluating the phase-field rows alone). Its
+    eigenvalues and V-cycle equal those of a fresh context at the second
+    state bit for bit; a changed phi~ is estimated again. Both hierarchies
+    (the global-coarsening levels carry hanging nodes)."""
     import torch
+    from paper_2404_03265_amd import SolverParams
     m = MESHES["tiny"]
+    gc = hier == "global"
 
     def fresh():
         return Case(m["n_base"], m["n_local"], p, coarse=m["coarse"], band=m["band"], u_std=1e-2,
-                    phit="shifted", build_oracle=False)
+                    phit="shifted", build_oracle=False, mg_global=gc,
+                    solver_params=SolverParams(mg_kind=1 if gc else 0))
     a = fresh()
     a.load_state(setup_mg=True)
     n = a.n
