@@ -85,12 +85,14 @@ typedef struct {
  *  ell: phase-field length scale l (Sec. 2, Table 1).
  *  cheb_degree: Chebyshev updates per smoothing step; smooth_range (0.08) and
  *  upper_factor (1.2): smoothing interval [smooth_range, upper_factor] *
- *  lambda_max (Sec. 3.2); eig_cg_its: CG steps of the eigenvalue estimate
- *  on levels > 0 (1..200, else PFF_E_ARG; default 20: with 10, the estimate
- *  of the finest level's displacement block stays up to 37 % below
- *  lambda_max once a crack of stiffness kappa ~ 1e-12 h is present, beyond
- *  the 1.2 safety factor, and the smoother amplifies the top of the
- *  spectrum);
+ *  lambda_max (Sec. 3.2); eig_cg_its: CG steps of the displacement block's
+ *  eigenvalue estimate on levels > 0 (1..200, else PFF_E_ARG; default 20:
+ *  with 10, the estimate of the finest level's displacement block stays up
+ *  to 37 % below lambda_max once a crack of stiffness kappa ~ 1e-12 h is
+ *  present, beyond the 1.2 safety factor, and the smoother amplifies the top
+ *  of the spectrum); eig_cg_its_phi: the same for the phase-field block
+ *  (1..200; default 10: within 3 % of lambda_max on every level of the
+ *  paper's meshes, inside the safety factor);
  *  coarse_mode 0: Chebyshev over [lambda_min, upper_factor * lambda_max] on
  *  level 0 with coarse_its updates (Sec. 3.2); coarse_mode 1: coarse_its
  *  Jacobi-preconditioned CG steps from zero on level 0, each block with its
@@ -138,6 +140,7 @@ typedef struct {
   double pdas_c;
   int32_t mg_kind;
   int32_t prec_kind;
+  int32_t eig_cg_its_phi;
 } pff_params;
 
 typedef struct {

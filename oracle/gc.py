@@ -189,10 +189,11 @@ class GCVCycle:
         for k, op in enumerate(self.ops):
             nk = self.gh.meshes[k].n_nodes
             bu, bp = block_masks(nk)
-            its = self.mgp.coarse_eig_its if k == 0 else self.mgp.eig_cg_its
+            its_u = self.mgp.coarse_eig_its if k == 0 else self.mgp.eig_cg_its
+            its_p = self.mgp.coarse_eig_its if k == 0 else self.mgp.eig_cg_its_phi
             if eigen is None:
-                lu = cg_eigs(op.A, op.Dinv, op.free & bu, its)
-                lp = cg_eigs(op.A, op.Dinv, op.free & bp, its)
+                lu = cg_eigs(op.A, op.Dinv, op.free & bu, its_u)
+                lp = cg_eigs(op.A, op.Dinv, op.free & bp, its_p)
                 op.lam_max = np.array([lu[1], lp[1]])
                 op.lam_min = np.array([lu[0], lp[0]])
             else:

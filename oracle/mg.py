@@ -50,7 +50,8 @@ class MGParams:
     cheb_degree: int = 3        # number of Chebyshev updates per smoothing
     smooth_range: float = 0.08  # lower end of the interval as a fraction of lambda_max
     upper_factor: float = 1.2   # upper end: factor on lambda_max
-    eig_cg_its: int = 20        # CG iterations for the eigenvalue estimate (levels > 0)
+    eig_cg_its: int = 20        # CG iterations for the displacement block's estimate (levels > 0)
+    eig_cg_its_phi: int = 10    # CG iterations for the phase-field block's estimate (levels > 0)
     coarse_mode: str = "cheb"   # 'cheb' (Sec. 3.2) or 'cg'
     coarse_its: int = 30        # coarse Chebyshev degree or CG iterations
     coarse_eig_its: int = 40    # CG iterations for the coarse eigenvalue estimate
@@ -310,10 +311,11 @@ class VCycle:
         for l, op in enumerate(self.ops):
             n = self.h.levels[l].n
             bu, bp = block_masks(n)
-            its = self.mgp.coarse_eig_its if l == 0 else self.mgp.eig_cg_its
+            its_u = self.mgp.coarse_eig_its if l == 0 else self.mgp.eig_cg_its
+            its_p = self.mgp.coarse_eig_its if l == 0 else self.mgp.eig_cg_its_phi
             if eigen is None:
-                lu = cg_eigs(op.A, op.Dinv, op.free & bu, its)
-                lp = cg_eigs(op.A, op.Dinv, op.free & bp, its)
+                lu = cg_eigs(op.A, op.Dinv, op.free & bu, its_u)
+                lp = cg_eigs(op.A, op.Dinv, op.free & bp, its_p)
                 op.lam_max = np.array([lu[1], lp[1]])
                 op.lam_min = np.array([lu[0], lp[0]])
             else:

@@ -51,6 +51,7 @@ class SolverParams:
     pdas_c: float = 0.0
     mg_kind: int = 0   # 0: local smoothing, 1: global coarsening (needs mg_global=True)
     prec_kind: int = 0  # 0: block diagonal, 1: block triangular (keeps the coupling block)
+    eig_cg_its_phi: int = 10  # CG steps of the phase-field block's eigenvalue estimate (levels > 0)
 
     def to_c(self):
         p = _lib.Params()

@@ -24,7 +24,7 @@ class Params(C.Structure):
                 ("gmres_max_its", C.c_int32), ("gmres_rtol", C.c_double),
                 ("gmres_atol", C.c_double), ("ls_omega", C.c_double), ("ls_max", C.c_int32),
                 ("vcycle_fp32", C.c_int32), ("pdas_c", C.c_double), ("mg_kind", C.c_int32),
-                ("prec_kind", C.c_int32)]
+                ("prec_kind", C.c_int32), ("eig_cg_its_phi", C.c_int32)]
 
 
 class GmresInfo(C.Structure):

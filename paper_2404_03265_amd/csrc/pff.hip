@@ -980,7 +980,7 @@ struct pff_ctx {
   // skip_u: the displacement block keeps its estimate and the vector passes
   // cover the phase-field rows only (the level operator is block diagonal,
   // so the phase-field rows of q do not depend on the other rows of p)
-  void eig_launch(int l, int its, double* out, bool skip_u = false) {
+  void eig_launch(int l, int its, int its_phi, double* out, bool skip_u = false) {
     DevLevel& L = lev(l);
     LevelWork<double>& w = w64of(L);
     const int64_t nl = L.n;
@@ -1001,9 +1001,11 @@ struct pff_ctx {
       dot2_async(r + off[b], r + off[b], len[b], sc + EIG_SC * b + EIG_PQ, rp);   // n_free (scratch slot)
       dot2_async(r + off[b], z + off[b], len[b], sc + EIG_SC * b + EIG_RZ, rp);
     }
-    hipLaunchKernelGGL(k_eig_init, dim3(1), dim3(64), 0, s, sc, its, skip_u ? 1 : 0);
+    hipLaunchKernelGGL(k_eig_init, dim3(1), dim3(64), 0, s, sc, its, its_phi, skip_u ? 1 : 0);
     const int stride = EIG_MAX_ITS;
-    const int max_it = std::min(its, stride);
+    // steps of the longer of the estimated blocks (a block past its own count
+    // takes no step)
+    const int max_it = std::min(skip_u ? its_phi : std::max(its, its_phi), stride);
     // per step: operator, p.q partials, alpha, update fused with the r.z
     // partials, beta, direction update (both blocks in every launch)
     // the same partition of the rows with and without the displacement block
@@ -1061,7 +1063,8 @@ struct pff_ctx {
     for (int i = 0; i < nl; ++i) {
       const int l = order[size_t(i)];
       s = es[i % EIG_STREAMS];
-      eig_launch(l, l == 0 ? prm.coarse_eig_its : prm.eig_cg_its, eig_host + per * size_t(l), skip_u);
+      eig_launch(l, l == 0 ? prm.coarse_eig_its : prm.eig_cg_its, l == 0 ? prm.coarse_eig_its : prm.eig_cg_its_phi,
+                 eig_host + per * size_t(l), skip_u);
     }
     s = main;
     for (int k = 0; k < EIG_STREAMS; ++k) {
@@ -1402,7 +1405,8 @@ static bool params_valid(const pff_params& p) {
          p.gmres_max_its >= 1 && p.ls_max >= 1 && p.ls_omega > 0.0 && p.ls_omega <= 1.0 &&
          p.coarse_mode >= 0 && p.coarse_mode <= 1 && p.eig_cg_its >= 1 && p.eig_cg_its <= EIG_MAX_ITS &&
          p.coarse_eig_its >= 1 && p.coarse_eig_its <= EIG_MAX_ITS && std::isfinite(p.pdas_c) && p.pdas_c >= 0.0 &&
-         p.mg_kind >= 0 && p.mg_kind <= 1 && p.prec_kind >= 0 && p.prec_kind <= 1;
+         p.mg_kind >= 0 && p.mg_kind <= 1 && p.prec_kind >= 0 && p.prec_kind <= 1 && p.eig_cg_its_phi >= 1 &&
+         p.eig_cg_its_phi <= EIG_MAX_ITS;
 }
 
 extern "C" {
@@ -1431,6 +1435,7 @@ int pff_default_params(pff_params* p) {
   p->ls_max = 10;
   p->vcycle_fp32 = 0;
   p->pdas_c = 0.0;
+  p->eig_cg_its_phi = 10;
   return PFF_OK;
 }
 

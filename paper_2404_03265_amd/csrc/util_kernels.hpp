@@ -458,11 +458,12 @@ constexpr int EIG_MAX_ITS = 200;   // largest accepted eig_cg_its / coarse_eig_i
 enum { EIG_RZ = 0, EIG_PQ, EIG_RZ2, EIG_ALPHA, EIG_BETA, EIG_RZ0, EIG_ACTIVE, EIG_STEPS, EIG_MAX };
 
 // start of the estimate from the two dots of the start vector (r.r = the
-// number of free unknowns in the EIG_PQ slot, r.z in EIG_RZ): at most `its`
-// steps and never more than the free unknowns; a block without free unknowns
+// number of free unknowns in the EIG_PQ slot, r.z in EIG_RZ): at most its_u
+// (displacement block) or its_phi (phase-field block) steps and never more
+// than the free unknowns; a block without free unknowns
 // or with r.z = 0 takes no step
 // skip_u: the displacement block takes no step (its estimate is kept)
-__global__ void k_eig_init(double* sc, int its, int skip_u) {
+__global__ void k_eig_init(double* sc, int its_u, int its_phi, int skip_u) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int b = 0; b < 2; ++b) {
     double* c = sc + EIG_SC * b;
@@ -473,7 +474,7 @@ __global__ void k_eig_init(double* sc, int its, int skip_u) {
     }
     const double n_free = c[EIG_PQ];
     c[EIG_RZ0] = c[EIG_RZ];
-    c[EIG_MAX] = fmin(double(its), n_free);
+    c[EIG_MAX] = fmin(double(b == 0 ? its_u : its_phi), n_free);
     c[EIG_ACTIVE] = (c[EIG_MAX] >= 1.0 && c[EIG_RZ] > 0.0) ? 1.0 : 0.0;
     c[EIG_STEPS] = 0.0;
   }

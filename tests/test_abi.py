@@ -46,10 +46,12 @@ def test_host_only_calls():
     assert lib.pff_default_params(C.byref(p)) == 0
     assert p.cheb_degree == 3 and p.gmres_restart == 30 and abs(p.smooth_range - 0.08) < 1e-15
     assert p.pdas_c == 0.0
+    assert p.eig_cg_its == 20 and p.eig_cg_its_phi == 10
     # invalid parameters are refused before any device work
     ctx = C.c_void_p()
     mspec = _lib.MeshSpec(32, 1, 1, 16, 2.0, 0.5, 0, 0)
-    for field, value in (("pdas_c", -1.0), ("pdas_c", float("inf")), ("cheb_degree", 0), ("eig_cg_its", 201)):
+    for field, value in (("pdas_c", -1.0), ("pdas_c", float("inf")), ("cheb_degree", 0), ("eig_cg_its", 201),
+                         ("eig_cg_its_phi", 0)):
         bad = _lib.Params()
         lib.pff_default_params(C.byref(bad))
         setattr(bad, field, value)

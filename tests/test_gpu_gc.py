@@ -96,9 +96,9 @@ def test_gc_eigenvalue_estimates(name, p):
         nl = c.gh.meshes[l].n_nodes
         bu = np.zeros(3 * nl, bool)
         bu[:2 * nl] = True
-        its = c.mgp.coarse_eig_its if l == 0 else c.mgp.eig_cg_its
+        its2 = (c.mgp.coarse_eig_its,) * 2 if l == 0 else (c.mgp.eig_cg_its, c.mgp.eig_cg_its_phi)
         for b, blk in enumerate((bu, ~bu)):
-            lo, hi = cg_eigs(op.A, op.Dinv, op.free & blk, its)
+            lo, hi = cg_eigs(op.A, op.Dinv, op.free & blk, its2[b])
             assert abs(lam_max[l, b] - hi) <= 1e-9 * hi, (l, b, lam_max[l, b], hi)
             if l == 0:
                 assert abs(lam_min0[b] - lo) <= 1e-9 * hi
