@@ -287,6 +287,24 @@ __device__ __forceinline__ void level_coefs(const Basis<T>& B, T H, T mu, T lam,
   for (int q = 0; q < NQ; ++q) g[q] = (T(1) - kap) * tq[q] * tq[q] + kap;
 }
 
+// The phase-field rows of the level block operator (level_cell): gather(0, u)
+// fetches the phase-field operand, c1 holds H^2 c1 at the Gauss points.
+template <int P, typename T, class Gather>
+__device__ __forceinline__ void level_cell_phi(const Basis<T>& B, T gcell, const T (&c1)[(P + 1) * (P + 1)],
+                                               Gather&& gather, T (&out)[(P + 1) * (P + 1)]) {
+  constexpr int NL = (P + 1) * (P + 1), NQ = NL;
+  T u[NL], pv[NQ], px[NQ], py[NQ];
+  gather(0, u);
+  interp_vg<P, T>(B, u, pv, px, py);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    pv[q] = c1[q] * pv[q];
+    px[q] = gcell * px[q];
+    py[q] = gcell * py[q];
+  }
+  integrate_w<P, T>(B, pv, px, py, out);
+}
+
 // One cell of the level block operator diag(G_uu, G_phiphi) (Sec. 3.2) from
 // its state coefficients (level_coefs); gather(f, u), f = 0..2, fetches the
 // operand. The same arithmetic as jacobian_cell without the coupling.
@@ -315,34 +333,7 @@ __device__ __forceinline__ void level_cell(const Basis<T>& B, T mu, T lam, T gce
     integrate_gw<P, T>(B, dxx, dxy, out[0]);
     integrate_gw<P, T>(B, dyx, dyy, out[1]);
   }
-  T u[NL], pv[NQ], px[NQ], py[NQ];
-  gather(2, u);
-  interp_vg<P, T>(B, u, pv, px, py);
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    pv[q] = c1[q] * pv[q];
-    px[q] = gcell * px[q];
-    py[q] = gcell * py[q];
-  }
-  integrate_w<P, T>(B, pv, px, py, out[2]);
-}
-
-// The phase-field rows of level_cell alone: gather(0, u) fetches the
-// phase-field operand, c1 holds H^2 c1 at the Gauss points.
-template <int P, typename T, class Gather>
-__device__ __forceinline__ void level_cell_phi(const Basis<T>& B, T gcell, const T (&c1)[(P + 1) * (P + 1)],
-                                               Gather&& gather, T (&out)[(P + 1) * (P + 1)]) {
-  constexpr int NL = (P + 1) * (P + 1), NQ = NL;
-  T u[NL], pv[NQ], px[NQ], py[NQ];
-  gather(0, u);
-  interp_vg<P, T>(B, u, pv, px, py);
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    pv[q] = c1[q] * pv[q];
-    px[q] = gcell * px[q];
-    py[q] = gcell * py[q];
-  }
-  integrate_w<P, T>(B, pv, px, py, out);
+  level_cell_phi<P, T>(B, gcell, c1, [&](int, T(&u)[NL]) { gather(2, u); }, out[2]);
 }
 
 // One cell of the transposed Jacobian, in the reference units of
