@@ -1,13 +1,17 @@
 // Coarse-level solve in one kernel (Sec. 3.2: the level-0 solve of the
-// V-cycle). One workgroup holds the level's operand, accumulator, state and
-// iteration vectors in LDS and runs every step of the fixed-length solve:
-// Chebyshev from x = 0 over [lambda_min, upper_factor * lambda_max], or
-// Jacobi-preconditioned CG from x = 0 with per-block scalars. Each thread
-// evaluates one level-0 cell with the same cell routines as the tile kernels
-// (its state coefficients once, kept in registers for every step) and adds it
-// into the accumulator in colour phases (cells of one colour share no node),
-// so the summation order is fixed. Replaces 2-3 launches per
-// step (tile kernel, shared-node fix-up, CG scalars) by one launch.
+// V-cycle). The block operator is block diagonal, so its two blocks are
+// solved by two workgroups at once (blockIdx.x 0: the displacement rows,
+// 1: the phase-field rows). Each holds the level's operand, accumulator, state
+// and iteration vectors in LDS and runs every step of the fixed-length solve
+// of its block: Chebyshev from x = 0 over [lambda_min, upper_factor *
+// lambda_max], or Jacobi-preconditioned CG from x = 0 with the block's
+// scalars. Each thread evaluates its block's rows of one level-0 cell with
+// the cell routines of the tile kernels (the state coefficients once, kept in
+// registers for every step) and adds them into the accumulator in colour
+// phases (cells of one colour share no node), so the summation order is
+// fixed; unknown i belongs to thread i mod COARSE_THREADS in both blocks.
+// Replaces 2-3 launches per step (tile kernel, shared-node fix-up, CG
+// scalars) by one launch.
 #pragma once
 
 #include "tile_kernel.hpp"
@@ -67,6 +71,9 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[2 * (COARSE_THREADS / 64)];
   const int n0 = a.n0, N = 3 * n0, tid = int(threadIdx.x);
+  const int blk = int(blockIdx.x);                    // 0: u_x, u_y rows; 1: phi rows
+  const int r0 = blk == 0 ? 0 : 2 * n0, r1 = blk == 0 ? 2 * n0 : N;
+  const int c0 = blk == 0 ? 0 : 2, c1e = blk == 0 ? 2 : 3;   // components [c0, c1e)
   double* xo = reinterpret_cast<double*>(smem_raw);   // operand of A: x (Chebyshev) or p (CG)
   double* acc = xo + N;                               // A * operand
   double* st = acc + N;                               // state
@@ -93,38 +100,43 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
     for (int k = 0; k < NL; ++k) u[k] = T(xo[f * n0 + nodes[k]]);
   };
   __syncthreads();
-  // the state enters every step only through these coefficients
-  T cg[NL], cc1[NL];
+  // the state enters every step only through the block's coefficients (g
+  // for the displacement rows, H^2 c1 for the phase-field rows)
+  T cf[NL];
 #pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    cg[k] = T(0);
-    cc1[k] = T(0);
-  }
+  for (int k = 0; k < NL; ++k) cf[k] = T(0);
   if (live) {
     auto gather_state = [&](int f, T(&u)[NL]) {
 #pragma unroll
       for (int k = 0; k < NL; ++k) u[k] = T(st[f * n0 + nodes[k]]);
     };
+    T cg[NL], cc1[NL];
     level_coefs<P, T>(a.B, a.H, mu, lam, kap, pr, Gc, ell, gather_state, cg, cc1);
-  }
-  // acc = A xo (level block operator, held columns of xo are zero)
-  auto apply = [&]() {
-    for (int i = tid; i < N; i += COARSE_THREADS) acc[i] = 0.0;
-    __syncthreads();
-    T out[3][NL];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < NL; ++k) cf[k] = blk == 0 ? cg[k] : cc1[k];
+  }
+  // acc = A xo on the block's rows (held columns of xo are zero)
+  auto apply = [&]() {
+    for (int i = r0 + tid; i < r1; i += COARSE_THREADS) acc[i] = 0.0;
+    __syncthreads();
+    T out[2][NL];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int k = 0; k < NL; ++k) out[c][k] = T(0);
-    if (live) level_cell<P, T>(a.B, mu, lam, Gc * ell, cg, cc1, gather, out);
+    if (live) {
+      if (blk == 0) level_cell_u<P, T>(a.B, mu, lam, cf, gather, out[0], out[1]);
+      else level_cell_phi<P, T>(a.B, Gc * ell, cf, [&](int, T(&u)[NL]) { gather(2, u); }, out[0]);
+    }
     for (int col = 0; col < a.ncolor; ++col) {
       if (color == col) {
 #pragma unroll
         for (int k = 0; k < NL; ++k)
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-            __hip_atomic_fetch_add(&acc[c * n0 + nodes[k]], double(out[c][k]), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+          for (int c = 0; c < 2; ++c)
+            if (c0 + c < c1e)
+              __hip_atomic_fetch_add(&acc[(c0 + c) * n0 + nodes[k]], double(out[c][k]), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       __syncthreads();
     }
@@ -142,8 +154,8 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
       bi[k] = T(0);
       di[k] = T(0);
       held[k] = true;
-      if (i < N) {
-        const int c = i / n0, blk = c < 2 ? 0 : 1;
+      if (i >= r0 && i < r1) {
+        const int c = i / n0;
         const uint8_t f = a.flags[i - c * n0];
         bi[k] = a.b[i];
         di[k] = a.dinv[i];
@@ -159,8 +171,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
 #pragma unroll
       for (int k = 0; k < COARSE_PER_THREAD; ++k) {
         const int i = tid + k * COARSE_THREADS;
-        if (i < N) {
-          const int blk = i < 2 * n0 ? 0 : 1;
+        if (i >= r0 && i < r1) {
           if (held[k]) {
             v1[i] = 0.0;
           } else {
@@ -173,7 +184,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
       }
       __syncthreads();
     }
-    for (int i = tid; i < N; i += COARSE_THREADS) a.x[i] = T(xo[i]);
+    for (int i = r0 + tid; i < r1; i += COARSE_THREADS) a.x[i] = T(xo[i]);
     return;
   }
 
@@ -187,7 +198,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
   for (int k = 0; k < COARSE_PER_THREAD; ++k) {
     const int i = tid + k * COARSE_THREADS;
     di[k] = T(0);
-    if (i < N) {
+    if (i >= r0 && i < r1) {
       di[k] = a.dinv[i];
       const T ri = di[k] != T(0) ? a.b[i] : T(0);
       v2[i] = 0.0;
@@ -205,7 +216,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
 #pragma unroll
     for (int k = 0; k < COARSE_PER_THREAD; ++k) {
       const int i = tid + k * COARSE_THREADS;
-      if (i < N) {
+      if (i >= r0 && i < r1) {
         const double c = di[k] != T(0) ? double(T(xo[i])) * double(T(acc[i])) : 0.0;
         if (i < 2 * n0) pq0 += c; else pq1 += c;
       }
@@ -216,8 +227,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
 #pragma unroll
     for (int k = 0; k < COARSE_PER_THREAD; ++k) {
       const int i = tid + k * COARSE_THREADS;
-      if (i < N) {
-        const int blk = i < 2 * n0 ? 0 : 1;
+      if (i >= r0 && i < r1) {
         const T qi = di[k] != T(0) ? T(acc[i]) : T(0);
         const T al = T(alpha[blk]);
         v2[i] = double(T(v2[i]) + al * T(xo[i]));
@@ -232,8 +242,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
 #pragma unroll
     for (int k = 0; k < COARSE_PER_THREAD; ++k) {
       const int i = tid + k * COARSE_THREADS;
-      if (i < N) {
-        const int blk = i < 2 * n0 ? 0 : 1;
+      if (i >= r0 && i < r1) {
         xo[i] = double(di[k] * T(v1[i]) + T(beta[blk]) * T(xo[i]));
       }
     }
@@ -241,7 +250,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
     rz[1] = rn1;
     __syncthreads();
   }
-  for (int i = tid; i < N; i += COARSE_THREADS) a.x[i] = T(v2[i]);
+  for (int i = r0 + tid; i < r1; i += COARSE_THREADS) a.x[i] = T(v2[i]);
 }
 
 }  // namespace pff

@@ -820,9 +820,9 @@ struct pff_ctx {
                              : reinterpret_cast<const void*>(&coarse_kernel<2, T>);
     if (lds > size_t(64 * 1024)) HIPCHK(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     if (p == 1)
-      hipLaunchKernelGGL((coarse_kernel<1, T>), dim3(1), dim3(COARSE_THREADS), lds, s, a);
+      hipLaunchKernelGGL((coarse_kernel<1, T>), dim3(2), dim3(COARSE_THREADS), lds, s, a);
     else
-      hipLaunchKernelGGL((coarse_kernel<2, T>), dim3(1), dim3(COARSE_THREADS), lds, s, a);
+      hipLaunchKernelGGL((coarse_kernel<2, T>), dim3(2), dim3(COARSE_THREADS), lds, s, a);
     HIPCHK(hipGetLastError());
     return 0;
   }

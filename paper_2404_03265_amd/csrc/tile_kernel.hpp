@@ -308,31 +308,38 @@ __device__ __forceinline__ void level_cell_phi(const Basis<T>& B, T gcell, const
 // One cell of the level block operator diag(G_uu, G_phiphi) (Sec. 3.2) from
 // its state coefficients (level_coefs); gather(f, u), f = 0..2, fetches the
 // operand. The same arithmetic as jacobian_cell without the coupling.
+// level_cell_u: the displacement rows (ox, oy) from g.
+template <int P, typename T, class Gather>
+__device__ __forceinline__ void level_cell_u(const Basis<T>& B, T mu, T lam, const T (&g)[(P + 1) * (P + 1)],
+                                             Gather&& gather, T (&ox)[(P + 1) * (P + 1)],
+                                             T (&oy)[(P + 1) * (P + 1)]) {
+  constexpr int NL = (P + 1) * (P + 1), NQ = NL;
+  T u[NL], dxx[NQ], dxy[NQ], dyx[NQ], dyy[NQ];
+  gather(0, u);
+  interp_g<P, T>(B, u, dxx, dxy);
+  gather(1, u);
+  interp_g<P, T>(B, u, dyx, dyy);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const T gq = g[q];
+    const T exx = dxx[q], eyy = dyy[q], exy2 = dxy[q] + dyx[q];
+    const T tr = exx + eyy;
+    const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = mu * exy2;
+    dxx[q] = gq * sxx;
+    dxy[q] = gq * sxy;
+    dyx[q] = gq * sxy;
+    dyy[q] = gq * syy;
+  }
+  integrate_gw<P, T>(B, dxx, dxy, ox);
+  integrate_gw<P, T>(B, dyx, dyy, oy);
+}
+
 template <int P, typename T, class Gather>
 __device__ __forceinline__ void level_cell(const Basis<T>& B, T mu, T lam, T gcell, const T (&g)[(P + 1) * (P + 1)],
                                            const T (&c1)[(P + 1) * (P + 1)], Gather&& gather,
                                            T (&out)[3][(P + 1) * (P + 1)]) {
-  constexpr int NL = (P + 1) * (P + 1), NQ = NL;
-  {
-    T u[NL], dxx[NQ], dxy[NQ], dyx[NQ], dyy[NQ];
-    gather(0, u);
-    interp_g<P, T>(B, u, dxx, dxy);
-    gather(1, u);
-    interp_g<P, T>(B, u, dyx, dyy);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const T gq = g[q];
-      const T exx = dxx[q], eyy = dyy[q], exy2 = dxy[q] + dyx[q];
-      const T tr = exx + eyy;
-      const T sxx = T(2) * mu * exx + lam * tr, syy = T(2) * mu * eyy + lam * tr, sxy = mu * exy2;
-      dxx[q] = gq * sxx;
-      dxy[q] = gq * sxy;
-      dyx[q] = gq * sxy;
-      dyy[q] = gq * syy;
-    }
-    integrate_gw<P, T>(B, dxx, dxy, out[0]);
-    integrate_gw<P, T>(B, dyx, dyy, out[1]);
-  }
+  constexpr int NL = (P + 1) * (P + 1);
+  level_cell_u<P, T>(B, mu, lam, g, gather, out[0], out[1]);
   level_cell_phi<P, T>(B, gcell, c1, [&](int, T(&u)[NL]) { gather(2, u); }, out[2]);
 }
 
