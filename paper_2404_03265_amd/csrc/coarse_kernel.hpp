@@ -39,7 +39,6 @@ struct CoarseArgs {
   const T* dinv;                         // [3][n0] inverse diagonal (0 on held rows)
   T* x;                                  // [3][n0] result
   T H;                                   // cell edge on level 0
-  Basis<T> B;
   Material mat;
   T c1[COARSE_MAX_STEPS][2], c2[COARSE_MAX_STEPS][2];   // Chebyshev coefficients per step and block
 };
@@ -111,7 +110,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
       for (int k = 0; k < NL; ++k) u[k] = T(st[f * n0 + nodes[k]]);
     };
     T cg[NL], cc1[NL];
-    level_coefs<P, T>(a.B, a.H, mu, lam, kap, pr, Gc, ell, gather_state, cg, cc1);
+    level_coefs<P, T>(a.H, mu, lam, kap, pr, Gc, ell, gather_state, cg, cc1);
 #pragma unroll
     for (int k = 0; k < NL; ++k) cf[k] = blk == 0 ? cg[k] : cc1[k];
   }
@@ -125,8 +124,8 @@ __global__ void __launch_bounds__(COARSE_THREADS) coarse_kernel(const CoarseArgs
 #pragma unroll
       for (int k = 0; k < NL; ++k) out[c][k] = T(0);
     if (live) {
-      if (blk == 0) level_cell_u<P, T>(a.B, mu, lam, cf, gather, out[0], out[1]);
-      else level_cell_phi<P, T>(a.B, Gc * ell, cf, [&](int, T(&u)[NL]) { gather(2, u); }, out[0]);
+      if (blk == 0) level_cell_u<P, T>(mu, lam, cf, gather, out[0], out[1]);
+      else level_cell_phi<P, T>(Gc * ell, cf, [&](int, T(&u)[NL]) { gather(2, u); }, out[0]);
     }
     for (int col = 0; col < a.ncolor; ++col) {
       if (color == col) {

@@ -60,6 +60,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_cod_partial(const TileArgs<doub
 #pragma unroll
   for (int j = 0; j < K; ++j) acc[j] = 0.0;
   const int cell = int(threadIdx.x);
+  constexpr Basis<double> BC = basis_table<P, double>();
   if (cell < nc) {
     const int64_t rec = int64_t(c0) + cell;
     const unsigned info = a.cell_info[rec];
@@ -78,9 +79,9 @@ __global__ void __launch_bounds__(RED_THREADS) k_cod_partial(const TileArgs<doub
       ph[k] = U[2 * n + g];
     }
     if (info & 15u) {
-      hang_apply<P, double>(a.B, ux, info);
-      hang_apply<P, double>(a.B, uy, info);
-      hang_apply<P, double>(a.B, ph, info);
+      hang_apply<P, double>(ux, info);
+      hang_apply<P, double>(uy, info);
+      hang_apply<P, double>(ph, info);
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -106,12 +107,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_cod_partial(const TileArgs<doub
             rs += ph[k] * ds[a2];
             rv += ph[k] * vs[a2];
           }
-          fx += a.B.v[q][b] * rx;
-          fy += a.B.v[q][b] * ry;
-          fs += a.B.v[q][b] * rs;
-          ft += a.B.d[q][b] * rv;
+          fx += BC.v[q][b] * rx;
+          fy += BC.v[q][b] * ry;
+          fs += BC.v[q][b] * rs;
+          ft += BC.d[q][b] * rv;
         }
-        sum += a.B.w[q] * (fx * fs + fy * ft);
+        sum += BC.w[q] * (fx * fs + fy * ft);
       }
       acc[j] += sum;
     }

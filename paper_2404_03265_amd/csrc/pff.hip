@@ -98,49 +98,6 @@ struct DevLevel {
 };
 
 template <typename T>
-Basis<T> make_basis(int p) {
-  Basis<T> B{};
-  const int N = p + 1;
-  double g[3], w[3];
-  if (p == 1) {
-    const double s = 0.5 / std::sqrt(3.0);
-    g[0] = 0.5 - s; g[1] = 0.5 + s; w[0] = w[1] = 0.5;
-  } else {
-    const double s = 0.5 * std::sqrt(0.6);
-    g[0] = 0.5 - s; g[1] = 0.5; g[2] = 0.5 + s;
-    w[0] = w[2] = 5.0 / 18.0; w[1] = 8.0 / 18.0;
-  }
-  auto lag = [&](int k, double t) {
-    double v = 1.0;
-    for (int m = 0; m < N; ++m) if (m != k) v *= (t - double(m) / p) / (double(k - m) / p);
-    return v;
-  };
-  auto dlag = [&](int k, double t) {
-    double s = 0.0;
-    for (int r = 0; r < N; ++r) {
-      if (r == k) continue;
-      double v = 1.0 / (double(k - r) / p);
-      for (int m = 0; m < N; ++m) if (m != k && m != r) v *= (t - double(m) / p) / (double(k - m) / p);
-      s += v;
-    }
-    return s;
-  };
-  for (int q = 0; q < N; ++q) {
-    B.w[q] = T(w[q]);
-    for (int a = 0; a < N; ++a) {
-      B.v[q][a] = T(lag(a, g[q]));
-      B.d[q][a] = T(dlag(a, g[q]));
-      B.vw[q][a] = T(w[q] * lag(a, g[q]));
-      B.dw[q][a] = T(w[q] * dlag(a, g[q]));
-    }
-  }
-  for (int sub = 0; sub < 2; ++sub)
-    for (int t = 0; t < N; ++t)
-      for (int k = 0; k < N; ++k) B.hang[sub][t][k] = T(lag(k, (sub + double(t) / p) / 2.0));
-  return B;
-}
-
-template <typename T>
 T* dalloc(int64_t count) {
   if (count <= 0) count = 1;
   void* p = nullptr;
@@ -407,7 +364,6 @@ struct pff_ctx {
     a.sh_tab = t.sh_tab;
     a.sh_w = t.sh_w;
     a.H0 = T(mesh.level_H[0]);
-    a.B = make_basis<T>(p);
     a.mat = mat();
   }
 
@@ -794,7 +750,6 @@ struct pff_ctx {
     a.dinv = w.dinv;
     a.x = w.x[0];
     a.H = T(mesh.level_H[0]);
-    a.B = make_basis<T>(p);
     a.mat = mat();
     if (!a.cg) {
       // the coefficients of chebyshev(0, b, start from zero, coarse_its)
@@ -1480,6 +1435,12 @@ int pff_create(const pff_mesh_spec* spec, const pff_params* params, pff_ctx** ou
     for (const Level& L : c->mesh.levels) too_big = too_big || L.tiles.max_local > 65535;
     for (const GcLevel& G : c->mesh.gc) too_big = too_big || G.tiles.max_local > 65535;
     if (too_big) return create_failed(nullptr, PFF_E_MESH, "pff_create: a tile has more than 65535 local nodes");
+    // the tile kernels address node arrays and partial sums with 32-bit byte
+    // offsets per component (8-byte elements)
+    bool too_many = c->mesh.n_nodes >= (int64_t(1) << 29) || c->mesh.tiles.n_slots >= (int64_t(1) << 29);
+    for (const GcLevel& G : c->mesh.gc) too_many = too_many || G.tiles.n_slots >= (int64_t(1) << 29);
+    for (const Level& L : c->mesh.levels) too_many = too_many || L.tiles.n_slots >= (int64_t(1) << 29);
+    if (too_many) return create_failed(nullptr, PFF_E_MESH, "pff_create: more than 2^29 nodes or partial-sum slots");
     c->prm = *params;
     c->p = ms.degree;
     c->n = c->mesh.n_nodes;

@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(256) tile_kernel_jt_batch(const TileArgs<doubl
 #pragma unroll
         for (int k = 0; k < NL; ++k) u[k] = base[loc[k]];
       };
-      jacobian_t_cell<P, T>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
+      jacobian_t_cell<P, T>(H, mu, lam, kap, pr, Gc, ell, gather, out);
     }
     __syncthreads();   // every gather done: the operand arrays become the accumulators
     for (int l = tid; l < nloc; l += bs) {

@@ -72,7 +72,6 @@ struct TileArgs {
   const int32_t* sh_tab;
   int sh_w;
   T H0;             // cell edge on level 0; level l has H0 / 2^l
-  Basis<T> B;
   Material mat;
   const T* src;      // 3n input (operand / state U)
   const T* st[4];    // state fields: leaf (ux, uy, phi, phit); level (ux, uy, phit: inverse diagonal, coefficients)
@@ -90,6 +89,20 @@ struct TileArgs {
   T* coef;
   int64_t n_coef;
 };
+
+// Element i of a device array addressed as a uniform base plus a 32-bit
+// byte offset (the scalar-base form of the global loads and stores): one
+// 32-bit register per node serves every field of the node, where a 64-bit
+// address per load would hold two. Arrays of at most 2^29 elements of 8
+// bytes (the host checks the node count).
+template <typename T>
+__device__ __forceinline__ const T& at32(const T* base, uint32_t i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + uint64_t(i * uint32_t(sizeof(T))));
+}
+template <typename T>
+__device__ __forceinline__ T& at32(T* base, uint32_t i) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + uint64_t(i * uint32_t(sizeof(T))));
+}
 
 template <int MODE>
 struct ModeTraits {
@@ -166,7 +179,7 @@ __device__ __forceinline__ void node_epilogue(const TileArgs<T>& a, int c, int64
 // field f (0..2 the operand, then the state fields: u_x, u_y, phi, phit), out
 // receives the cell's contributions to its nodes.
 template <int P, typename T, class Gather>
-__device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T lam, T kap, T pr, T Gc, T ell,
+__device__ __forceinline__ void jacobian_cell(T H, T mu, T lam, T kap, T pr, T Gc, T ell,
                                               Gather&& gather, T (&out)[3][(P + 1) * (P + 1)]) {
   constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
   // Jacobian (Sec. 3.1) in reference units (gradients of the unit square,
@@ -184,9 +197,9 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
   {
     T u[NL], sx1[NQ], sy1[NQ], sx2[NQ], sy2[NQ];
     gather(FUX, u);
-    interp_g<P, T>(B, u, sx1, sy1);
+    interp_g<P, T>(u, sx1, sy1);
     gather(FUY, u);
-    interp_g<P, T>(B, u, sx2, sy2);
+    interp_g<P, T>(u, sx2, sy2);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const T exx = sx1[q], eyy = sy2[q], exy = T(0.5) * (sy1[q] + sx2[q]);
@@ -202,7 +215,7 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
   {
     T u[NL], pq[NQ];
     gather(FPHI, u);
-    interp_v<P, T>(B, u, pq);
+    interp_v<P, T>(u, pq);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const T f = T(2) * (T(1) - kap) * pq[q], t = twopH * pq[q];
@@ -215,16 +228,16 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
   {
     T u[NL];
     gather(0, u);
-    interp_g<P, T>(B, u, dxx, dxy);
+    interp_g<P, T>(u, dxx, dxy);
     gather(1, u);
-    interp_g<P, T>(B, u, dyx, dyy);
+    interp_g<P, T>(u, dyx, dyy);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) be[q] = bxx[q] * dxx[q] + byy[q] * dyy[q] + bxy[q] * (dxy[q] + dyx[q]);
   }
   {
     T u[NL], tq[NQ];
     gather(FPT, u);
-    interp_v<P, T>(B, u, tq);
+    interp_v<P, T>(u, tq);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const T gq = (T(1) - kap) * tq[q] * tq[q] + kap;
@@ -237,19 +250,19 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
       dyy[q] = gq * syy;
     }
   }
-  integrate_gw<P, T>(B, dxx, dxy, out[0]);
-  integrate_gw<P, T>(B, dyx, dyy, out[1]);
+  integrate_gw<P, T>(dxx, dxy, out[0]);
+  integrate_gw<P, T>(dyx, dyy, out[1]);
   {
     T u[NL], pv[NQ], px[NQ], py[NQ];
     gather(2, u);
-    interp_vg<P, T>(B, u, pv, px, py);
+    interp_vg<P, T>(u, pv, px, py);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       pv[q] = c1[q] * pv[q] + be[q];
       px[q] = gcell * px[q];
       py[q] = gcell * py[q];
     }
-    integrate_w<P, T>(B, pv, px, py, out[2]);
+    integrate_w<P, T>(pv, px, py, out[2]);
   }
 }
 
@@ -260,7 +273,7 @@ __device__ __forceinline__ void jacobian_cell(const Basis<T>& B, T H, T mu, T la
 // The level state is fixed for a multigrid set-up, so they are evaluated
 // once per set-up (MODE_LEVEL_COEF) rather than in every application.
 template <int P, typename T, class Gather>
-__device__ __forceinline__ void level_coefs(const Basis<T>& B, T H, T mu, T lam, T kap, T pr, T Gc, T ell,
+__device__ __forceinline__ void level_coefs(T H, T mu, T lam, T kap, T pr, T Gc, T ell,
                                             Gather&& gather, T (&g)[(P + 1) * (P + 1)],
                                             T (&c1)[(P + 1) * (P + 1)]) {
   constexpr int NL = (P + 1) * (P + 1), NQ = NL;
@@ -268,9 +281,9 @@ __device__ __forceinline__ void level_coefs(const Basis<T>& B, T H, T mu, T lam,
   {
     T u[NL], sx1[NQ], sy1[NQ], sx2[NQ], sy2[NQ];
     gather(0, u);
-    interp_g<P, T>(B, u, sx1, sy1);
+    interp_g<P, T>(u, sx1, sy1);
     gather(1, u);
-    interp_g<P, T>(B, u, sx2, sy2);
+    interp_g<P, T>(u, sx2, sy2);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const T exx = sx1[q], eyy = sy2[q], exy = T(0.5) * (sy1[q] + sx2[q]);
@@ -282,7 +295,7 @@ __device__ __forceinline__ void level_coefs(const Basis<T>& B, T H, T mu, T lam,
   }
   T u[NL], tq[NQ];
   gather(2, u);
-  interp_v<P, T>(B, u, tq);
+  interp_v<P, T>(u, tq);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) g[q] = (T(1) - kap) * tq[q] * tq[q] + kap;
 }
@@ -290,19 +303,19 @@ __device__ __forceinline__ void level_coefs(const Basis<T>& B, T H, T mu, T lam,
 // The phase-field rows of the level block operator (level_cell): gather(0, u)
 // fetches the phase-field operand, c1 holds H^2 c1 at the Gauss points.
 template <int P, typename T, class Gather>
-__device__ __forceinline__ void level_cell_phi(const Basis<T>& B, T gcell, const T (&c1)[(P + 1) * (P + 1)],
+__device__ __forceinline__ void level_cell_phi(T gcell, const T (&c1)[(P + 1) * (P + 1)],
                                                Gather&& gather, T (&out)[(P + 1) * (P + 1)]) {
   constexpr int NL = (P + 1) * (P + 1), NQ = NL;
   T u[NL], pv[NQ], px[NQ], py[NQ];
   gather(0, u);
-  interp_vg<P, T>(B, u, pv, px, py);
+  interp_vg<P, T>(u, pv, px, py);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     pv[q] = c1[q] * pv[q];
     px[q] = gcell * px[q];
     py[q] = gcell * py[q];
   }
-  integrate_w<P, T>(B, pv, px, py, out);
+  integrate_w<P, T>(pv, px, py, out);
 }
 
 // One cell of the level block operator diag(G_uu, G_phiphi) (Sec. 3.2) from
@@ -310,15 +323,15 @@ __device__ __forceinline__ void level_cell_phi(const Basis<T>& B, T gcell, const
 // operand. The same arithmetic as jacobian_cell without the coupling.
 // level_cell_u: the displacement rows (ox, oy) from g.
 template <int P, typename T, class Gather>
-__device__ __forceinline__ void level_cell_u(const Basis<T>& B, T mu, T lam, const T (&g)[(P + 1) * (P + 1)],
+__device__ __forceinline__ void level_cell_u(T mu, T lam, const T (&g)[(P + 1) * (P + 1)],
                                              Gather&& gather, T (&ox)[(P + 1) * (P + 1)],
                                              T (&oy)[(P + 1) * (P + 1)]) {
   constexpr int NL = (P + 1) * (P + 1), NQ = NL;
   T u[NL], dxx[NQ], dxy[NQ], dyx[NQ], dyy[NQ];
   gather(0, u);
-  interp_g<P, T>(B, u, dxx, dxy);
+  interp_g<P, T>(u, dxx, dxy);
   gather(1, u);
-  interp_g<P, T>(B, u, dyx, dyy);
+  interp_g<P, T>(u, dyx, dyy);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const T gq = g[q];
@@ -330,17 +343,17 @@ __device__ __forceinline__ void level_cell_u(const Basis<T>& B, T mu, T lam, con
     dyx[q] = gq * sxy;
     dyy[q] = gq * syy;
   }
-  integrate_gw<P, T>(B, dxx, dxy, ox);
-  integrate_gw<P, T>(B, dyx, dyy, oy);
+  integrate_gw<P, T>(dxx, dxy, ox);
+  integrate_gw<P, T>(dyx, dyy, oy);
 }
 
 template <int P, typename T, class Gather>
-__device__ __forceinline__ void level_cell(const Basis<T>& B, T mu, T lam, T gcell, const T (&g)[(P + 1) * (P + 1)],
+__device__ __forceinline__ void level_cell(T mu, T lam, T gcell, const T (&g)[(P + 1) * (P + 1)],
                                            const T (&c1)[(P + 1) * (P + 1)], Gather&& gather,
                                            T (&out)[3][(P + 1) * (P + 1)]) {
   constexpr int NL = (P + 1) * (P + 1);
-  level_cell_u<P, T>(B, mu, lam, g, gather, out[0], out[1]);
-  level_cell_phi<P, T>(B, gcell, c1, [&](int, T(&u)[NL]) { gather(2, u); }, out[2]);
+  level_cell_u<P, T>(mu, lam, g, gather, out[0], out[1]);
+  level_cell_phi<P, T>(gcell, c1, [&](int, T(&u)[NL]) { gather(2, u); }, out[2]);
 }
 
 // One cell of the transposed Jacobian, in the reference units of
@@ -352,7 +365,7 @@ __device__ __forceinline__ void level_cell(const Basis<T>& B, T mu, T lam, T gce
 // few values live: state coefficients, then the phase-field rows (whose
 // operand scales H B in place), then the displacement rows.
 template <int P, typename T, class Gather>
-__device__ __forceinline__ void jacobian_t_cell(const Basis<T>& B, T H, T mu, T lam, T kap, T pr, T Gc, T ell,
+__device__ __forceinline__ void jacobian_t_cell(T H, T mu, T lam, T kap, T pr, T Gc, T ell,
                                                 Gather&& gather, T (&out)[3][(P + 1) * (P + 1)]) {
   constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
   constexpr int FUX = 3, FUY = 4, FPHI = 5, FPT = 6;
@@ -363,9 +376,9 @@ __device__ __forceinline__ void jacobian_t_cell(const Basis<T>& B, T H, T mu, T 
     {
       T u[NL], sx1[NQ], sy1[NQ], sx2[NQ], sy2[NQ];
       gather(FUX, u);
-      interp_g<P, T>(B, u, sx1, sy1);
+      interp_g<P, T>(u, sx1, sy1);
       gather(FUY, u);
-      interp_g<P, T>(B, u, sx2, sy2);
+      interp_g<P, T>(u, sx2, sy2);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const T exx = sx1[q], eyy = sy2[q], exy = T(0.5) * (sy1[q] + sx2[q]);
@@ -381,7 +394,7 @@ __device__ __forceinline__ void jacobian_t_cell(const Basis<T>& B, T H, T mu, T 
     {
       T u[NL], pq[NQ];
       gather(FPHI, u);
-      interp_v<P, T>(B, u, pq);
+      interp_v<P, T>(u, pq);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const T f = T(2) * (T(1) - kap) * pq[q], t = twopH * pq[q];
@@ -393,7 +406,7 @@ __device__ __forceinline__ void jacobian_t_cell(const Basis<T>& B, T H, T mu, T 
     // phi rows; the operand dphi then scales H B for the u rows
     T u[NL], pv[NQ], px[NQ], py[NQ];
     gather(2, u);
-    interp_vg<P, T>(B, u, pv, px, py);
+    interp_vg<P, T>(u, pv, px, py);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       bxx[q] *= pv[q];
@@ -403,20 +416,20 @@ __device__ __forceinline__ void jacobian_t_cell(const Basis<T>& B, T H, T mu, T 
       px[q] = gcell * px[q];
       py[q] = gcell * py[q];
     }
-    integrate_w<P, T>(B, pv, px, py, out[2]);
+    integrate_w<P, T>(pv, px, py, out[2]);
   }
   T dxx[NQ], dxy[NQ], dyx[NQ], dyy[NQ];
   {
     T u[NL];
     gather(0, u);
-    interp_g<P, T>(B, u, dxx, dxy);
+    interp_g<P, T>(u, dxx, dxy);
     gather(1, u);
-    interp_g<P, T>(B, u, dyx, dyy);
+    interp_g<P, T>(u, dyx, dyy);
   }
   {
     T u[NL], tq[NQ];
     gather(FPT, u);
-    interp_v<P, T>(B, u, tq);
+    interp_v<P, T>(u, tq);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const T gq = (T(1) - kap) * tq[q] * tq[q] + kap;
@@ -429,8 +442,8 @@ __device__ __forceinline__ void jacobian_t_cell(const Basis<T>& B, T H, T mu, T 
       dyy[q] = gq * syy + byy[q];
     }
   }
-  integrate_gw<P, T>(B, dxx, dxy, out[0]);
-  integrate_gw<P, T>(B, dyx, dyy, out[1]);
+  integrate_gw<P, T>(dxx, dxy, out[0]);
+  integrate_gw<P, T>(dyx, dyy, out[1]);
 }
 
 // One cell of an operator mode: gather(f, u) fetches the cell's nodal values
@@ -447,17 +460,18 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
   const T mu = T(m.mu), lam = T(m.lam);
   (void)info;
   (void)hang;
+  constexpr Basis<T> BW = basis_table<P, T>();
   T wq[NQ];
 #pragma unroll
   for (int qy = 0; qy < N1; ++qy)
 #pragma unroll
-    for (int qx = 0; qx < N1; ++qx) wq[qy * N1 + qx] = a.B.w[qx] * a.B.w[qy];
+    for (int qx = 0; qx < N1; ++qx) wq[qy * N1 + qx] = BW.w[qx] * BW.w[qy];
   const T invH = T(1) / H;
 
   if constexpr (MODE == MODE_J) {
-    jacobian_cell<P, T>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
+    jacobian_cell<P, T>(H, mu, lam, kap, pr, Gc, ell, gather, out);
   } else if constexpr (MODE == MODE_JT) {
-    jacobian_t_cell<P, T>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, out);
+    jacobian_t_cell<P, T>(H, mu, lam, kap, pr, Gc, ell, gather, out);
   } else if constexpr (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL) {
     // state-derived coefficients at the Gauss points:
     //   g = (1-k) phit^2 + k, c1 = (1-k) S + 2 p tr e(u) + Gc/l
@@ -468,11 +482,11 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
     {
       T u[NL], gx1[NQ], gy1[NQ], gx2[NQ], gy2[NQ], tq[NQ];
       gather(SU + 0, u);
-      interp_g<P, T>(a.B, u, gx1, gy1);
+      interp_g<P, T>(u, gx1, gy1);
       gather(SU + 1, u);
-      interp_g<P, T>(a.B, u, gx2, gy2);
+      interp_g<P, T>(u, gx2, gy2);
       gather(FPT, u);
-      interp_v<P, T>(a.B, u, tq);
+      interp_v<P, T>(u, tq);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const T exx = gx1[q] * invH, eyy = gy2[q] * invH, exy = T(0.5) * (gy1[q] + gx2[q]) * invH;
@@ -490,8 +504,8 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
       T u[NL], vq[NQ], gxq[NQ], gyq[NQ];
 #pragma unroll
       for (int j = 0; j < NL; ++j) u[j] = (j == k) ? T(1) : T(0);
-      if (hang) hang_apply<P, T>(a.B, u, info);
-      interp_vg<P, T>(a.B, u, vq, gxq, gyq);
+      if (hang) hang_apply<P, T>(u, info);
+      interp_vg<P, T>(u, vq, gxq, gyq);
       T dux = T(0), duy = T(0), dph = T(0);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -513,13 +527,13 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
     {
       T u[NL];
       gather(0, u);
-      interp_g<P, T>(a.B, u, gx1, gy1);
+      interp_g<P, T>(u, gx1, gy1);
       gather(1, u);
-      interp_g<P, T>(a.B, u, gx2, gy2);
+      interp_g<P, T>(u, gx2, gy2);
       gather(2, u);
-      interp_vg<P, T>(a.B, u, pv, px, py);
+      interp_vg<P, T>(u, pv, px, py);
       gather(3, u);
-      interp_v<P, T>(a.B, u, tq);
+      interp_v<P, T>(u, tq);
     }
     constexpr T sig = (MODE == MODE_RESID || MODE == MODE_DE) ? T(1) : T(0);
     const T spr = (MODE == MODE_RESID) ? pr : (MODE == MODE_DP ? T(1) : T(0));
@@ -543,20 +557,20 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
       px[q] = wq[q] * sgc * ell * px[q];
       py[q] = wq[q] * sgc * ell * py[q];
     }
-    integrate_g<P, T>(a.B, gx1, gy1, out[0]);
-    integrate_g<P, T>(a.B, gx2, gy2, out[1]);
-    integrate<P, T>(a.B, pv, px, py, out[2]);
+    integrate_g<P, T>(gx1, gy1, out[0]);
+    integrate_g<P, T>(gx2, gy2, out[1]);
+    integrate<P, T>(pv, px, py, out[2]);
   } else if constexpr (MODE == MODE_TCVGRAD) {
     // TCV = int u . grad phi; derivative: (v . grad phi) for u, (u . grad psi) for phi
     T vx[NQ], vy[NQ], px[NQ], py[NQ], zero[NQ];
     {
       T u[NL], d1[NQ], d2[NQ];
       gather(0, u);
-      interp_v<P, T>(a.B, u, vx);
+      interp_v<P, T>(u, vx);
       gather(1, u);
-      interp_v<P, T>(a.B, u, vy);
+      interp_v<P, T>(u, vy);
       gather(2, u);
-      interp_g<P, T>(a.B, u, px, py);
+      interp_g<P, T>(u, px, py);
       (void)d1;
       (void)d2;
     }
@@ -570,9 +584,9 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
       px[q] = wg * vx[q];
       py[q] = wg * vy[q];
     }
-    integrate<P, T>(a.B, f0, zero, zero, out[0]);
-    integrate<P, T>(a.B, f1, zero, zero, out[1]);
-    integrate<P, T>(a.B, zero, px, py, out[2]);
+    integrate<P, T>(f0, zero, zero, out[0]);
+    integrate<P, T>(f1, zero, zero, out[1]);
+    integrate<P, T>(zero, px, py, out[2]);
   } else if constexpr (MODE == MODE_MASS) {
     T f[NQ], zero[NQ];
 #pragma unroll
@@ -580,7 +594,7 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
       f[q] = H * H * wq[q];
       zero[q] = T(0);
     }
-    integrate<P, T>(a.B, f, zero, zero, out[2]);
+    integrate<P, T>(f, zero, zero, out[2]);
   }
 }
 
@@ -698,14 +712,14 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   if constexpr (LPRE) {
 #pragma unroll
     for (int k = 0; k < SP; ++k) {
-      const int64_t g = min(int64_t(o0) + min(k * bs + tid, max(no - 1, 0)), n - 1);
+      const uint32_t g = uint32_t(min(o0 + min(k * bs + tid, max(no - 1, 0)), int(n - 1)));
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        pb[k][c] = a.b[c * n + g];
+        pb[k][c] = at32(a.b + c * n, g);
         if constexpr (CHEB) {
-          pdi[k][c] = a.dinv[c * n + g];
+          pdi[k][c] = at32(a.dinv + c * n, g);
           if constexpr (FIRST) pdo[k][c] = a.c0[c < 2 ? 0 : 1] * pdi[k][c] * pb[k][c];
-          else pdo[k][c] = a.dold ? a.dold[c * n + g] : T(0);
+          else pdo[k][c] = a.dold ? at32(a.dold + c * n, g) : T(0);
         }
       }
     }
@@ -714,18 +728,19 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   for (int rp = 0, rs = 0; rp < no || rs < ns; rp += SP * bs, rs += SS * bs) {
     // shared ids before any load is in flight: with the list, the wait for
     // the ids then holds nothing else up
-    int64_t gsh[SS];
+    // (out-of-range entries read node 0 and are discarded)
+    uint32_t gsh[SS];
     if (nrun > 0) {
 #pragma unroll
       for (int k = 0; k < SS; ++k) {
         const int r = rs + k * bs + tid;
-        gsh[k] = r < ns ? run_id(r) : int64_t(-1);
+        gsh[k] = r < ns ? uint32_t(run_id(r)) : 0u;
       }
     } else {
 #pragma unroll
       for (int k = 0; k < SS; ++k) {
         const int r = rs + k * bs + tid;
-        gsh[k] = r < ns ? int64_t(a.shared[s0 + r]) : int64_t(-1);
+        gsh[k] = r < ns ? uint32_t(a.shared[s0 + r]) : 0u;
       }
     }
     // loads without branches (out-of-range lanes read an in-range node and
@@ -735,38 +750,38 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < SP; ++k) {
       const int l = rp + k * bs + tid;
-      const int64_t g = min(int64_t(o0) + min(l, max(no - 1, 0)), n - 1);
-      fp_[k] = a.flags[g];
+      const uint32_t g = uint32_t(min(o0 + min(l, max(no - 1, 0)), int(n - 1)));
+      fp_[k] = at32(a.flags, g);
       if constexpr (NF > 0) {
         if constexpr (FIRST) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) vp[k][c] = a.c0[c < 2 ? 0 : 1] * a.dinv[c * n + g] * a.b[c * n + g];
+          for (int c = 0; c < 3; ++c) vp[k][c] = a.c0[c < 2 ? 0 : 1] * at32(a.dinv + c * n, g) * at32(a.b + c * n, g);
         } else if constexpr (PHI) {
-          vp[k][0] = a.src[2 * n + g];
+          vp[k][0] = at32(a.src + 2 * n, g);
         } else if constexpr (TR::n_src > 0) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) vp[k][c] = a.src[c * n + g];
+          for (int c = 0; c < 3; ++c) vp[k][c] = at32(a.src + c * n, g);
         }
 #pragma unroll
-        for (int st = 0; st < TR::n_state; ++st) vp[k][TR::n_src + st] = a.st[st][g];
+        for (int st = 0; st < TR::n_state; ++st) vp[k][TR::n_src + st] = at32(a.st[st], g);
       }
     }
 #pragma unroll
     for (int k = 0; k < SS; ++k) {
-      const int64_t g = gsh[k] >= 0 ? gsh[k] : int64_t(0);
-      fsh[k] = a.flags[g];
+      const uint32_t g = gsh[k];
+      fsh[k] = at32(a.flags, g);
       if constexpr (NF > 0) {
         if constexpr (FIRST) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) vsh[k][c] = a.c0[c < 2 ? 0 : 1] * a.dinv[c * n + g] * a.b[c * n + g];
+          for (int c = 0; c < 3; ++c) vsh[k][c] = a.c0[c < 2 ? 0 : 1] * at32(a.dinv + c * n, g) * at32(a.b + c * n, g);
         } else if constexpr (PHI) {
-          vsh[k][0] = a.src[2 * n + g];
+          vsh[k][0] = at32(a.src + 2 * n, g);
         } else if constexpr (TR::n_src > 0) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) vsh[k][c] = a.src[c * n + g];
+          for (int c = 0; c < 3; ++c) vsh[k][c] = at32(a.src + c * n, g);
         }
 #pragma unroll
-        for (int st = 0; st < TR::n_state; ++st) vsh[k][TR::n_src + st] = a.st[st][g];
+        for (int st = 0; st < TR::n_state; ++st) vsh[k][TR::n_src + st] = at32(a.st[st], g);
       }
     }
     if (first) load_cell_record();
@@ -798,12 +813,12 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         }
         if constexpr (JMODE) {
           const uint8_t f = fp_[k];
-          const int64_t g = int64_t(o0) + l;
+          const uint32_t g = uint32_t(o0 + l);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             raw[k][c] = vp[k][c];
             const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
-            if (cons && !keep_raw) a.dst[c * n + g] = vp[k][c];
+            if (cons && !keep_raw) at32(a.dst + c * n, g) = vp[k][c];
           }
         }
       }
@@ -842,7 +857,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         for (int k = 0; k < NL; ++k) u[k] = T(lds[field * ML + loc[k]]);
       };
       T g[NQ], c1[NQ];
-      level_coefs<P, T>(a.B, H, mu, lam, kap, pr, Gc, ell, gather, g, c1);
+      level_coefs<P, T>(H, mu, lam, kap, pr, Gc, ell, gather, g, c1);
       const int64_t rec = int64_t(c0) + cell;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -870,13 +885,13 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       auto gather = [&](int field, T(&u)[NL]) {
 #pragma unroll
         for (int k = 0; k < NL; ++k) u[k] = T(lds[field * ML + loc[k]]);
-        if (hang) hang_apply<P, T>(a.B, u, info);
+        if (hang) hang_apply<P, T>(u, info);
       };
       if constexpr (PHI) {
         T c1[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) c1[q] = cf[q];
-        level_cell_phi<P, T>(a.B, Gc * ell, c1, gather, out[2]);
+        level_cell_phi<P, T>(Gc * ell, c1, gather, out[2]);
       } else if constexpr (MODE == MODE_LEVEL) {
         T g[NQ], c1[NQ];
 #pragma unroll
@@ -884,7 +899,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
           g[q] = cf[q];
           c1[q] = cf[NQ + q];
         }
-        level_cell<P, T>(a.B, mu, lam, Gc * ell, g, c1, gather, out);
+        level_cell<P, T>(mu, lam, Gc * ell, g, c1, gather, out);
       } else {
         compute_cell<P, T, MODE>(a, H, hang, info, gather, out);
       }
@@ -946,26 +961,26 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       const int l = k * int(blockDim.x) + int(threadIdx.x);
       if (l < no) {
         const uint8_t f = lflag[l];
-        const int64_t g = int64_t(o0) + l;
+        const uint32_t g = uint32_t(o0 + l);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const int64_t i = c * n + g;
+          T& di = at32(a.dst + c * n, g);
           const T v = T(acc[c * ML + l]);
           if constexpr (JMODE) {
             const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
-            a.dst[i] = cons ? raw[k][c] : v;
+            di = cons ? raw[k][c] : v;
           } else if constexpr (CHEB) {
             // the level smoother step, as in node_epilogue
             const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_EDGE | NODE_HANGING));
             const int blk = c < 2 ? 0 : 1;
             const T x = raw[k][c];
             const T dn = a.c1[blk] * pdo[k][c] + a.c2[blk] * pdi[k][c] * (pb[k][c] - v);
-            a.dst[i] = fixed ? T(0) : dn;
-            a.xnew[i] = fixed ? x : x + dn;
+            di = fixed ? T(0) : dn;
+            at32(a.xnew + c * n, g) = fixed ? x : x + dn;
           } else if constexpr (LPRE) {
             const bool held =
                 (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
-            a.dst[i] = held ? T(0) : pb[k][c] - v;
+            di = held ? T(0) : pb[k][c] - v;
           }
         }
       }
@@ -979,7 +994,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   }
   for (int r = threadIdx.x; r < ns; r += blockDim.x) {
 #pragma unroll
-    for (int c = C0; c < 3; ++c) a.part[c * a.n_slots + slot0 + r] = T(acc[c * ML + no + r]);
+    for (int c = C0; c < 3; ++c) at32(a.part + c * a.n_slots, uint32_t(slot0 + r)) = T(acc[c * ML + no + r]);
   }
 }
 
