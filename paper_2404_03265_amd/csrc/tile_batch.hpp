@@ -21,8 +21,11 @@ namespace pff {
 
 constexpr int JT_BATCH_MAX = 8;   // right-hand sides per launch
 
+// two waves per SIMD: left to itself the register allocator takes two
+// accumulation registers beyond 256 for Q2 and halves the occupancy
 template <int P>
-__global__ void __launch_bounds__(256) tile_kernel_jt_batch(const TileArgs<double> a, int nrhs) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+tile_kernel_jt_batch(const TileArgs<double> a, int nrhs) {
   using T = double;
   constexpr int N1 = P + 1, NL = N1 * N1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -57,17 +60,17 @@ __global__ void __launch_bounds__(256) tile_kernel_jt_batch(const TileArgs<doubl
   constexpr int KB = P == 1 ? 2 : 5;
   // global id of local node l: private range, then the shared list (from the
   // header's runs of consecutive ids, else the list)
-  auto node_id = [&](int l) -> int64_t {
-    if (l < no) return int64_t(o0) + l;
+  auto node_id = [&](int l) -> uint32_t {
+    if (l < no) return uint32_t(o0 + l);
     const int r = l - no;
     if (nrun > 0) {
       int id = ti[TILE_RUN_START] + r;
 #pragma unroll
       for (int k = 1; k < TILE_MAX_RUNS; ++k)
         if (k < nrun && r >= ti[TILE_RUN_OFF + k]) id = ti[TILE_RUN_START + k] + (r - ti[TILE_RUN_OFF + k]);
-      return id;
+      return uint32_t(id);
     }
-    return int64_t(a.shared[s0 + r]);
+    return uint32_t(a.shared[s0 + r]);
   };
   // values at hanging nodes from their masters, fields [f0, f0 + nf) of base
   auto interp_hanging = [&](T* base, int nf) {
@@ -82,16 +85,16 @@ __global__ void __launch_bounds__(256) tile_kernel_jt_batch(const TileArgs<doubl
 
   // 1. state and flags, once (every load of a round before its stores)
   for (int l0 = 0; l0 < nloc; l0 += KB * bs) {
-    int64_t g[KB];
+    uint32_t g[KB];
     uint8_t fl[KB];
     T v[KB][4];
 #pragma unroll
     for (int k = 0; k < KB; ++k) g[k] = node_id(min(l0 + k * bs + tid, nloc - 1));
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-      fl[k] = a.flags[g[k]];
+      fl[k] = at32(a.flags, g[k]);
 #pragma unroll
-      for (int f = 0; f < 4; ++f) v[k][f] = a.st[f][g[k]];
+      for (int f = 0; f < 4; ++f) v[k][f] = at32(a.st[f], g[k]);
     }
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
@@ -124,14 +127,14 @@ __global__ void __launch_bounds__(256) tile_kernel_jt_batch(const TileArgs<doubl
     //    private nodes written now. Per round every load is issued before the
     //    first store (a store to dst between loads of src would order them).
     for (int l0 = 0; l0 < nloc; l0 += KB * bs) {
-      int64_t g[KB];
+      uint32_t g[KB];
       T v[KB][3];
 #pragma unroll
       for (int k = 0; k < KB; ++k) g[k] = node_id(min(l0 + k * bs + tid, nloc - 1));
 #pragma unroll
       for (int k = 0; k < KB; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) v[k][c] = src[c * n + g[k]];
+        for (int c = 0; c < 3; ++c) v[k][c] = at32(src + c * n, g[k]);
 #pragma unroll
       for (int k = 0; k < KB; ++k) {
         const int l = l0 + k * bs + tid;
@@ -142,7 +145,7 @@ __global__ void __launch_bounds__(256) tile_kernel_jt_batch(const TileArgs<doubl
             if (l < no) {
               const bool cons =
                   (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
-              if (cons) dst[c * n + g[k]] = v[k][c];
+              if (cons) at32(dst + c * n, g[k]) = v[k][c];
             }
             const bool fixed = (c < 2) ? (f & NODE_DIRICHLET) : (f & NODE_ACTIVE);
             opd[c * ML + l] = fixed ? T(0) : v[k][c];
@@ -223,16 +226,16 @@ __global__ void __launch_bounds__(256) tile_kernel_jt_batch(const TileArgs<doubl
     //    staging), shared rows into this right-hand side's slots
     for (int l = tid; l < no; l += bs) {
       const uint8_t f = lflag[l];
-      const int64_t g = int64_t(o0) + l;
+      const uint32_t g = uint32_t(o0 + l);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
-        if (!cons) dst[c * n + g] = opd[c * ML + l];
+        if (!cons) at32(dst + c * n, g) = opd[c * ML + l];
       }
     }
     for (int r = tid; r < ns; r += bs) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) part[c * a.n_slots + slot0 + r] = opd[c * ML + no + r];
+      for (int c = 0; c < 3; ++c) at32(part + c * a.n_slots, uint32_t(slot0 + r)) = opd[c * ML + no + r];
     }
     __syncthreads();   // the next operand overwrites the accumulators
   }
