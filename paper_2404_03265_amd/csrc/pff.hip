@@ -327,16 +327,26 @@ struct pff_ctx {
     // hanging nodes are handled on the tile's nodes; only the inverse
     // diagonal runs the per-cell constraint form
     constexpr bool HANG = (MODE == MODE_DIAG_LEAF || MODE == MODE_DIAG_LEVEL);
-    const void* kfn = p == 1 ? reinterpret_cast<const void*>(&tile_kernel<1, T, MODE, EPI, HANG>)
-                             : reinterpret_cast<const void*>(&tile_kernel<2, T, MODE, EPI, HANG>);
+    // the default tiles' block size (Q1 256, Q2 64 threads) is compiled in
+    const bool fixed = threads == (p == 1 ? 256 : 64);
+    const void* kfn =
+        p == 1 ? (fixed ? reinterpret_cast<const void*>(&tile_kernel<1, T, MODE, EPI, HANG, true>)
+                        : reinterpret_cast<const void*>(&tile_kernel<1, T, MODE, EPI, HANG, false>))
+               : (fixed ? reinterpret_cast<const void*>(&tile_kernel<2, T, MODE, EPI, HANG, true>)
+                        : reinterpret_cast<const void*>(&tile_kernel<2, T, MODE, EPI, HANG, false>));
     if (lds > size_t(64 * 1024))
       HIPCHK(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     a.tile_base = 0;
+    a.n_grid = int(t.n_tiles);
     if (t.n_tiles > 0) {
-      if (p == 1)
-        hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI, HANG>), dim3(t.n_tiles), dim3(threads), lds, s, a);
+      if (p == 1 && fixed)
+        hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI, HANG, true>), dim3(t.n_tiles), dim3(threads), lds, s, a);
+      else if (p == 1)
+        hipLaunchKernelGGL((tile_kernel<1, T, MODE, EPI, HANG, false>), dim3(t.n_tiles), dim3(threads), lds, s, a);
+      else if (fixed)
+        hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI, HANG, true>), dim3(t.n_tiles), dim3(threads), lds, s, a);
       else
-        hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI, HANG>), dim3(t.n_tiles), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL((tile_kernel<2, T, MODE, EPI, HANG, false>), dim3(t.n_tiles), dim3(threads), lds, s, a);
     }
     if (MODE != MODE_LEVEL_COEF && t.n_shared > 0)
       hipLaunchKernelGGL((shared_fixup<T, MODE, EPI>), dim3(grid_for(t.n_shared)), dim3(256), 0, s, a);

@@ -49,7 +49,9 @@ enum Epi : int { EPI_PLAIN = 0, EPI_RESID = 1, EPI_CHEB = 2, EPI_CHEB_FIRST = 3,
 
 template <typename T>
 struct TileArgs {
-  int tile_base;               // this launch handles tiles tile_base + [0, gridDim.x)
+  int tile_base;               // this launch handles tiles tile_base + [0, n_grid)
+  int n_grid;                  // = gridDim.x, beside tile_base and tile_info so that one scalar
+                               // load brings all three
   const int32_t* tile_info;
   const int32_t* shared;       // global ids of the tiles' shared local nodes
   const uint16_t* cell_loc;       // own nodes per cell (hanging nodes included)
@@ -598,7 +600,10 @@ __device__ __forceinline__ void compute_cell(const TileArgs<T>& a, T H, bool han
   }
 }
 
-template <int P, typename T, int MODE, int EPI, bool HANG>
+// FIXED: the launch uses the default tile's block (64 threads for Q2, 256
+// for Q1), known at compile time: reading blockDim.x would cost every
+// workgroup a vector load of the dispatch packet ahead of its node loads.
+template <int P, typename T, int MODE, int EPI, bool HANG, bool FIXED>
 __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   constexpr int N1 = P + 1, NL = N1 * N1, NQ = NL;
   using TR = ModeTraits<MODE>;
@@ -619,18 +624,22 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   // XCD-aware order: workgroups go to the 8 XCDs round-robin, so XCD x
   // receives a contiguous chunk of the tile list and neighbouring tiles (which
   // share nodes) run on the same XCD and hit the same L2.
-  const int nb = int(gridDim.x), bid = int(blockIdx.x);
+  const int nb = a.n_grid, bid = int(blockIdx.x);
   const int xq = nb >> 3, xr = nb & 7, xcd = bid & 7;
   const int order_idx = xcd * xq + (xcd < xr ? xcd : xr) + (bid >> 3);
   const int tile = a.tile_base + order_idx;
   // the whole tile header goes into scalar registers in one batch of loads;
   // reading it field by field under the branches below would serialise a
-  // scalar-load round trip per run
+  // scalar-load round trip per run. The empty asm statements take every
+  // word, so that the compiler cannot sink a word's load into the branch
+  // that first uses it.
   int ti[TILE_STRIDE];
   {
     const int32_t* tp = a.tile_info + TILE_STRIDE * tile;
 #pragma unroll
     for (int k = 0; k < TILE_STRIDE; ++k) ti[k] = tp[k];
+#pragma unroll
+    for (int k = 0; k < TILE_STRIDE; ++k) asm volatile("" ::"s"(ti[k]));
   }
   const int o0 = ti[TILE_OWNED0], no = ti[TILE_NOWNED];
   const int s0 = ti[TILE_SHARED0], ns = ti[TILE_NSHARED];
@@ -696,7 +705,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   // (Q1: 16 x 16 cells on four waves, Q2: 8 x 8 cells on one wave) so that
   // one round covers a tile without many idle lanes
   constexpr int SP = P == 1 ? 1 : 4, SS = P == 1 ? 1 : 2;
-  const int bs = int(blockDim.x), tid = int(threadIdx.x);
+  const int bs = FIXED ? (P == 1 ? 256 : 64) : int(blockDim.x), tid = int(threadIdx.x);
   // When one round covers the private range, each thread keeps what the
   // epilogue of its private rows needs in registers: the raw source values
   // (Jacobian identity rows, smoother iterate) and, for the level smoother
@@ -834,7 +843,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   if constexpr (NODE_HANG && NF > 0) {
     if (nhang > 0) {
       // values at hanging nodes from their masters (masters are never hanging)
-      for (int r = threadIdx.x; r < nhang; r += blockDim.x) {
+      for (int r = threadIdx.x; r < nhang; r += bs) {
         const uint16_t* hr = a.hang_rec + 4 * int64_t(hr0 + r);
         const double* hw = a.hang_w + 3 * int64_t(hr0 + r);
         const int h = hr[0], m0 = hr[1], m1 = hr[2], m2 = hr[3];
@@ -906,7 +915,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
     }
     // every gather is done: the accumulators take over the field arrays
     __syncthreads();
-    for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
+    for (int l = threadIdx.x; l < nloc; l += bs) {
 #pragma unroll
       for (int c = C0; c < 3; ++c) acc[c * ML + l] = LT(0);
     }
@@ -917,7 +926,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
     // summation order is fixed. A one-wave tile over the cells' own nodes
     // needs no colour phases: two distinct cells never have the same node at
     // the same local position.
-    const bool one_phase = !HANG && blockDim.x <= 64;
+    const bool one_phase = !HANG && bs <= 64;
     const int nphase = one_phase ? 1 : ncol;
     for (int col = 0; col < nphase; ++col) {
       if (live && (one_phase || color == col)) {
@@ -936,7 +945,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
     // contributions at hanging nodes go to their masters; records of one
     // colour share no master
     for (int col = 0; col < nhcol; ++col) {
-      for (int r = threadIdx.x; r < nhang; r += blockDim.x) {
+      for (int r = threadIdx.x; r < nhang; r += bs) {
         if (a.hang_col[hr0 + r] != col) continue;
         const uint16_t* hr = a.hang_rec + 4 * int64_t(hr0 + r);
         const double* hw = a.hang_w + 3 * int64_t(hr0 + r);
@@ -958,7 +967,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   if (keep_raw) {
 #pragma unroll
     for (int k = 0; k < NPRE; ++k) {
-      const int l = k * int(blockDim.x) + int(threadIdx.x);
+      const int l = k * bs + int(threadIdx.x);
       if (l < no) {
         const uint8_t f = lflag[l];
         const uint32_t g = uint32_t(o0 + l);
@@ -986,13 +995,13 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       }
     }
   } else {
-    for (int l = threadIdx.x; l < no; l += blockDim.x) {
+    for (int l = threadIdx.x; l < no; l += bs) {
       const uint8_t f = lflag[l];
 #pragma unroll
       for (int c = C0; c < 3; ++c) node_epilogue<MODE, EPI, true, T>(a, c, int64_t(o0) + l, f, T(acc[c * ML + l]));
     }
   }
-  for (int r = threadIdx.x; r < ns; r += blockDim.x) {
+  for (int r = threadIdx.x; r < ns; r += bs) {
 #pragma unroll
     for (int c = C0; c < 3; ++c) at32(a.part + c * a.n_slots, uint32_t(slot0 + r)) = T(acc[c * ML + no + r]);
   }
@@ -1003,8 +1012,9 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
 template <typename T, int MODE, int EPI>
 __global__ void __launch_bounds__(256) shared_fixup(const TileArgs<T> a) {
   constexpr int C0 = (MODE == MODE_LEVEL && EPI == EPI_PHI) ? 2 : 0;
-  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < a.n_shared;
-       s += int64_t(gridDim.x) * blockDim.x) {
+  // launched with 256-thread blocks (a compile-time block size spares each
+  // workgroup a load of the dispatch packet)
+  for (int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x; s < a.n_shared; s += int64_t(gridDim.x) * 256) {
     const int64_t g = a.n_private + s;
     const uint8_t f = a.flags[g];
     T v[3] = {T(0), T(0), T(0)};
