@@ -1012,33 +1012,108 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
 template <typename T, int MODE, int EPI>
 __global__ void __launch_bounds__(256) shared_fixup(const TileArgs<T> a) {
   constexpr int C0 = (MODE == MODE_LEVEL && EPI == EPI_PHI) ? 2 : 0;
+  constexpr bool JM = MODE == MODE_J || MODE == MODE_JT;
+  constexpr bool LRES = MODE == MODE_LEVEL && EPI == EPI_RESID;
+  constexpr bool LCHEB = MODE == MODE_LEVEL && (EPI == EPI_CHEB || EPI == EPI_CHEB_FIRST);
+  const int64_t n = a.n;
   // launched with 256-thread blocks (a compile-time block size spares each
   // workgroup a load of the dispatch packet)
   for (int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x; s < a.n_shared; s += int64_t(gridDim.x) * 256) {
-    const int64_t g = a.n_private + s;
-    const uint8_t f = a.flags[g];
+    const uint32_t g = uint32_t(a.n_private + s);
+    // Every load that does not depend on another goes out first: the node
+    // flag, the slot list and what the epilogue reads besides the sum; then
+    // the partial sums of all slots (an unused slot reads slot 0 and is
+    // dropped) and, on constrained rows of the Jacobian modes, the operand.
+    // Two memory round trips per node, where a branch per slot and loads
+    // inside the epilogue had made nine.
+    // (the slot table has SHARED_SLOTS or more entries per node, so this
+    // 16-byte read stays inside it whatever its width)
+    const int4 sl = reinterpret_cast<const int4*>(a.sh_tab)[s];
+    const uint8_t f = at32(a.flags, g);
+    T eb[3], ed[3], ex[3], ep[3], es[3];
+#pragma unroll
+    for (int c = C0; c < 3; ++c) {
+      if constexpr (LRES || LCHEB) eb[c] = at32(a.b + c * n, g);
+      if constexpr (LCHEB) ed[c] = at32(a.dinv + c * n, g);
+      if constexpr (MODE == MODE_LEVEL && EPI == EPI_CHEB) {
+        ex[c] = at32(a.src + c * n, g);
+        ep[c] = a.dold ? at32(a.dold + c * n, g) : T(0);
+      }
+    }
+    if constexpr (JM) {
+      // the operand on constrained rows (identity rows). Branch-free: the
+      // other lanes read element 0 (one cached line), since a load under a
+      // branch would make the compiler wait for every load before it
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
+        es[c] = at32(a.src + c * n, cons ? g : 0u);
+      }
+    }
+    // partial sums of the four slots, loaded without a branch (a load under
+    // a branch is sunk there and waited for apart); with a wider slot table
+    // (sh_w > SHARED_SLOTS, rare) they read in-range slots of other nodes and
+    // the loop below sums the node's own
+    const bool four = a.sh_w == SHARED_SLOTS;
+    const int slot[SHARED_SLOTS] = {sl.x, sl.y, sl.z, sl.w};
+    T pv[SHARED_SLOTS][3];
+#pragma unroll
+    for (int j = 0; j < SHARED_SLOTS; ++j)
+#pragma unroll
+      for (int c = C0; c < 3; ++c) pv[j][c] = at32(a.part + c * a.n_slots, uint32_t(max(slot[j], 0)));
+    // ascending tile order, the used slots only (computed on every path, so
+    // that the loads above stay ahead of the branch)
     T v[3] = {T(0), T(0), T(0)};
-    if (a.sh_w == SHARED_SLOTS) {
-      // the slot list in one 16-byte load: the partial sums are then one
-      // batch of independent loads
-      const int4 sl = reinterpret_cast<const int4*>(a.sh_tab)[s];
-      const int slot[SHARED_SLOTS] = {sl.x, sl.y, sl.z, sl.w};
 #pragma unroll
-      for (int j = 0; j < SHARED_SLOTS; ++j)
-        if (slot[j] >= 0) {
+    for (int j = 0; j < SHARED_SLOTS; ++j)
 #pragma unroll
-          for (int c = C0; c < 3; ++c) v[c] += a.part[c * a.n_slots + slot[j]];
-        }
-    } else {
+      for (int c = C0; c < 3; ++c) v[c] = slot[j] >= 0 ? v[c] + pv[j][c] : v[c];
+    if (!four) {
+#pragma unroll
+      for (int c = C0; c < 3; ++c) v[c] = T(0);
       for (int j = 0; j < a.sh_w; ++j) {
-        const int slot = a.sh_tab[s * a.sh_w + j];
-        if (slot < 0) break;
+        const int sj = a.sh_tab[s * a.sh_w + j];
+        if (sj < 0) break;
 #pragma unroll
-        for (int c = C0; c < 3; ++c) v[c] += a.part[c * a.n_slots + slot];
+        for (int c = C0; c < 3; ++c) v[c] += at32(a.part + c * a.n_slots, uint32_t(sj));
       }
     }
 #pragma unroll
-    for (int c = C0; c < 3; ++c) node_epilogue<MODE, EPI, false, T>(a, c, g, f, v[c]);
+    for (int c = C0; c < 3; ++c) {
+      T& d = at32(a.dst + c * n, g);
+      if constexpr (JM) {
+        const bool cons = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
+        d = cons ? es[c] : v[c];
+      } else if constexpr (LCHEB) {
+        // the level smoother step (as node_epilogue)
+        const bool fixed =
+            (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_EDGE | NODE_HANGING));
+        const int blk = c < 2 ? 0 : 1;
+        T x, dp;
+        if constexpr (EPI == EPI_CHEB_FIRST) {
+          x = a.c0[blk] * ed[c] * eb[c];
+          dp = x;
+        } else {
+          x = ex[c];
+          dp = ep[c];
+        }
+        T& xn = at32(a.xnew + c * n, g);
+        if (fixed) {
+          d = T(0);
+          xn = x;
+        } else {
+          const T r = eb[c] - v[c];
+          const T dn = a.c1[blk] * dp + a.c2[blk] * ed[c] * r;
+          d = dn;
+          xn = x + dn;
+        }
+      } else if constexpr (LRES) {
+        const bool held = (c < 2) ? (f & (NODE_DIRICHLET | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_HANGING));
+        d = held ? T(0) : eb[c] - v[c];
+      } else {
+        node_epilogue<MODE, EPI, false, T>(a, c, int64_t(g), f, v[c]);
+      }
+    }
   }
 }
 
