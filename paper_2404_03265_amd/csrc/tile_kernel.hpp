@@ -718,21 +718,26 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
   constexpr int NPRE = (JMODE || LPRE) ? SP : 1;
   const bool keep_raw = (JMODE || LPRE) && no <= SP * bs;
   T raw[NPRE][3], pb[LPRE ? SP : 1][3], pdi[CHEB ? SP : 1][3], pdo[CHEB ? SP : 1][3];
-  if constexpr (LPRE) {
+  // Requested after the first round's node loads and cell records: issued
+  // before them, they would be waited for first (the shared ids of a tile
+  // without runs come from a load whose register the other path writes,
+  // and the compiler waits for every load in flight there).
+  auto load_epilogue_inputs = [&]() {
+    if constexpr (LPRE) {
 #pragma unroll
-    for (int k = 0; k < SP; ++k) {
-      const uint32_t g = uint32_t(min(o0 + min(k * bs + tid, max(no - 1, 0)), int(n - 1)));
+      for (int k = 0; k < SP; ++k) {
+        const uint32_t g = uint32_t(min(o0 + min(k * bs + tid, max(no - 1, 0)), int(n - 1)));
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        pb[k][c] = at32(a.b + c * n, g);
-        if constexpr (CHEB) {
-          pdi[k][c] = at32(a.dinv + c * n, g);
-          if constexpr (FIRST) pdo[k][c] = a.c0[c < 2 ? 0 : 1] * pdi[k][c] * pb[k][c];
-          else pdo[k][c] = a.dold ? at32(a.dold + c * n, g) : T(0);
+        for (int c = 0; c < 3; ++c) {
+          pb[k][c] = at32(a.b + c * n, g);
+          if constexpr (CHEB) {
+            pdi[k][c] = at32(a.dinv + c * n, g);
+            if constexpr (!FIRST) pdo[k][c] = a.dold ? at32(a.dold + c * n, g) : T(0);
+          }
         }
       }
     }
-  }
+  };
   bool first = true;
   for (int rp = 0, rs = 0; rp < no || rs < ns; rp += SP * bs, rs += SS * bs) {
     // shared ids before any load is in flight: with the list, the wait for
@@ -793,7 +798,10 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
         for (int st = 0; st < TR::n_state; ++st) vsh[k][TR::n_src + st] = at32(a.st[st], g);
       }
     }
-    if (first) load_cell_record();
+    if (first) {
+      load_cell_record();
+      load_epilogue_inputs();
+    }
     first = false;
     auto put = [&](int l, uint8_t f, const T* v) {
       lflag[l] = f;
@@ -838,7 +846,10 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
       if (r < ns) put(no + r, fsh[k], vsh[k]);
     }
   }
-  if (first) load_cell_record();
+  if (first) {
+    load_cell_record();
+    load_epilogue_inputs();
+  }
   __syncthreads();
   if constexpr (NODE_HANG && NF > 0) {
     if (nhang > 0) {
@@ -983,7 +994,9 @@ __global__ void __launch_bounds__(256) tile_kernel(const TileArgs<T> a) {
             const bool fixed = (c < 2) ? (f & (NODE_DIRICHLET | NODE_EDGE | NODE_HANGING)) : (f & (NODE_ACTIVE | NODE_EDGE | NODE_HANGING));
             const int blk = c < 2 ? 0 : 1;
             const T x = raw[k][c];
-            const T dn = a.c1[blk] * pdo[k][c] + a.c2[blk] * pdi[k][c] * (pb[k][c] - v);
+            // (EPI_CHEB_FIRST: the previous update is d_0 = c0 D^-1 b)
+            const T dold = FIRST ? a.c0[blk] * pdi[k][c] * pb[k][c] : pdo[k][c];
+            const T dn = a.c1[blk] * dold + a.c2[blk] * pdi[k][c] * (pb[k][c] - v);
             di = fixed ? T(0) : dn;
             at32(a.xnew + c * n, g) = fixed ? x : x + dn;
           } else if constexpr (LPRE) {
