@@ -851,11 +851,12 @@ struct pff_ctx {
     ca.nlev = L + 1;
     for (int l = 0; l <= L; ++l) {
       ca.start[l + 1] = ca.start[l] + lv[l].n;
+      ca.bstart[l + 1] = ca.bstart[l] + int((lv[l].n + 255) / 256);
       ca.vec[l] = work<T>(lv[l]).d;
       ca.fl[l] = lv[l].flags;
       ca.leaf_index[l] = lv[l].leaf_index;
     }
-    hipLaunchKernelGGL((k_copy_to_levels<T>), dim3(grid_for(ca.start[L + 1])), dim3(256), 0, s, ca, src, flags, n);
+    hipLaunchKernelGGL((k_copy_to_levels<T>), dim3(ca.bstart[L + 1]), dim3(256), 0, s, ca, src, flags, n);
     for (int l = L; l >= 1; --l) {
       DevLevel& D = lv[l];
       LevelWork<T>& w = work<T>(D);
@@ -883,7 +884,7 @@ struct pff_ctx {
       xi[l] = chebyshev<T>(l, w.d, xi[l], k);
     }
     for (int l = 0; l <= L; ++l) ca.vec[l] = work<T>(lv[l]).x[xi[l]];
-    hipLaunchKernelGGL((k_copy_from_levels<T>), dim3(grid_for(ca.start[L + 1])), dim3(256), 0, s, dst, ca, src, flags,
+    hipLaunchKernelGGL((k_copy_from_levels<T>), dim3(ca.bstart[L + 1]), dim3(256), 0, s, dst, ca, src, flags,
                        n);
     if (n_hang)
       hipLaunchKernelGGL(k_copy_hanging, dim3(grid_for(3 * n_hang)), dim3(256), 0, s, dst, src, n, hang, n_hang);

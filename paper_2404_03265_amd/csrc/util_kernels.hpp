@@ -210,53 +210,88 @@ template <typename T>
 struct LevelCopyArgs {
   int nlev;
   int64_t start[COPY_MAX_LEVELS + 1];
+  // first 256-thread block of each level: a block holds nodes of one level,
+  // so the level and its pointers are uniform (scalar) in the kernels
+  int bstart[COPY_MAX_LEVELS + 1];
   T* vec[COPY_MAX_LEVELS];                  // level vector (3 x n_l) written or read
   const uint8_t* fl[COPY_MAX_LEVELS];       // level node flags
   const int32_t* leaf_index[COPY_MAX_LEVELS];
 };
 
+// the block's level and its node k (launched with 256-thread blocks, one
+// grid of bstart[nlev] blocks); false past the level's last node
 template <typename T>
-__device__ __forceinline__ int copy_level_of(const LevelCopyArgs<T>& a, int64_t t) {
-  int l = 0;
-  while (l + 1 < a.nlev && t >= a.start[l + 1]) ++l;
-  return l;
+__device__ __forceinline__ bool copy_node_of(const LevelCopyArgs<T>& a, int& l, int64_t& k, int64_t& nl) {
+  const int bid = int(blockIdx.x);
+  l = 0;
+#pragma unroll
+  for (int j = 1; j < COPY_MAX_LEVELS; ++j)
+    if (j < a.nlev && bid >= a.bstart[j]) l = j;
+  nl = a.start[l + 1] - a.start[l];
+  k = int64_t(bid - a.bstart[l]) * 256 + threadIdx.x;
+  return k < nl;
 }
 
 // level vectors = the leaf values of their copy targets (zero elsewhere and on
-// constrained leaf rows)
+// constrained leaf rows). The node's flag and leaf index go out together, then
+// the leaf flag and values (branch-free: other nodes read leaf node 0).
 template <typename T>
-__global__ void k_copy_to_levels(const LevelCopyArgs<T> a, const double* b, const uint8_t* leaf_flags, int64_t n) {
-  GRID_LOOP(t, a.start[a.nlev]) {
-    const int l = copy_level_of(a, t);
-    const int64_t k = t - a.start[l], nl = a.start[l + 1] - a.start[l];
-    T v[3] = {T(0), T(0), T(0)};
-    if (a.fl[l][k] & NODE_COPY) {
-      const int64_t g = a.leaf_index[l][k];
-      const uint8_t lf = leaf_flags[g];
+__global__ void __launch_bounds__(256) k_copy_to_levels(const LevelCopyArgs<T> a, const double* b,
+                                                        const uint8_t* leaf_flags, int64_t n) {
+  int l;
+  int64_t k, nl;
+  if (!copy_node_of(a, l, k, nl)) return;
+  const uint8_t* flp = a.fl[l];
+  const int32_t* lip = a.leaf_index[l];
+  T* vp = a.vec[l];
+  // the level's three pointers in one scalar round trip
+  asm volatile("" ::"s"(flp), "s"(lip), "s"(vp));
+  const uint8_t fl = flp[k];
+  const int32_t gi = lip[k];
+  const bool copy = fl & NODE_COPY;
+  const int64_t g = copy ? int64_t(gi) : 0;
+  const uint8_t lf = leaf_flags[g];
+  double bv[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        if (!leaf_constrained(lf, c)) v[c] = T(b[c * n + g]);
-    }
+  for (int c = 0; c < 3; ++c) bv[c] = b[c * n + g];
+  // the four loads together (the compiler would otherwise branch on the
+  // flag first and load the values behind it)
+  asm volatile("" ::"v"(int(lf)), "v"(bv[0]), "v"(bv[1]), "v"(bv[2]));
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.vec[l][c * nl + k] = v[c];
-  }
+  for (int c = 0; c < 3; ++c) vp[c * nl + k] = (copy && !leaf_constrained(lf, c)) ? T(bv[c]) : T(0);
 }
 
 // leaf rows = the value of their copy level (the input on constrained rows);
 // every leaf node is the copy target of one level at most
 template <typename T>
-__global__ void k_copy_from_levels(double* out, const LevelCopyArgs<T> a, const double* b, const uint8_t* leaf_flags,
-                                   int64_t n) {
-  GRID_LOOP(t, a.start[a.nlev]) {
-    const int l = copy_level_of(a, t);
-    const int64_t k = t - a.start[l], nl = a.start[l + 1] - a.start[l];
-    if (a.fl[l][k] & NODE_COPY) {
-      const int64_t g = a.leaf_index[l][k];
-      const uint8_t lf = leaf_flags[g];
+__global__ void __launch_bounds__(256) k_copy_from_levels(double* out, const LevelCopyArgs<T> a, const double* b,
+                                                          const uint8_t* leaf_flags, int64_t n) {
+  int l;
+  int64_t k, nl;
+  if (!copy_node_of(a, l, k, nl)) return;
+  const uint8_t* flp = a.fl[l];
+  const int32_t* lip = a.leaf_index[l];
+  const T* vp = a.vec[l];
+  // the level's three pointers in one scalar round trip
+  asm volatile("" ::"s"(flp), "s"(lip), "s"(vp));
+  const uint8_t fl = flp[k];
+  const int32_t gi = lip[k];
+  T xv[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        out[c * n + g] = leaf_constrained(lf, c) ? b[c * n + g] : double(a.vec[l][c * nl + k]);
-    }
+  for (int c = 0; c < 3; ++c) xv[c] = vp[c * nl + k];
+  // the flag, leaf index and level values together (the compiler would
+  // otherwise branch on the flag first and load the rest behind it)
+  asm volatile("" ::"v"(int(fl)), "v"(gi), "v"(xv[0]), "v"(xv[1]), "v"(xv[2]));
+  const bool copy = fl & NODE_COPY;
+  const int64_t g = copy ? int64_t(gi) : 0;
+  const uint8_t lf = leaf_flags[g];
+  double bv[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) bv[c] = b[c * n + g];
+  asm volatile("" ::"v"(int(lf)), "v"(bv[0]), "v"(bv[1]), "v"(bv[2]));
+  if (copy) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c * n + g] = leaf_constrained(lf, c) ? bv[c] : double(xv[c]);
   }
 }
 
