@@ -726,8 +726,10 @@ __device__ __forceinline__ void eig_reduce2(const double* part, int nb, double* 
 // the other block.
 template <class F>
 __device__ __forceinline__ void eig_block_loops(int64_t nl, int64_t begin, F&& body) {
-  const int64_t st = int64_t(gridDim.x) * blockDim.x;
-  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  // (launched with RED_THREADS-thread blocks: a compile-time block size
+  // spares each workgroup a load of the dispatch packet)
+  const int64_t st = int64_t(gridDim.x) * RED_THREADS;
+  const int64_t t0 = int64_t(blockIdx.x) * RED_THREADS + threadIdx.x;
   if (begin == 0)
     for (int64_t i = t0; i < 2 * nl; i += st) body(0, i);
   for (int64_t i = 2 * nl + t0; i < 3 * nl; i += st) body(1, i);
@@ -763,10 +765,11 @@ __global__ void __launch_bounds__(RED_THREADS) k_eig_update_partial(double* r, d
   const double alpha[2] = {sc[EIG_ALPHA], sc[EIG_SC + EIG_ALPHA]};
   double s[2] = {0.0, 0.0};
   eig_block_loops(nl, begin, [&](int b, int64_t i) {
+    // all four loads at once (under the branches they waited in turn)
     double ri = r[i], zi = z[i];
+    const double di = dinv[i], qi = q[i];
     if (act[b]) {
-      const double di = dinv[i];
-      if (di != 0.0) ri -= alpha[b] * q[i];
+      ri = di != 0.0 ? ri - alpha[b] * qi : ri;
       zi = di * ri;
       r[i] = ri;
       z[i] = zi;
@@ -793,11 +796,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_eig_beta_reduce(const double* p
   if (rz2[b] <= 1e-24 * c[EIG_RZ0] || double(it + 1) >= c[EIG_MAX]) c[EIG_ACTIVE] = 0.0;
 }
 // p = z + beta p on active blocks
-__global__ void k_eig_waxpy(double* p, const double* z, const double* sc, int64_t nl, int64_t begin) {
+// (launched with 256-thread blocks)
+__global__ void __launch_bounds__(256) k_eig_waxpy(double* p, const double* z, const double* sc, int64_t nl,
+                                                   int64_t begin) {
   const bool act[2] = {sc[EIG_ACTIVE] != 0.0, sc[EIG_SC + EIG_ACTIVE] != 0.0};
   const double beta[2] = {sc[EIG_BETA], sc[EIG_SC + EIG_BETA]};
-  for (int64_t i = begin + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < 3 * nl;
-       i += int64_t(gridDim.x) * blockDim.x) {
+  for (int64_t i = begin + int64_t(blockIdx.x) * 256 + threadIdx.x; i < 3 * nl; i += int64_t(gridDim.x) * 256) {
     const int b = i < 2 * nl ? 0 : 1;
     if (act[b]) p[i] = z[i] + beta[b] * p[i];
   }
