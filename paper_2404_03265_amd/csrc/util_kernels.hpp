@@ -361,38 +361,116 @@ __device__ __forceinline__ void ell_row3(const uint32_t* E, int64_t stride, int6
   }
 }
 
+// the weights and gathers of one ELL row whose WIDTH entries t are in registers
+template <typename T, int WIDTH>
+__device__ __forceinline__ void ell_gather3(const uint32_t (&t)[WIDTH], const float* W, const T* x, int64_t nx,
+                                            T& s0, T& s1, T& s2) {
+#pragma unroll
+  for (int e = 0; e < WIDTH; ++e) {
+    const int64_t col = t[e] & TRANSFER_COL_MASK;
+    const T w = T(W[t[e] >> TRANSFER_COL_BITS]);
+    s0 += w * x[col];
+    s1 += w * x[nx + col];
+    s2 += w * x[2 * nx + col];
+  }
+}
+
+// With a compile-time row width each thread requests its (first) row's
+// entries before the block loads the weight table and passes its barrier,
+// so the two latencies overlap, and the next row's entries (when the grid
+// does not cover the rows) before the current row's gathers are summed.
+// Launched with 256-thread blocks.
+
 // x_f += P x_c on unknowns the fine level does not hold at zero
 // (Dirichlet for u, active for phi)
 template <typename T, int WIDTH>
-__global__ void k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, int width, const uint32_t* E,
-                              const float* wtab, const uint8_t* ff) {
+__global__ void __launch_bounds__(256) k_prolong_add(T* xf, const T* xc, int64_t nf, int64_t nc, int width,
+                                                     const uint32_t* E, const float* wtab, const uint8_t* ff) {
   __shared__ float W[TRANSFER_WEIGHTS];
-  load_weight_table(W, wtab);
-  GRID_LOOP(i, nf) {
-    T s0 = T(0), s1 = T(0), s2 = T(0);
-    ell_row3<T, WIDTH>(E, nf, i, width, W, xc, nc, s0, s1, s2);
-    const uint8_t f = ff[i];
-    if (!(f & NODE_DIRICHLET)) {
-      xf[i] += s0;
-      xf[nf + i] += s1;
+  if constexpr (WIDTH > 0) {
+    const int64_t st = int64_t(gridDim.x) * 256;
+    int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    // a row's entries, flag and the values it adds to, requested together
+    uint32_t t[WIDTH];
+    uint8_t f = 0;
+    T x0 = T(0), x1 = T(0), x2 = T(0);
+    auto fetch = [&](int64_t row) {
+#pragma unroll
+      for (int e = 0; e < WIDTH; ++e) t[e] = E[int64_t(e) * nf + row];
+      f = ff[row];
+      x0 = xf[row];
+      x1 = xf[nf + row];
+      x2 = xf[2 * nf + row];
+    };
+    if (i < nf) fetch(i);
+    load_weight_table(W, wtab);
+    for (; i < nf; i += st) {
+      T s0 = T(0), s1 = T(0), s2 = T(0);
+      ell_gather3<T, WIDTH>(t, W, xc, nc, s0, s1, s2);
+      const uint8_t fi = f;
+      const T y0 = x0 + s0, y1 = x1 + s1, y2 = x2 + s2;
+      if (i + st < nf) fetch(i + st);
+      if (!(fi & NODE_DIRICHLET)) {
+        xf[i] = y0;
+        xf[nf + i] = y1;
+      }
+      if (!(fi & NODE_ACTIVE)) xf[2 * nf + i] = y2;
     }
-    if (!(f & NODE_ACTIVE)) xf[2 * nf + i] += s2;
+  } else {
+    load_weight_table(W, wtab);
+    GRID_LOOP(i, nf) {
+      T s0 = T(0), s1 = T(0), s2 = T(0);
+      ell_row3<T, WIDTH>(E, nf, i, width, W, xc, nc, s0, s1, s2);
+      const uint8_t f = ff[i];
+      if (!(f & NODE_DIRICHLET)) {
+        xf[i] += s0;
+        xf[nf + i] += s1;
+      }
+      if (!(f & NODE_ACTIVE)) xf[2 * nf + i] += s2;
+    }
   }
 }
 
 // d_c += P^T t_f over the coarse rows that receive fine contributions
 template <typename T, int WIDTH>
-__global__ void k_restrict_add(T* dc, const T* tf, int64_t nc, int64_t nf, int64_t nrows, const int32_t* rows,
-                               int width, const uint32_t* E, const float* wtab) {
+__global__ void __launch_bounds__(256) k_restrict_add(T* dc, const T* tf, int64_t nc, int64_t nf, int64_t nrows,
+                                                      const int32_t* rows, int width, const uint32_t* E,
+                                                      const float* wtab) {
   __shared__ float W[TRANSFER_WEIGHTS];
-  load_weight_table(W, wtab);
-  GRID_LOOP(r, nrows) {
-    T s0 = T(0), s1 = T(0), s2 = T(0);
-    ell_row3<T, WIDTH>(E, nrows, r, width, W, tf, nf, s0, s1, s2);
-    const int64_t i = rows[r];
-    dc[i] += s0;
-    dc[nc + i] += s1;
-    dc[2 * nc + i] += s2;
+  if constexpr (WIDTH > 0) {
+    const int64_t st = int64_t(gridDim.x) * 256;
+    int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    // a row's entries and its receiving node, requested together
+    uint32_t t[WIDTH];
+    int64_t i = 0;
+    auto fetch = [&](int64_t row) {
+#pragma unroll
+      for (int e = 0; e < WIDTH; ++e) t[e] = E[int64_t(e) * nrows + row];
+      i = rows[row];
+    };
+    if (r < nrows) fetch(r);
+    load_weight_table(W, wtab);
+    for (; r < nrows; r += st) {
+      // the values added to go out with the gathers
+      const int64_t ir = i;
+      const T d0 = dc[ir], d1 = dc[nc + ir], d2 = dc[2 * nc + ir];
+      T s0 = T(0), s1 = T(0), s2 = T(0);
+      ell_gather3<T, WIDTH>(t, W, tf, nf, s0, s1, s2);
+      if (r + st < nrows) fetch(r + st);
+      dc[ir] = d0 + s0;
+      dc[nc + ir] = d1 + s1;
+      dc[2 * nc + ir] = d2 + s2;
+    }
+  } else {
+    load_weight_table(W, wtab);
+    GRID_LOOP(r, nrows) {
+      T s0 = T(0), s1 = T(0), s2 = T(0);
+      ell_row3<T, WIDTH>(E, nrows, r, width, W, tf, nf, s0, s1, s2);
+      const int64_t i = rows[r];
+      dc[i] += s0;
+      dc[nc + i] += s1;
+      dc[2 * nc + i] += s2;
+    }
   }
 }
 
