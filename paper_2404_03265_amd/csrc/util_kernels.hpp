@@ -330,38 +330,22 @@ __device__ __forceinline__ void load_weight_table(float* W, const float* wtab) {
   __syncthreads();
 }
 
-// s_c += sum over the entries e of ELL row r of weight_e * x[c * nx + col_e]
-// (c = 0, 1, 2). WIDTH > 0: the row width is known at compile time and every
-// entry of the row is requested before the first gather (padding entries
-// have weight 0 and column 0); WIDTH == 0: runtime width.
-template <typename T, int WIDTH>
+// s_c += sum over the entries e of ELL row r (column-major, runtime width)
+// of weight_e * x[c * nx + col_e] (c = 0, 1, 2)
+template <typename T>
 __device__ __forceinline__ void ell_row3(const uint32_t* E, int64_t stride, int64_t r, int width, const float* W,
                                          const T* x, int64_t nx, T& s0, T& s1, T& s2) {
-  if constexpr (WIDTH > 0) {
-    uint32_t t[WIDTH];
-#pragma unroll
-    for (int e = 0; e < WIDTH; ++e) t[e] = E[int64_t(e) * stride + r];
-#pragma unroll
-    for (int e = 0; e < WIDTH; ++e) {
-      const int64_t col = t[e] & TRANSFER_COL_MASK;
-      const T w = T(W[t[e] >> TRANSFER_COL_BITS]);
-      s0 += w * x[col];
-      s1 += w * x[nx + col];
-      s2 += w * x[2 * nx + col];
-    }
-  } else {
-    for (int e = 0; e < width; ++e) {
-      const uint32_t t = E[int64_t(e) * stride + r];
-      const int64_t col = t & TRANSFER_COL_MASK;
-      const T w = T(W[t >> TRANSFER_COL_BITS]);
-      s0 += w * x[col];
-      s1 += w * x[nx + col];
-      s2 += w * x[2 * nx + col];
-    }
+  for (int e = 0; e < width; ++e) {
+    const uint32_t t = E[int64_t(e) * stride + r];
+    const int64_t col = t & TRANSFER_COL_MASK;
+    const T w = T(W[t >> TRANSFER_COL_BITS]);
+    s0 += w * x[col];
+    s1 += w * x[nx + col];
+    s2 += w * x[2 * nx + col];
   }
 }
 
-// the weights and gathers of one ELL row whose WIDTH entries t are in registers
+// the weights and gathers of WIDTH entries t of one ELL row held in registers
 template <typename T, int WIDTH>
 __device__ __forceinline__ void ell_gather3(const uint32_t (&t)[WIDTH], const float* W, const T* x, int64_t nx,
                                             T& s0, T& s1, T& s2) {
@@ -379,7 +363,9 @@ __device__ __forceinline__ void ell_gather3(const uint32_t (&t)[WIDTH], const fl
 // entries before the block loads the weight table and passes its barrier,
 // so the two latencies overlap, and the next row's entries (when the grid
 // does not cover the rows) before the current row's gathers are summed.
-// Launched with 256-thread blocks.
+// Launched with 256-thread blocks. (The grouped form of the restriction
+// below was slower here: one lane per fine row already gathers neighbouring
+// coarse nodes, two fine rows sharing each.)
 
 // x_f += P x_c on unknowns the fine level does not hold at zero
 // (Dirichlet for u, active for phi)
@@ -420,7 +406,7 @@ __global__ void __launch_bounds__(256) k_prolong_add(T* xf, const T* xc, int64_t
     load_weight_table(W, wtab);
     GRID_LOOP(i, nf) {
       T s0 = T(0), s1 = T(0), s2 = T(0);
-      ell_row3<T, WIDTH>(E, nf, i, width, W, xc, nc, s0, s1, s2);
+      ell_row3<T>(E, nf, i, width, W, xc, nc, s0, s1, s2);
       const uint8_t f = ff[i];
       if (!(f & NODE_DIRICHLET)) {
         xf[i] += s0;
@@ -431,45 +417,83 @@ __global__ void __launch_bounds__(256) k_prolong_add(T* xf, const T* xc, int64_t
   }
 }
 
-// d_c += P^T t_f over the coarse rows that receive fine contributions
-template <typename T, int WIDTH>
+// Grouped restriction, for the P^T rows of width G^2 (9 for Q1, 25 for Q2):
+// the entries of one row are spread over G lanes, lane g of the row's group
+// taking the entries j G + g (j < G), stored at E[(j * rows + row) * G + g].
+// The row's entries are sorted by fine node and a coarse node's support
+// holds G neighbouring fine nodes per grid line, so one load instruction
+// gathers, for 64 / G consecutive rows, runs of neighbouring fine nodes
+// instead of one fine node per row and lane spread over many cache lines.
+// The group's first lane adds the G partial sums in lane order and updates
+// the row. Each lane requests its first row's entries (with the row's
+// receiving node) before the block loads the weight table and passes its
+// barrier, and the next row's before the current row's sums (when the grid
+// does not cover the rows).
+// Launched with 256-thread blocks, 64 / G rows per wave; the lanes past the
+// last group, and those past the last row, read row 0 and store nothing.
+
+// sum over the lanes of a group (lane order), valid in the group's first lane
+template <typename T, int G>
+__device__ __forceinline__ T group_sum(T s, int lane) {
+  T a = s;
+#pragma unroll
+  for (int k = 1; k < G; ++k) a += __shfl(s, lane + k < 64 ? lane + k : lane, 64);
+  return a;
+}
+
+// d_c += P^T t_f over the coarse rows that receive fine contributions, any
+// row width (runtime)
+template <typename T>
 __global__ void __launch_bounds__(256) k_restrict_add(T* dc, const T* tf, int64_t nc, int64_t nf, int64_t nrows,
                                                       const int32_t* rows, int width, const uint32_t* E,
                                                       const float* wtab) {
   __shared__ float W[TRANSFER_WEIGHTS];
-  if constexpr (WIDTH > 0) {
-    const int64_t st = int64_t(gridDim.x) * 256;
-    int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    // a row's entries and its receiving node, requested together
-    uint32_t t[WIDTH];
-    int64_t i = 0;
-    auto fetch = [&](int64_t row) {
+  load_weight_table(W, wtab);
+  GRID_LOOP(r, nrows) {
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    ell_row3<T>(E, nrows, r, width, W, tf, nf, s0, s1, s2);
+    const int64_t i = rows[r];
+    dc[i] += s0;
+    dc[nc + i] += s1;
+    dc[2 * nc + i] += s2;
+  }
+}
+
+// d_c += P^T t_f over the coarse rows that receive fine contributions
+template <typename T, int G>
+__global__ void __launch_bounds__(256) k_restrict_add_grouped(T* dc, const T* tf, int64_t nc, int64_t nf,
+                                                              int64_t nrows, const int32_t* rows, const uint32_t* E,
+                                                              const float* wtab) {
+  constexpr int RPW = 64 / G;   // rows per wave
+  __shared__ float W[TRANSFER_WEIGHTS];
+  const int lane = int(threadIdx.x) & 63, g = lane % G, rl = lane / G;
+  const int64_t wst = int64_t(gridDim.x) * 4;
+  int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  uint32_t t[G];
+  int64_t i = 0;
+  // a row's entries of this lane and its receiving node, requested together
+  auto fetch = [&](int64_t wv) {
+    const int64_t r = wv * RPW + rl;
+    const int64_t row = (rl < RPW && r < nrows) ? r : int64_t(0);
 #pragma unroll
-      for (int e = 0; e < WIDTH; ++e) t[e] = E[int64_t(e) * nrows + row];
-      i = rows[row];
-    };
-    if (r < nrows) fetch(r);
-    load_weight_table(W, wtab);
-    for (; r < nrows; r += st) {
-      // the values added to go out with the gathers
-      const int64_t ir = i;
-      const T d0 = dc[ir], d1 = dc[nc + ir], d2 = dc[2 * nc + ir];
-      T s0 = T(0), s1 = T(0), s2 = T(0);
-      ell_gather3<T, WIDTH>(t, W, tf, nf, s0, s1, s2);
-      if (r + st < nrows) fetch(r + st);
-      dc[ir] = d0 + s0;
-      dc[nc + ir] = d1 + s1;
-      dc[2 * nc + ir] = d2 + s2;
-    }
-  } else {
-    load_weight_table(W, wtab);
-    GRID_LOOP(r, nrows) {
-      T s0 = T(0), s1 = T(0), s2 = T(0);
-      ell_row3<T, WIDTH>(E, nrows, r, width, W, tf, nf, s0, s1, s2);
-      const int64_t i = rows[r];
-      dc[i] += s0;
-      dc[nc + i] += s1;
-      dc[2 * nc + i] += s2;
+    for (int j = 0; j < G; ++j) t[j] = E[(int64_t(j) * nrows + row) * G + g];
+    i = rows[row];
+  };
+  if (w * RPW < nrows) fetch(w);
+  load_weight_table(W, wtab);
+  for (; w * RPW < nrows; w += wst) {   // uniform per wave
+    const int64_t r = w * RPW + rl;
+    const bool store = rl < RPW && r < nrows && g == 0;
+    const int64_t ir = i;
+    const T d0 = dc[ir], d1 = dc[nc + ir], d2 = dc[2 * nc + ir];
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    ell_gather3<T, G>(t, W, tf, nf, s0, s1, s2);
+    if ((w + wst) * RPW < nrows) fetch(w + wst);
+    const T a0 = group_sum<T, G>(s0, lane), a1 = group_sum<T, G>(s1, lane), a2 = group_sum<T, G>(s2, lane);
+    if (store) {
+      dc[ir] = d0 + a0;
+      dc[nc + ir] = d1 + a1;
+      dc[2 * nc + ir] = d2 + a2;
     }
   }
 }
