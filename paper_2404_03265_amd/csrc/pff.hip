@@ -82,6 +82,7 @@ struct DevLevel {
   int32_t* PT_rows = nullptr;
   int64_t PT_nrows = 0;
   int PT_width = 0;
+  int PT_group = 1;   // lanes per P^T row (ell_from_csr)
   LevelWork<double> w64;
   LevelWork<float> w32;
   double lam_max[2] = {1, 1}, lam_min[2] = {1, 1};
@@ -148,16 +149,21 @@ DevTiles upload_tiles(const TileSet& t) {
 // Column-major ELL copies of P (all fine rows) and P^T (the coarse rows with
 // entries) with packed (column, weight index) entries; the weights must be
 // exact in float (dyadic values) and shared through one table per level.
-// grouped (P^T): rows of width G^2 (G = restrict_group(width) > 1) stored
-// for k_restrict_add_grouped, entry j G + g of row k at (j nr + k) G + g.
-int restrict_group(int width) { return width == 25 ? 5 : width == 9 ? 3 : width == 4 ? 2 : 1; }
-
+// grouped (P^T): width G^2 (25, 9 or 4) with the rows on average at least
+// half full gives group = G, the rows stored for k_restrict_add_grouped
+// (entry j G + g of row k at (j nr + k) G + g); else group = 1.
 void ell_from_csr(const Csr& A, const std::vector<int64_t>& rows, std::vector<double>& wtab,
-                  std::vector<uint32_t>& E, int& width, bool grouped) {
+                  std::vector<uint32_t>& E, int& width, bool grouped, int& group) {
   width = 0;
-  for (int64_t r : rows) width = std::max<int>(width, int(A.ptr[r + 1] - A.ptr[r]));
+  int64_t nnz = 0;
+  for (int64_t r : rows) {
+    width = std::max<int>(width, int(A.ptr[r + 1] - A.ptr[r]));
+    nnz += A.ptr[r + 1] - A.ptr[r];
+  }
   const int64_t nr = int64_t(rows.size());
-  const size_t G = size_t(grouped ? restrict_group(width) : 1);
+  const int g2 = width == 25 ? 5 : width == 9 ? 3 : width == 4 ? 2 : 1;
+  group = (grouped && g2 > 1 && 2 * nnz >= int64_t(width) * nr) ? g2 : 1;
+  const size_t G = size_t(group);
   E.assign(size_t(std::max(width, 1)) * size_t(std::max<int64_t>(nr, 1)), 0u);
   for (int64_t k = 0; k < nr; ++k) {
     const int64_t r = rows[k];
@@ -179,12 +185,13 @@ void upload_transfers(const Csr& P, const Csr& PT, DevLevel& D) {
   std::vector<double> wtab(1, 0.0);   // index 0: padding
   std::vector<int64_t> rows(size_t(P.rows));
   std::iota(rows.begin(), rows.end(), 0);
-  ell_from_csr(P, rows, wtab, E, D.P_width, false);
+  int group = 1;
+  ell_from_csr(P, rows, wtab, E, D.P_width, false, group);
   D.P_ell = upload(E);
   rows.clear();
   for (int64_t r = 0; r < PT.rows; ++r)
     if (PT.ptr[r + 1] > PT.ptr[r]) rows.push_back(r);
-  ell_from_csr(PT, rows, wtab, E, D.PT_width, true);
+  ell_from_csr(PT, rows, wtab, E, D.PT_width, true, D.PT_group);
   D.PT_ell = upload(E);
   std::vector<int32_t> r32(rows.begin(), rows.end());
   D.PT_rows = upload(r32);
@@ -818,9 +825,10 @@ struct pff_ctx {
 
   // transfers of level D (to and from level D - 1): prolongation with the
   // row width as a compile-time constant for the widths of Q1 and Q2 (4 and
-  // 9); restriction rows of width G^2 (restrict_group; 9 and 25 with Q1 and
-  // Q2) by the grouped kernel, 64 / G rows per wave and four waves a block,
-  // the layout of ell_from_csr; other widths by the runtime-width kernels
+  // 9); restriction with PT_group = G > 1 (widths 9 and 25 with Q1 and Q2,
+  // rows at least half full) by the grouped kernel, 64 / G rows per wave and
+  // four waves a block, the layout of ell_from_csr; otherwise one lane per
+  // row, the widths 9 and 25 as compile-time constants
   static dim3 grouped_grid(int64_t rows, int G) { return dim3(grid_for((rows + 64 / G - 1) / (64 / G) * 64)); }
   template <typename T>
   void prolong_add(T* xf, const T* xc, int64_t nc, const DevLevel& D) {
@@ -836,7 +844,7 @@ struct pff_ctx {
   void restrict_add(T* dc, const T* tf, int64_t nc, const DevLevel& D) {
     const dim3 b(256);
     const int64_t nr = D.PT_nrows;
-    switch (restrict_group(D.PT_width)) {
+    switch (D.PT_group) {
       case 2:
         hipLaunchKernelGGL((k_restrict_add_grouped<T, 2>), grouped_grid(nr, 2), b, 0, s, dc, tf, nc, D.n, nr,
                            D.PT_rows, D.PT_ell, D.P_wtab);
@@ -849,9 +857,22 @@ struct pff_ctx {
         hipLaunchKernelGGL((k_restrict_add_grouped<T, 5>), grouped_grid(nr, 5), b, 0, s, dc, tf, nc, D.n, nr,
                            D.PT_rows, D.PT_ell, D.P_wtab);
         break;
-      default:
-        hipLaunchKernelGGL((k_restrict_add<T>), dim3(grid_for(nr)), b, 0, s, dc, tf, nc, D.n, nr, D.PT_rows,
-                           D.PT_width, D.PT_ell, D.P_wtab);
+      default: {
+        const dim3 g(grid_for(nr));
+        switch (D.PT_width) {
+          case 9:
+            hipLaunchKernelGGL((k_restrict_add<T, 9>), g, b, 0, s, dc, tf, nc, D.n, nr, D.PT_rows, 9, D.PT_ell,
+                               D.P_wtab);
+            break;
+          case 25:
+            hipLaunchKernelGGL((k_restrict_add<T, 25>), g, b, 0, s, dc, tf, nc, D.n, nr, D.PT_rows, 25, D.PT_ell,
+                               D.P_wtab);
+            break;
+          default:
+            hipLaunchKernelGGL((k_restrict_add<T, 0>), g, b, 0, s, dc, tf, nc, D.n, nr, D.PT_rows, D.PT_width,
+                               D.PT_ell, D.P_wtab);
+        }
+      }
     }
   }
 

@@ -417,7 +417,9 @@ __global__ void __launch_bounds__(256) k_prolong_add(T* xf, const T* xc, int64_t
   }
 }
 
-// Grouped restriction, for the P^T rows of width G^2 (9 for Q1, 25 for Q2):
+// Grouped restriction, for P^T of width G^2 (9 for Q1, 25 for Q2) whose rows
+// are on average at least half full (local smoothing; not the identity rows
+// of global coarsening away from the refined cells):
 // the entries of one row are spread over G lanes, lane g of the row's group
 // taking the entries j G + g (j < G), stored at E[(j * rows + row) * G + g].
 // The row's entries are sorted by fine node and a coarse node's support
@@ -441,21 +443,47 @@ __device__ __forceinline__ T group_sum(T s, int lane) {
   return a;
 }
 
-// d_c += P^T t_f over the coarse rows that receive fine contributions, any
-// row width (runtime)
-template <typename T>
+// d_c += P^T t_f over the coarse rows that receive fine contributions, one
+// lane per row (WIDTH > 0: compile-time row width, as the prolongation)
+template <typename T, int WIDTH>
 __global__ void __launch_bounds__(256) k_restrict_add(T* dc, const T* tf, int64_t nc, int64_t nf, int64_t nrows,
                                                       const int32_t* rows, int width, const uint32_t* E,
                                                       const float* wtab) {
   __shared__ float W[TRANSFER_WEIGHTS];
-  load_weight_table(W, wtab);
-  GRID_LOOP(r, nrows) {
-    T s0 = T(0), s1 = T(0), s2 = T(0);
-    ell_row3<T>(E, nrows, r, width, W, tf, nf, s0, s1, s2);
-    const int64_t i = rows[r];
-    dc[i] += s0;
-    dc[nc + i] += s1;
-    dc[2 * nc + i] += s2;
+  if constexpr (WIDTH > 0) {
+    const int64_t st = int64_t(gridDim.x) * 256;
+    int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    // a row's entries and its receiving node, requested together
+    uint32_t t[WIDTH];
+    int64_t i = 0;
+    auto fetch = [&](int64_t row) {
+#pragma unroll
+      for (int e = 0; e < WIDTH; ++e) t[e] = E[int64_t(e) * nrows + row];
+      i = rows[row];
+    };
+    if (r < nrows) fetch(r);
+    load_weight_table(W, wtab);
+    for (; r < nrows; r += st) {
+      // the values added to go out with the gathers
+      const int64_t ir = i;
+      const T d0 = dc[ir], d1 = dc[nc + ir], d2 = dc[2 * nc + ir];
+      T s0 = T(0), s1 = T(0), s2 = T(0);
+      ell_gather3<T, WIDTH>(t, W, tf, nf, s0, s1, s2);
+      if (r + st < nrows) fetch(r + st);
+      dc[ir] = d0 + s0;
+      dc[nc + ir] = d1 + s1;
+      dc[2 * nc + ir] = d2 + s2;
+    }
+  } else {
+    load_weight_table(W, wtab);
+    GRID_LOOP(r, nrows) {
+      T s0 = T(0), s1 = T(0), s2 = T(0);
+      ell_row3<T>(E, nrows, r, width, W, tf, nf, s0, s1, s2);
+      const int64_t i = rows[r];
+      dc[i] += s0;
+      dc[nc + i] += s1;
+      dc[2 * nc + i] += s2;
+    }
   }
 }
 
